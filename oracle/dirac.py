@@ -1,0 +1,231 @@
+"""Fine-grid twisted-mass Wilson-clover operator, written out from its definition.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Paper: Sec. 1 defines D(+-mu) = D_W +- i Gamma5 mu and the bound
+D(mu)^dag D(mu) = D_W^dag D_W + mu^2; Sec. 2 fixes gamma5 = diag(-1,-1,1,1)
+and the lexicographic site order TZYX, and leaves the other gamma matrices
+free.  D_W itself is only named ("Wilson clover operator"); the form used here
+is the textbook Wilson + Sheikholeslami-Wohlert operator in mass
+normalisation:
+
+  (D_W psi)(x) = (m0+4) psi(x)
+                 - 1/2 sum_mu [ (1-gamma_mu) U_mu(x) psi(x+mu)
+                              + (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+                 + (i c_sw / 4) sum_{mu,nu} sigma_{mu nu} F_{mu nu}(x) psi(x)
+
+  sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu],  F_{mu nu} = (Q_{mu nu} - Q_{nu mu}) / 8,
+  Q_{mu nu}(x) = sum of the four plaquette leaves at x in the (mu,nu) plane,
+  m0 = 1/(2 kappa) - 4.
+
+Gamma basis (Euclidean, chiral): gamma_k = [[0, -i s_k], [i s_k, 0]] for the
+X, Y, Z directions (s_k Pauli), gamma_T = [[0, -1], [-1, 0]]; their product
+gamma_X gamma_Y gamma_Z gamma_T is the paper's gamma5.
+
+Pins (tests/test_oracle_dirac.py): free-field plane waves (closed form),
+pure-gauge fields, constant diagonal links (per-colour momentum shift), a
+constant abelian field strength (closed form of the clover term), Gamma5
+hermiticity, the squared-operator identity, gauge covariance, dense
+brute-force spectrum bound sigma_min >= mu.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# direction index: 0:T 1:Z 2:Y 3:X (lattice axis order T, Z, Y, X)
+NDIM = 4
+
+_s1 = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_s2 = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+_s3 = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+_Z2 = np.zeros((2, 2), dtype=np.complex128)
+_I2 = np.eye(2, dtype=np.complex128)
+
+
+def _gamma_spatial(s):
+    return np.block([[_Z2, -1j * s], [1j * s, _Z2]])
+
+
+GAMMA_X = _gamma_spatial(_s1)
+GAMMA_Y = _gamma_spatial(_s2)
+GAMMA_Z = _gamma_spatial(_s3)
+GAMMA_T = np.block([[_Z2, -_I2], [-_I2, _Z2]])
+# gamma matrix belonging to each link direction mu = 0:T 1:Z 2:Y 3:X
+GAMMA = np.stack([GAMMA_T, GAMMA_Z, GAMMA_Y, GAMMA_X])
+GAMMA5 = np.diag([-1.0, -1.0, 1.0, 1.0]).astype(np.complex128)
+
+
+def sigma_munu(mu: int, nu: int) -> np.ndarray:
+    """sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu] (4x4)."""
+    g1, g2 = GAMMA[mu], GAMMA[nu]
+    return 0.5j * (g1 @ g2 - g2 @ g1)
+
+
+def m0_from_kappa(kappa: float) -> float:
+    return 1.0 / (2.0 * kappa) - 4.0
+
+
+def _dag(M):
+    return np.conj(np.swapaxes(M, -1, -2))
+
+
+def _shift(f, mu: int, sign: int):
+    """f(x + sign*mu) on the periodic lattice (lattice axes are the first four)."""
+    return np.roll(f, -sign, axis=mu)
+
+
+def spin_mul(G, psi):
+    """Apply a 4x4 spin matrix to psi[..., 4, 3]."""
+    return np.einsum("st,...tc->...sc", G, psi)
+
+
+def colour_mul(U, psi):
+    """Apply per-site colour matrices U[...,3,3] to psi[...,4,3]."""
+    return np.einsum("...ab,...sb->...sa", U, psi)
+
+
+# ----------------------------------------------------------------------------
+# clover term
+# ----------------------------------------------------------------------------
+
+def clover_leaves(U, mu: int, nu: int):
+    """Q_{mu nu}(x): the four plaquettes in the (mu,nu) plane that touch x,
+    all taken with the same orientation (mu first, then nu)."""
+    Um = U[..., mu, :, :]
+    Un = U[..., nu, :, :]
+    sh = _shift
+    # leaf 1: x -> x+mu -> x+mu+nu -> x+nu -> x
+    q = Um @ sh(Un, mu, +1) @ _dag(sh(Um, nu, +1)) @ _dag(Un)
+    # leaf 2: x -> x+nu -> x-mu+nu -> x-mu -> x
+    q = q + Un @ _dag(sh(sh(Um, mu, -1), nu, +1)) @ _dag(sh(Un, mu, -1)) @ sh(Um, mu, -1)
+    # leaf 3: x -> x-mu -> x-mu-nu -> x-nu -> x
+    q = q + _dag(sh(Um, mu, -1)) @ _dag(sh(sh(Un, mu, -1), nu, -1)) @ sh(sh(Um, mu, -1), nu, -1) @ sh(Un, nu, -1)
+    # leaf 4: x -> x-nu -> x+mu-nu -> x+mu -> x
+    q = q + _dag(sh(Un, nu, -1)) @ sh(Um, nu, -1) @ sh(sh(Un, mu, +1), nu, -1) @ _dag(Um)
+    return q
+
+
+def field_strength(U, mu: int, nu: int):
+    """F_{mu nu} = (Q_{mu nu} - Q_{nu mu}) / 8 (anti-Hermitian 3x3 per site)."""
+    return (clover_leaves(U, mu, nu) - clover_leaves(U, nu, mu)) / 8.0
+
+
+def clover_matrix(U, csw: float):
+    """Clover term A(x) = (i c_sw/4) sum_{mu,nu} sigma_{mu nu} (x) F_{mu nu}(x)
+    as a 12x12 matrix per site, index = 3*spin + colour.  Shape [T,Z,Y,X,12,12]."""
+    dims = U.shape[:4]
+    A = np.zeros(dims + (4, 3, 4, 3), dtype=np.complex128)
+    for mu in range(4):
+        for nu in range(4):
+            if mu == nu:
+                continue
+            F = field_strength(U, mu, nu)
+            A += np.einsum("st,...ab->...satb", sigma_munu(mu, nu), F)
+    A *= 1j * csw / 4.0
+    return A.reshape(dims + (12, 12))
+
+
+def clover_blocks(A12):
+    """The two 6x6 chirality blocks of a chirality-block-diagonal 12x12 matrix.
+    Block 0 = spins 0,1 (gamma5 = -1), block 1 = spins 2,3 (gamma5 = +1);
+    6-index = 3*(spin mod 2) + colour.  Shape [..., 2, 6, 6]."""
+    return np.stack([A12[..., 0:6, 0:6], A12[..., 6:12, 6:12]], axis=-3)
+
+
+def clover_from_blocks(Ab):
+    """Inverse of clover_blocks: [...,2,6,6] -> [...,12,12]."""
+    out = np.zeros(Ab.shape[:-3] + (12, 12), dtype=np.complex128)
+    out[..., 0:6, 0:6] = Ab[..., 0, :, :]
+    out[..., 6:12, 6:12] = Ab[..., 1, :, :]
+    return out
+
+
+# ----------------------------------------------------------------------------
+# operator
+# ----------------------------------------------------------------------------
+
+class WilsonClover:
+    """D(mu) = D_W + i mu Gamma5 on a periodic lattice.
+
+    U      links [T,Z,Y,X,4,3,3]
+    kappa  hopping parameter (m0 = 1/(2 kappa) - 4)
+    csw    clover coefficient (ignored if `clover` is given)
+    mu     twisted mass (mass normalisation)
+    clover optional clover term [T,Z,Y,X,2,6,6] (A only, without m0+4)
+    """
+
+    def __init__(self, U, kappa: float, csw: float, mu: float, clover=None):
+        self.U = np.asarray(U, dtype=np.complex128)
+        self.dims = self.U.shape[:4]
+        self.m0 = m0_from_kappa(kappa)
+        self.mu = float(mu)
+        if clover is None:
+            self.A = clover_matrix(self.U, csw)
+        else:
+            self.A = clover_from_blocks(np.asarray(clover, dtype=np.complex128))
+
+    # --- pieces -------------------------------------------------------------
+    def hop(self, psi):
+        """-1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^dag psi(x-mu)]."""
+        out = np.zeros_like(psi)
+        for mu in range(4):
+            fwd = colour_mul(self.U[..., mu, :, :], _shift(psi, mu, +1))
+            Ub = _shift(self.U[..., mu, :, :], mu, -1)
+            bwd = colour_mul(_dag(Ub), _shift(psi, mu, -1))
+            out -= 0.5 * (fwd - spin_mul(GAMMA[mu], fwd) + bwd + spin_mul(GAMMA[mu], bwd))
+        return out
+
+    def site(self, psi, mu=None):
+        """T(x) psi(x) = (m0+4) psi + A psi + i mu gamma5 psi."""
+        mu = self.mu if mu is None else mu
+        flat = psi.reshape(psi.shape[:-2] + (12,))
+        a = np.einsum("...ij,...j->...i", self.A, flat).reshape(psi.shape)
+        return (self.m0 + 4.0) * psi + a + 1j * mu * spin_mul(GAMMA5, psi)
+
+    def site_matrix(self, mu=None):
+        """T(x) as a 12x12 matrix per site."""
+        mu = self.mu if mu is None else mu
+        g5 = np.kron(GAMMA5, np.eye(3))
+        return self.A + (self.m0 + 4.0) * np.eye(12) + 1j * mu * g5
+
+    def site_inv(self, psi, mu=None):
+        """T(x)^{-1} psi(x) by a direct solve per site."""
+        T = self.site_matrix(mu)
+        flat = psi.reshape(psi.shape[:-2] + (12,))
+        return np.linalg.solve(T, flat[..., None])[..., 0].reshape(psi.shape)
+
+    # --- full operators -------------------------------------------------------
+    def apply(self, psi, mu=None):
+        """D(mu) psi.  Pass mu=-self.mu for D(-mu), mu=0 for D_W."""
+        return self.site(psi, mu) + self.hop(psi)
+
+    def apply_w(self, psi):
+        return self.apply(psi, 0.0)
+
+    def dense(self, mu=None):
+        """Dense matrix of D(mu) (tiny lattices only); column index = site*12+comp."""
+        V = int(np.prod(self.dims))
+        n = V * 12
+        M = np.zeros((n, n), dtype=np.complex128)
+        e = np.zeros(self.dims + (4, 3), dtype=np.complex128)
+        ef = e.reshape(-1)
+        for k in range(n):
+            ef[:] = 0
+            ef[k] = 1
+            M[:, k] = self.apply(e, mu).reshape(-1)
+        return M
+
+
+def gamma5_field(psi):
+    """Gamma5 psi (spin index second-to-last)."""
+    return spin_mul(GAMMA5, psi)
+
+
+def plane_wave_symbol(p, m0: float, mu: float):
+    """Closed form of D(mu) on psi(x) = exp(i p.x) u in the free field (U = 1):
+    m0 + sum_mu (1 - cos p_mu) + i sum_mu gamma_mu sin p_mu + i mu gamma5.
+    p is indexed by direction (T,Z,Y,X)."""
+    M = (m0 + sum(1.0 - np.cos(pm) for pm in p)) * np.eye(4, dtype=np.complex128)
+    for d in range(4):
+        M = M + 1j * np.sin(p[d]) * GAMMA[d]
+    return M + 1j * mu * GAMMA5
