@@ -1,0 +1,194 @@
+/*
+ * ddamg.h -- C interface of the MI355X (gfx950) DD-alpha-AMG library for
+ * twisted-mass Wilson-clover fermions.
+ *
+ * The method follows Bacchio, Alexandrou, Finkenrath, Frommer, Kahl,
+ * Rottmann, "DDalphaAMG for Twisted Mass Fermions" (PoS LATTICE2016):
+ *   - Sec. 1: flexible GMRES preconditioned at every step by the multigrid
+ *     cycle of Eq. (1), SAP smoother, Gamma5-compatible aggregation P,
+ *     coarse operator D_c = P^dag D_W P, twisted-mass operator
+ *     D(+-mu) = D_W +- i Gamma5 mu with D_c(mu) = D_c + i mu Gamma5,c and the
+ *     raised coarsest twist mu_coarse = delta * mu;
+ *   - Sec. 2: gamma5 = diag(-1,-1,1,1), lexicographic site order TZYX,
+ *     three levels with 4^4 and 2^4 aggregates, a minimal init interface plus
+ *     defaulted parameters;
+ *   - Sec. 3: Listing 1 parameter names (MGBlock*, MGSetupIter,
+ *     MGCoarseSetupIter, MGNumberOfVectors, MGNumberOfLevels,
+ *     MGCoarseMuFactor); odd-even preconditioning only in the smoother and on
+ *     the coarsest level; one setup serves D(+mu) and D(-mu).
+ *
+ * Conventions of every host array (complex numbers are interleaved double
+ * pairs, i.e. C99 double complex / numpy complex128):
+ *   lattice extents dims = {T, Z, Y, X}; site index ((t*Z + z)*Y + y)*X + x;
+ *   links   [V][4][3][3]  direction 0:T 1:Z 2:Y 3:X, row-major 3x3 SU(3);
+ *   spinor  [V][4][3]     spin, colour;
+ *   clover  [V][2][6][6]  the two chirality blocks of the clover term A(x)
+ *                         (block 0: spins 0,1; 6-index = 3*(spin%2)+colour),
+ *                         without the mass term m0 + 4;
+ *   coarse vectors on level l >= 1: [Vl][n] with n = 2*nvec[l-1], sites in
+ *     lexicographic order of the level-l lattice (dims / product of blocks),
+ *     components [0, n/2) with Gamma5,c = -1, [n/2, n) with Gamma5,c = +1.
+ * The gamma basis is the chiral one: g_k = [[0,-i s_k],[i s_k,0]] for k = X,Y,Z,
+ * g_T = [[0,-1],[-1,0]]; D_W is the textbook Wilson + Sheikholeslami-Wohlert
+ * operator in mass normalisation, m0 = 1/(2 kappa) - 4.
+ *
+ * Ownership: the caller owns every buffer it passes; the library copies what
+ * it needs into its own device memory and never keeps a caller pointer after
+ * a call returns.  `on_device` = 1 means the pointer is device memory of the
+ * current HIP device (e.g. a torch tensor's data_ptr()), used on the
+ * context's stream; 0 means host memory.
+ *
+ * Errors: every int-returning function returns a status (DDAMG_OK = 0).
+ * Nothing is thrown across the interface and nothing exits the process;
+ * ddamg_last_error() gives the message of the last failing call.
+ * One context must not be used by two threads at once.
+ */
+#ifndef DDAMG_H
+#define DDAMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDAMG_OK 0
+#define DDAMG_NOT_CONVERGED 1
+#define DDAMG_INVALID_ARG (-1)
+#define DDAMG_BAD_STATE (-2)
+#define DDAMG_HIP_ERROR (-3)
+#define DDAMG_OUT_OF_MEMORY (-4)
+#define DDAMG_NUMERICAL (-5)
+
+/* preconditioner precision (the outer FGMRES is always FP64) */
+#define DDAMG_FP64 0
+#define DDAMG_FP32 1
+#define DDAMG_FP16 2 /* fine links and coarse operators stored in FP16, FP32 arithmetic */
+#define DDAMG_BF16 3 /* same with BF16 storage */
+
+typedef struct ddamg_ctx ddamg_ctx;
+
+/* Solver parameters.  Names follow Listing 1 (Sec. 3) where the paper gives
+ * one; everything else is a reading of the paper's silence, with the default
+ * set by ddamg_default_params(). */
+typedef struct ddamg_params {
+  int levels;                  /* MGNumberOfLevels: 2 or 3 */
+  int block[3][4];             /* MGBlockT/Z/Y/X per level transition; block[0] must equal the
+                                  block given to ddamg_create (fine SAP block = first aggregate) */
+  int nvec[3];                 /* MGNumberOfVectors per level transition */
+  int coarse_sap_block[4];     /* SAP blocks on intermediate coarse levels (coarse sites) */
+  int sap_pre, sap_post;       /* j, k of Eq. (1) on the fine level (default 0, 3) */
+  int mr_steps;                /* MR steps per fine SAP block solve (default 4) */
+  int coarse_sap_post;         /* SAP iterations on intermediate levels (default 2) */
+  int coarse_mr_steps;         /* MR steps per coarse SAP block solve (default 3) */
+  int init_sap_iters;          /* smoothing of the random test vectors (default 3) */
+  int setup_iters;             /* MGSetupIter (default 3) */
+  int coarse_setup_iters;      /* MGCoarseSetupIter (default 3) */
+  double coarse_mu_factor;     /* MGCoarseMuFactor, delta (default 1) */
+  int restart, max_iter;       /* outer FGMRES(m) (default 10, 1000) */
+  int inter_restart, inter_max_iter; /* intermediate-level FGMRES (default 10, 10) */
+  double inter_tol;            /* (default 0.1) */
+  int coarse_restart, coarse_max_iter; /* coarsest odd-even GMRES (default 30, 300) */
+  double coarse_tol;           /* (default 0.1) */
+  int precision;               /* DDAMG_FP64 / FP32 / FP16 / BF16 */
+  int fixed_iters;             /* 1: inner solves run exactly their max iteration counts */
+} ddamg_params;
+
+typedef struct ddamg_stats {
+  int iters;             /* outer FGMRES iterations */
+  int converged;         /* 1 if the true relative residual <= tol */
+  double resid;          /* true relative residual |b - D x| / |b| in FP64 */
+  long coarse_iters[4];  /* Krylov iterations per level (index = level) */
+  long vcycles;          /* fine-level V-cycles */
+  double seconds;        /* wall time of the call */
+} ddamg_stats;
+
+/* Fill p with the defaults documented above (2 levels, 4^4 then 2^4 blocks,
+ * nvec 24 then 32). */
+void ddamg_default_params(ddamg_params* p);
+
+/* Create a context.  dims {T,Z,Y,X}: even extents; block {bT,bZ,bY,bX}: even
+ * block extents dividing dims with an even number of blocks per direction
+ * (SAP domains, red/black coloured; Sec. 1 SAP).  mu: twisted mass in mass
+ * normalisation (Sec. 1, D(mu) = D_W + i Gamma5 mu).  stream: hipStream_t on
+ * which every kernel runs (NULL: the null stream).  Returns INVALID_ARG on bad
+ * shapes, HIP_ERROR if no device is usable. */
+int ddamg_create(const int dims[4], const int block[4], double kappa, double csw, double mu, void* stream,
+                 ddamg_ctx** out);
+void ddamg_destroy(ddamg_ctx* ctx);
+const char* ddamg_last_error(const ddamg_ctx* ctx);
+
+/* Gauge field U_mu(x) (links layout above).  Builds the clover term from the
+ * links with the csw of ddamg_create (Sec. 1: Wilson clover operator).
+ * Returns NUMERICAL if a link is not finite. */
+int ddamg_set_gauge(ddamg_ctx* ctx, const void* links, int on_device);
+/* Replace the clover term by a caller-supplied one (clover layout above);
+ * clover = NULL rebuilds it from the links.  Invalidates any setup. */
+int ddamg_set_clover(ddamg_ctx* ctx, const void* clover, int on_device);
+/* Copy the clover term the library uses into clover (host, layout above). */
+int ddamg_get_clover(ddamg_ctx* ctx, void* clover);
+/* Change mu for every later solve, keeping the setup (Sec. 1: the same setup
+ * serves D(+mu) and D(-mu)); coarse twists are rescaled (delta on the
+ * coarsest level). */
+int ddamg_set_mu(ddamg_ctx* ctx, double mu);
+
+/* Adaptive setup (Sec. 1; setup_iters / coarse_setup_iters of Listing 1).
+ * init_vectors[l] (l < levels-1) holds the random starting test vectors of
+ * the interpolation from level l to l+1: nvec[l] fields, fine level in the
+ * spinor layout, coarse levels in the coarse-vector layout.  The library
+ * draws no random numbers itself.  Returns INVALID_ARG for shapes that do
+ * not aggregate, NUMERICAL for a rank-deficient aggregate. */
+int ddamg_setup(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_vectors, int on_device);
+/* Build the hierarchy directly from given test vectors (no smoothing, no
+ * setup iteration): P from their block orthonormalisation, D_c by Galerkin
+ * assembly.  Same shapes as ddamg_setup. */
+int ddamg_set_test_vectors(ddamg_ctx* ctx, const ddamg_params* p, const void* const* vectors, int on_device);
+
+/* Solve D(mu) x_r = b_r for nrhs right-hand sides (spinor layout, nrhs
+ * contiguous fields) with FGMRES preconditioned by Eq. (1), stopping at a
+ * true relative residual <= tol computed in FP64.  Returns NOT_CONVERGED
+ * (x holds the last iterate) when max_iter is hit; BAD_STATE before setup.
+ * st (may be NULL) receives the statistics of the last right-hand side,
+ * with iteration counts summed over all of them. */
+int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, ddamg_stats* st, int on_device);
+
+/* ---- single operators, for parity checks (host or device FP64 arrays) ---- */
+/* out = D(sign*mu) in, full lattice (Sec. 1); precision FP64 or FP32 (and
+ * FP16/BF16 links with FP32 arithmetic). */
+int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int precision, int on_device);
+/* iters SAP iterations on D x = b starting from x (updated in place). */
+int ddamg_sap(ddamg_ctx* ctx, const void* b, void* x, int iters, int mr_steps, int precision, int on_device);
+/* level l >= 0: lattice dims of level l and components per site. */
+int ddamg_level_info(ddamg_ctx* ctx, int level, int dims[4], int* ncomp);
+/* orthonormalised test vectors spanning P from level l to l+1, level-l layout */
+int ddamg_get_interpolation(ddamg_ctx* ctx, int level, void* Q);
+/* r_c = P^dag r from level l to l+1; x = P e_c from level l+1 to l. */
+int ddamg_restrict(ddamg_ctx* ctx, int level, const void* in, void* out);
+int ddamg_prolong(ddamg_ctx* ctx, int level, const void* in, void* out);
+/* coarse operator of level l >= 1 as blocks: S [Vl][n][n] (self, without
+ * twist) and F [4][Vl][n][n] (forward T,Z,Y,X), row-major, FP64, host. */
+int ddamg_get_coarse_op(ddamg_ctx* ctx, int level, void* S, void* F);
+/* out = D_c(mu_l) in on level l >= 1 (stored precision). */
+int ddamg_apply_coarse(ddamg_ctx* ctx, int level, const void* in, void* out);
+/* coarse SAP iterations on level l (intermediate levels). */
+int ddamg_coarse_sap(ddamg_ctx* ctx, int level, const void* b, void* x, int iters);
+/* coarse solve of level l: odd-even GMRES on the coarsest level, FGMRES with
+ * the next level's cycle otherwise (parameters of the last setup). */
+int ddamg_coarse_solve(ddamg_ctx* ctx, int level, const void* b, void* x);
+/* out = V-cycle (Eq. 1) applied to in on the fine level, x0 = 0. */
+int ddamg_vcycle(ddamg_ctx* ctx, const void* in, void* out);
+
+/* ---- measurement ---- */
+/* Run napply applications of D(mu) on device-resident fields in the
+ * library's own layout (inputs already in HBM), on the context stream;
+ * returns immediately after enqueueing. */
+int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply);
+/* Per-kernel timing with HIP events on the context stream (kind: 0 = D(mu)
+ * fine apply, 1 = fine SAP sweep, 2 = coarse operator apply, 3 = restriction
+ * + prolongation).  enable = 1 starts recording, 0 stops; query returns launch
+ * count and total milliseconds so far (synchronises the stream). */
+int ddamg_timing(ddamg_ctx* ctx, int enable);
+int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDAMG_H */

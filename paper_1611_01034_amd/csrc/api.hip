@@ -1,0 +1,610 @@
+// extern "C" boundary of the library (declared in include/ddamg.h).  Every
+// entry point catches all exceptions and turns them into status codes.
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "solver.hpp"
+
+struct ddamg_ctx {
+  ddamg::Ctx c;
+};
+
+namespace ddamg {
+void check_finite(Ctx& c, const double* dev, long n);
+}
+
+using namespace ddamg;
+
+namespace {
+
+// sigma^chi_{mu nu} chirality blocks in the chiral basis, mu<nu over directions
+// 0:T 1:Z 2:Y 3:X, computed from g_mu = [[0,B_mu],[B_mu^dag,0]]:
+// sigma = (i/2)[g_mu, g_nu]; block chi=0 (spins 0,1): (i/2)(B_mu B_nu^dag - B_nu B_mu^dag),
+// block chi=1 (spins 2,3): (i/2)(B_mu^dag B_nu - B_nu^dag B_mu).
+void sigma_table(double* tab) {
+  using C = std::complex<double>;
+  const C I(0, 1);
+  // B_mu for T, Z, Y, X: B_T = -1, B_k = -i s_k
+  C B[4][2][2];
+  C s1[2][2] = {{0, 1}, {1, 0}}, s2[2][2] = {{0, -I}, {I, 0}}, s3[2][2] = {{1, 0}, {0, -1}};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      B[0][a][b] = a == b ? C(-1) : C(0);
+      B[1][a][b] = -I * s3[a][b];
+      B[2][a][b] = -I * s2[a][b];
+      B[3][a][b] = -I * s1[a][b];
+    }
+  auto mul = [](const C x[2][2], const C y[2][2], bool dx, bool dy, C out[2][2]) {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        C acc = 0;
+        for (int k = 0; k < 2; ++k) {
+          C xv = dx ? std::conj(x[k][i]) : x[i][k];
+          C yv = dy ? std::conj(y[j][k]) : y[k][j];
+          acc += xv * yv;
+        }
+        out[i][j] = acc;
+      }
+  };
+  int p = 0;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int nu = mu + 1; nu < 4; ++nu, ++p) {
+      C a[2][2], b[2][2];
+      // chirality 0
+      mul(B[mu], B[nu], false, true, a);
+      mul(B[nu], B[mu], false, true, b);
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          C v = 0.5 * I * (a[i][j] - b[i][j]);
+          tab[((p * 2 + 0) * 4 + 2 * i + j) * 2 + 0] = v.real();
+          tab[((p * 2 + 0) * 4 + 2 * i + j) * 2 + 1] = v.imag();
+        }
+      // chirality 1
+      mul(B[mu], B[nu], true, false, a);
+      mul(B[nu], B[mu], true, false, b);
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          C v = 0.5 * I * (a[i][j] - b[i][j]);
+          tab[((p * 2 + 1) * 4 + 2 * i + j) * 2 + 0] = v.real();
+          tab[((p * 2 + 1) * 4 + 2 * i + j) * 2 + 1] = v.imag();
+        }
+    }
+}
+
+template <class F>
+int guard(ddamg_ctx* ctx, F&& f) {
+  try {
+    if (ctx) ctx->c.err.clear();
+    return f();
+  } catch (const Error& e) {
+    if (ctx) ctx->c.err = e.what();
+    return e.status;
+  } catch (const HipError& e) {
+    if (ctx) ctx->c.err = e.what();
+    return e.code == hipErrorOutOfMemory ? DDAMG_OUT_OF_MEMORY : DDAMG_HIP_ERROR;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->c.err = "host allocation failed";
+    return DDAMG_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->c.err = e.what();
+    return DDAMG_HIP_ERROR;
+  }
+}
+
+void need_gauge(Ctx& c) {
+  if (!c.have_gauge) throw Error(BAD_STATE, "no gauge field set");
+}
+void need_setup(Ctx& c) {
+  need_gauge(c);
+  if (!c.have_setup || !c.mg) throw Error(BAD_STATE, "no multigrid setup");
+}
+
+void check_params(const ddamg_params* p) {
+  if (!p) throw Error(INVALID_ARG, "params is NULL");
+  if (p->levels < 2 || p->levels > 3) throw Error(INVALID_ARG, "levels must be 2 or 3");
+  if (p->sap_pre < 0 || p->sap_post < 0 || p->mr_steps < 0 || p->coarse_sap_post < 0 || p->coarse_mr_steps < 0 ||
+      p->init_sap_iters < 0 || p->setup_iters < 0 || p->coarse_setup_iters < 0)
+    throw Error(INVALID_ARG, "negative iteration count");
+  if (p->restart < 1 || p->inter_restart < 1 || p->coarse_restart < 1 || p->max_iter < 1 || p->inter_max_iter < 1 ||
+      p->coarse_max_iter < 1)
+    throw Error(INVALID_ARG, "restart lengths and iteration limits must be >= 1");
+  if (!(p->coarse_mu_factor >= 1.0) || !std::isfinite(p->coarse_mu_factor))
+    throw Error(INVALID_ARG, "coarse_mu_factor (delta) must be >= 1");
+  if (!(p->inter_tol > 0) || !(p->coarse_tol > 0)) throw Error(INVALID_ARG, "inner tolerances must be > 0");
+  if (p->precision < 0 || p->precision > 3) throw Error(INVALID_ARG, "unknown precision");
+}
+
+}  // namespace
+
+extern "C" {
+
+void ddamg_default_params(ddamg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->levels = 2;
+  for (int d = 0; d < 4; ++d) {
+    p->block[0][d] = 4;
+    p->block[1][d] = 2;
+    p->block[2][d] = 2;
+    p->coarse_sap_block[d] = 2;
+  }
+  p->nvec[0] = 24;
+  p->nvec[1] = 32;
+  p->nvec[2] = 32;
+  p->sap_pre = 0;
+  p->sap_post = 3;
+  p->mr_steps = 4;
+  p->coarse_sap_post = 2;
+  p->coarse_mr_steps = 3;
+  p->init_sap_iters = 3;
+  p->setup_iters = 3;
+  p->coarse_setup_iters = 3;
+  p->coarse_mu_factor = 1.0;
+  p->restart = 10;
+  p->max_iter = 1000;
+  p->inter_restart = 10;
+  p->inter_max_iter = 10;
+  p->inter_tol = 0.1;
+  p->coarse_restart = 30;
+  p->coarse_max_iter = 300;
+  p->coarse_tol = 0.1;
+  p->precision = DDAMG_FP64;
+  p->fixed_iters = 0;
+}
+
+int ddamg_create(const int dims[4], const int block[4], double kappa, double csw, double mu, void* stream,
+                 ddamg_ctx** out) {
+  if (!out) return DDAMG_INVALID_ARG;
+  *out = nullptr;
+  if (!dims || !block) return DDAMG_INVALID_ARG;
+  for (int d = 0; d < 4; ++d) {
+    if (dims[d] <= 0 || block[d] <= 0 || block[d] % 2 || dims[d] % block[d]) return DDAMG_INVALID_ARG;
+    if ((dims[d] / block[d]) % 2) return DDAMG_INVALID_ARG;
+  }
+  int bs = block[0] * block[1] * block[2] * block[3];
+  if (bs > 256) return DDAMG_INVALID_ARG;
+  if (!(kappa > 0) || !std::isfinite(kappa) || !std::isfinite(csw) || !std::isfinite(mu)) return DDAMG_INVALID_ARG;
+  ddamg_ctx* ctx = new (std::nothrow) ddamg_ctx();
+  if (!ctx) return DDAMG_OUT_OF_MEMORY;
+  int st = guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    c.st = (hipStream_t)stream;
+    c.timer.st = c.st;
+    Geom& g = c.g;
+    g.V = 1;
+    for (int d = 0; d < 4; ++d) {
+      g.L[d] = dims[d];
+      g.b[d] = block[d];
+      g.nb[d] = dims[d] / block[d];
+      g.V *= dims[d];
+    }
+    g.bs = bs;
+    g.half = bs / 2;
+    g.nblocks = g.nb[0] * g.nb[1] * g.nb[2] * g.nb[3];
+    c.kappa = kappa;
+    c.csw = csw;
+    c.mu = mu;
+    c.m0 = 1.0 / (2.0 * kappa) - 4.0;
+    double tab[6 * 2 * 4 * 2];
+    sigma_table(tab);
+    set_sigma_table(tab);
+    c.U64.alloc(sizeof(cx<double>) * (size_t)g.V * 36);
+    c.H64.alloc(sizeof(double) * (size_t)g.V * 72);
+    c.M64.alloc(sizeof(double) * (size_t)g.V * 36);
+    c.f64a.alloc(sizeof(cx<double>) * c.fine_len());
+    c.f64b.alloc(sizeof(cx<double>) * c.fine_len());
+    c.iflag.alloc(sizeof(int) * 4);
+    return DDAMG_OK;
+  });
+  if (st != DDAMG_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return DDAMG_OK;
+}
+
+void ddamg_destroy(ddamg_ctx* ctx) {
+  if (!ctx) return;
+  try {
+    (void)hipStreamSynchronize(ctx->c.st);
+  } catch (...) {
+  }
+  delete ctx;
+}
+
+const char* ddamg_last_error(const ddamg_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+int ddamg_set_gauge(ddamg_ctx* ctx, const void* links, int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (!links) throw Error(INVALID_ARG, "links is NULL");
+    size_t bytes = sizeof(cx<double>) * (size_t)c.g.V * 36;
+    const cx<double>* src = (const cx<double>*)links;
+    DevBuf stage;
+    if (!on_device) {
+      stage.alloc(bytes);
+      HIP_CHECK(hipMemcpyAsync(stage.p, links, bytes, hipMemcpyHostToDevice, c.st));
+      src = stage.as<cx<double>>();
+    }
+    check_finite(c, (const double*)src, (long)c.g.V * 72);
+    launch_links_from_lex(c.g, src, c.U64.as<cx<double>>(), c.st);
+    launch_clover(c.g, c.U64.as<cx<double>>(), c.csw, c.m0 + 4.0, c.H64.as<double>(), c.st);
+    c.have_32 = false;
+    c.u16_kind = -1;
+    c.rebuild_odd_inverse();
+    c.sync();
+    c.have_gauge = true;
+    c.have_setup = false;
+    c.mg.reset();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_set_clover(ddamg_ctx* ctx, const void* clover, int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    if (!clover) {
+      launch_clover(c.g, c.U64.as<cx<double>>(), c.csw, c.m0 + 4.0, c.H64.as<double>(), c.st);
+    } else {
+      size_t bytes = sizeof(cx<double>) * (size_t)c.g.V * 72;
+      const cx<double>* src = (const cx<double>*)clover;
+      DevBuf stage;
+      if (!on_device) {
+        stage.alloc(bytes);
+        HIP_CHECK(hipMemcpyAsync(stage.p, clover, bytes, hipMemcpyHostToDevice, c.st));
+        src = stage.as<cx<double>>();
+      }
+      check_finite(c, (const double*)src, (long)c.g.V * 144);
+      launch_clover_from_lex(c.g, src, c.m0 + 4.0, c.H64.as<double>(), c.st);
+    }
+    c.have_32 = false;
+    c.u16_kind = -1;
+    c.rebuild_odd_inverse();
+    c.sync();
+    c.have_setup = false;
+    c.mg.reset();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_get_clover(ddamg_ctx* ctx, void* clover) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    if (!clover) throw Error(INVALID_ARG, "clover is NULL");
+    size_t bytes = sizeof(cx<double>) * (size_t)c.g.V * 72;
+    DevBuf stage;
+    stage.alloc(bytes);
+    launch_clover_to_lex(c.g, c.H64.as<double>(), c.m0 + 4.0, stage.as<cx<double>>(), c.st);
+    HIP_CHECK(hipMemcpyAsync(clover, stage.p, bytes, hipMemcpyDeviceToHost, c.st));
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_set_mu(ddamg_ctx* ctx, double mu) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (!std::isfinite(mu)) throw Error(INVALID_ARG, "mu must be finite");
+    c.mu = mu;
+    if (c.have_gauge) c.rebuild_odd_inverse();
+    if (c.mg) c.mg->set_mu(mu);
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+static int do_build(ddamg_ctx* ctx, const ddamg_params* p, const void* const* vecs, int on_device, bool run_setup) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    check_params(p);
+    if (!vecs) throw Error(INVALID_ARG, "init vectors are NULL");
+    for (int l = 0; l < p->levels - 1; ++l)
+      if (!vecs[l]) throw Error(INVALID_ARG, "init vectors are NULL");
+    c.have_setup = false;
+    c.mg.reset();
+    c.p = *p;
+    c.mg = make_mg(c);
+    c.mg->build(vecs, on_device, run_setup);
+    c.have_setup = true;
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_setup(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_vectors, int on_device) {
+  return do_build(ctx, p, init_vectors, on_device, true);
+}
+int ddamg_set_test_vectors(ddamg_ctx* ctx, const ddamg_params* p, const void* const* vectors, int on_device) {
+  return do_build(ctx, p, vectors, on_device, false);
+}
+
+int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, ddamg_stats* stats, int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_setup(c);
+    if (!b || !x || nrhs <= 0) throw Error(INVALID_ARG, "bad right-hand side arguments");
+    if (!(tol > 0) || !std::isfinite(tol)) throw Error(INVALID_ARG, "tol must be > 0");
+    auto t0 = std::chrono::steady_clock::now();
+    long N = c.fine_len();
+    c.outer.init(c.p.restart, N, N, true);
+    c.f64c.ensure(sizeof(cx<double>) * N);
+    std::function<void(const cx<double>*, cx<double>*)> A = [&c](const cx<double>* in, cx<double>* out) {
+      c.dirac64(in, out, c.mu);
+    };
+    std::function<void(const cx<double>*, cx<double>*)> M = [&c](const cx<double>* in, cx<double>* out) {
+      c.mg->precond(in, out);
+    };
+    for (int l = 0; l < 4; ++l) c.mg->coarse_iters[l] = 0;
+    c.mg->vcycles = 0;
+    int total_it = 0;
+    bool all_conv = true;
+    KrylovResult kr;
+    for (int r = 0; r < nrhs; ++r) {
+      const char* bs = (const char*)b + sizeof(cx<double>) * (size_t)N * r;
+      char* xs = (char*)x + sizeof(cx<double>) * (size_t)N * r;
+      c.upload_fine(bs, on_device, c.f64a.as<cx<double>>());
+      check_finite(c, (const double*)c.f64a.p, 2 * N);
+      kr = fgmres<double>(c, c.outer, N, A, &M, c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>(), tol, c.p.max_iter,
+                          false, true);
+      total_it += kr.iters;
+      all_conv = all_conv && kr.converged;
+      c.download_fine(c.f64b.as<cx<double>>(), xs, on_device);
+    }
+    c.sync();
+    if (stats) {
+      stats->iters = total_it;
+      stats->converged = all_conv ? 1 : 0;
+      stats->resid = kr.resid;
+      for (int l = 0; l < 4; ++l) stats->coarse_iters[l] = c.mg->coarse_iters[l];
+      stats->vcycles = c.mg->vcycles;
+      stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!all_conv) {
+      c.err = "FGMRES reached max_iter before the tolerance";
+      return DDAMG_NOT_CONVERGED;
+    }
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int precision, int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    if (!in || !out) throw Error(INVALID_ARG, "NULL field");
+    double tw = sign < 0 ? -c.mu : c.mu;
+    long N = c.fine_len();
+    c.upload_fine(in, on_device, c.f64a.as<cx<double>>());
+    if (precision == DDAMG_FP64) {
+      c.dirac64(c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>(), tw);
+    } else {
+      c.ensure_32();
+      c.f32a.ensure(sizeof(cx<float>) * N);
+      c.f32b.ensure(sizeof(cx<float>) * N);
+      launch_copy_cvt<double, float>(c.f64a.as<cx<double>>(), c.f32a.as<cx<float>>(), N, c.st);
+      if (precision == DDAMG_FP32)
+        launch_dirac<float, float>(c.g, c.U32.p, c.H32.as<float>(), tw, c.f32a.as<cx<float>>(),
+                                   c.f32b.as<cx<float>>(), c.st);
+      else if (precision == DDAMG_FP16 || precision == DDAMG_BF16) {
+        c.ensure_16(precision);
+        if (precision == DDAMG_FP16)
+          launch_dirac<float, f16>(c.g, c.U16.p, c.H32.as<float>(), tw, c.f32a.as<cx<float>>(),
+                                   c.f32b.as<cx<float>>(), c.st);
+        else
+          launch_dirac<float, bf16>(c.g, c.U16.p, c.H32.as<float>(), tw, c.f32a.as<cx<float>>(),
+                                    c.f32b.as<cx<float>>(), c.st);
+      } else
+        throw Error(INVALID_ARG, "unknown precision");
+      launch_copy_cvt<float, double>(c.f32b.as<cx<float>>(), c.f64b.as<cx<double>>(), N, c.st);
+    }
+    c.download_fine(c.f64b.as<cx<double>>(), out, on_device);
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_sap(ddamg_ctx* ctx, const void* b, void* x, int iters, int mr_steps, int precision, int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    if (!b || !x || iters < 0 || mr_steps < 0) throw Error(INVALID_ARG, "bad SAP arguments");
+    long N = c.fine_len();
+    c.upload_fine(b, on_device, c.f64a.as<cx<double>>());
+    c.upload_fine(x, on_device, c.f64b.as<cx<double>>());
+    if (precision == DDAMG_FP64) {
+      for (int it = 0; it < iters; ++it)
+        for (int col = 0; col < 2; ++col)
+          launch_sap<double, double>(c.g, col, c.U64.p, c.H64.as<double>(), c.M64.as<double>(), c.mu,
+                                     c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>(), mr_steps, c.st);
+    } else if (precision == DDAMG_FP32) {
+      c.ensure_32();
+      c.f32a.ensure(sizeof(cx<float>) * N);
+      c.f32b.ensure(sizeof(cx<float>) * N);
+      launch_copy_cvt<double, float>(c.f64a.as<cx<double>>(), c.f32a.as<cx<float>>(), N, c.st);
+      launch_copy_cvt<double, float>(c.f64b.as<cx<double>>(), c.f32b.as<cx<float>>(), N, c.st);
+      for (int it = 0; it < iters; ++it)
+        for (int col = 0; col < 2; ++col)
+          launch_sap<float, float>(c.g, col, c.U32.p, c.H32.as<float>(), c.M32.as<float>(), c.mu,
+                                   c.f32a.as<cx<float>>(), c.f32b.as<cx<float>>(), mr_steps, c.st);
+      launch_copy_cvt<float, double>(c.f32b.as<cx<float>>(), c.f64b.as<cx<double>>(), N, c.st);
+    } else
+      throw Error(INVALID_ARG, "SAP parity entry supports FP64 and FP32");
+    c.download_fine(c.f64b.as<cx<double>>(), x, on_device);
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_level_info(ddamg_ctx* ctx, int level, int dims[4], int* ncomp) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (level == 0) {
+      for (int d = 0; d < 4; ++d) dims[d] = c.g.L[d];
+      *ncomp = 12;
+      return DDAMG_OK;
+    }
+    need_setup(c);
+    if (level < 0 || level >= c.mg->nlev()) throw Error(INVALID_ARG, "bad level");
+    const CoarseGeo& G = c.mg->geo(level);
+    for (int d = 0; d < 4; ++d) dims[d] = G.L[d];
+    *ncomp = G.n;
+    return DDAMG_OK;
+  });
+}
+
+#define LEVEL_CHECK(lo, hi_off)                                                               \
+  need_setup(c);                                                                              \
+  if (level < (lo) || level >= c.mg->nlev() - (hi_off)) throw Error(INVALID_ARG, "bad level");
+
+int ddamg_get_interpolation(ddamg_ctx* ctx, int level, void* Q) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(0, 1);
+    c.mg->get_interp(level, (cx<double>*)Q);
+    return DDAMG_OK;
+  });
+}
+int ddamg_restrict(ddamg_ctx* ctx, int level, const void* in, void* out) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(0, 1);
+    c.mg->restrict_host(level, (const cx<double>*)in, (cx<double>*)out);
+    return DDAMG_OK;
+  });
+}
+int ddamg_prolong(ddamg_ctx* ctx, int level, const void* in, void* out) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(0, 1);
+    c.mg->prolong_host(level, (const cx<double>*)in, (cx<double>*)out);
+    return DDAMG_OK;
+  });
+}
+int ddamg_get_coarse_op(ddamg_ctx* ctx, int level, void* S, void* F) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 0);
+    c.mg->get_coarse_op(level, (cx<double>*)S, (cx<double>*)F);
+    return DDAMG_OK;
+  });
+}
+int ddamg_apply_coarse(ddamg_ctx* ctx, int level, const void* in, void* out) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 0);
+    c.mg->apply_coarse_host(level, (const cx<double>*)in, (cx<double>*)out);
+    return DDAMG_OK;
+  });
+}
+int ddamg_coarse_sap(ddamg_ctx* ctx, int level, const void* b, void* x, int iters) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 1);
+    c.mg->coarse_sap_host(level, (const cx<double>*)b, (cx<double>*)x, iters);
+    return DDAMG_OK;
+  });
+}
+int ddamg_coarse_solve(ddamg_ctx* ctx, int level, const void* b, void* x) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 0);
+    c.mg->coarse_solve_host(level, (const cx<double>*)b, (cx<double>*)x);
+    return DDAMG_OK;
+  });
+}
+int ddamg_vcycle(ddamg_ctx* ctx, const void* in, void* out) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_setup(c);
+    c.upload_fine(in, 0, c.f64a.as<cx<double>>());
+    c.mg->precond(c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>());
+    c.download_fine(c.f64b.as<cx<double>>(), out, 0);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    long N = c.fine_len();
+    if (precision == DDAMG_FP64) {
+      for (int i = 0; i < napply; ++i) {
+        const cx<double>* in = (i & 1) ? c.f64b.as<cx<double>>() : c.f64a.as<cx<double>>();
+        cx<double>* out = (i & 1) ? c.f64a.as<cx<double>>() : c.f64b.as<cx<double>>();
+        c.dirac64(in, out, c.mu);
+      }
+      return DDAMG_OK;
+    }
+    c.ensure_32();
+    c.f32a.ensure(sizeof(cx<float>) * N);
+    c.f32b.ensure(sizeof(cx<float>) * N);
+    const void* U = c.U32.p;
+    if (precision == DDAMG_FP16 || precision == DDAMG_BF16) {
+      c.ensure_16(precision);
+      U = c.U16.p;
+    }
+    for (int i = 0; i < napply; ++i) {
+      const cx<float>* in = (i & 1) ? c.f32b.as<cx<float>>() : c.f32a.as<cx<float>>();
+      cx<float>* out = (i & 1) ? c.f32a.as<cx<float>>() : c.f32b.as<cx<float>>();
+      hipEvent_t a;
+      c.timer.begin(0, &a);
+      if (precision == DDAMG_FP32) launch_dirac<float, float>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
+      else if (precision == DDAMG_FP16) launch_dirac<float, f16>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
+      else launch_dirac<float, bf16>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
+      c.timer.end(0, a);
+    }
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_timing(ddamg_ctx* ctx, int enable) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (enable) {
+      c.timer.flush();
+      c.timer.reset();
+      c.timer.on = true;
+    } else {
+      c.timer.flush();
+      c.timer.on = false;
+    }
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms) {
+  if (!ctx || kind < 0 || kind > 3) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    c.timer.flush();
+    if (count) *count = c.timer.count[kind];
+    if (ms) *ms = c.timer.ms[kind];
+    return DDAMG_OK;
+  });
+}
+
+}  // extern "C"

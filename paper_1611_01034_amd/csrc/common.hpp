@@ -1,0 +1,194 @@
+// Shared device/host definitions of the DD-alpha-AMG library (gfx950).
+//
+// Fine-lattice device layout ("block layout"): the lattice (T,Z,Y,X) is cut
+// into blocks of b = (bT,bZ,bY,bX) sites, all extents even.  The block is the
+// SAP domain and the first aggregate.  Blocks are numbered lexicographically
+// over block coordinates (T slowest).  Inside a block the bs = bT*bZ*bY*bX
+// sites are stored parity-major: slot = parity*half + (lexicographic local
+// index >> 1), parity = (t+z+y+x) mod 2 (block origins are even, so local and
+// global parity agree).  A field with C complex components per site is stored
+// component-major inside each block: element (B, c, slot) at
+// (B*C + c)*bs + slot, so a wavefront reading one component of 64
+// consecutive slots reads one contiguous segment.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+namespace ddamg {
+
+template <class T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <class T> __host__ __device__ __forceinline__ cx<T> mk(T r, T i) { cx<T> z; z.re = r; z.im = i; return z; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a) { return mk(-a.re, -a.im); }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class T> __host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return mk(s * a.re, s * a.im); }
+template <class T> __host__ __device__ __forceinline__ cx<T>& operator+=(cx<T>& a, cx<T> b) { a.re += b.re; a.im += b.im; return a; }
+template <class T> __host__ __device__ __forceinline__ cx<T>& operator-=(cx<T>& a, cx<T> b) { a.re -= b.re; a.im -= b.im; return a; }
+template <class T> __host__ __device__ __forceinline__ cx<T> conj(cx<T> a) { return mk(a.re, -a.im); }
+template <class T> __host__ __device__ __forceinline__ cx<T> times_i(cx<T> a) { return mk(-a.im, a.re); }
+template <class T> __host__ __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return mk(a.im, -a.re); }
+// a += b*c  and  a += conj(b)*c
+template <class T> __host__ __device__ __forceinline__ void cmac(cx<T>& a, cx<T> b, cx<T> c) {
+  a.re += b.re * c.re - b.im * c.im;
+  a.im += b.re * c.im + b.im * c.re;
+}
+template <class T> __host__ __device__ __forceinline__ void cjmac(cx<T>& a, cx<T> b, cx<T> c) {
+  a.re += b.re * c.re + b.im * c.im;
+  a.im += b.re * c.im - b.im * c.re;
+}
+template <class T> __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ---- storage types: complex numbers in double, float, fp16 or bf16 ----------
+// 16-bit storage uses the compiler's native _Float16 and __bf16 types; every
+// narrowing conversion rounds to nearest even.
+using f16 = _Float16;
+using bf16 = __bf16;
+struct alignas(4) h2 { f16 re, im; };
+struct alignas(4) b2 { bf16 re, im; };
+
+template <class S> struct store_traits;
+template <> struct store_traits<double> { using elem = cx<double>; };
+template <> struct store_traits<float> { using elem = cx<float>; };
+template <> struct store_traits<f16> { using elem = h2; };
+template <> struct store_traits<bf16> { using elem = b2; };
+
+template <class R, class S>
+__device__ __forceinline__ cx<R> ld(const typename store_traits<S>::elem* p, long i);
+template <> __device__ __forceinline__ cx<double> ld<double, double>(const cx<double>* p, long i) { return p[i]; }
+template <> __device__ __forceinline__ cx<float> ld<float, float>(const cx<float>* p, long i) { return p[i]; }
+template <> __device__ __forceinline__ cx<double> ld<double, float>(const cx<float>* p, long i) {
+  cx<float> v = p[i]; return mk<double>(v.re, v.im);
+}
+template <> __device__ __forceinline__ cx<float> ld<float, double>(const cx<double>* p, long i) {
+  cx<double> v = p[i]; return mk<float>((float)v.re, (float)v.im);
+}
+template <> __device__ __forceinline__ cx<float> ld<float, f16>(const h2* p, long i) {
+  h2 v = p[i]; return mk<float>((float)v.re, (float)v.im);
+}
+template <> __device__ __forceinline__ cx<float> ld<float, bf16>(const b2* p, long i) {
+  b2 v = p[i]; return mk<float>((float)v.re, (float)v.im);
+}
+
+template <class S, class R> __device__ __forceinline__ typename store_traits<S>::elem st_cvt(cx<R> v);
+template <> __device__ __forceinline__ cx<double> st_cvt<double, double>(cx<double> v) { return v; }
+template <> __device__ __forceinline__ cx<float> st_cvt<float, double>(cx<double> v) { return mk<float>((float)v.re, (float)v.im); }
+template <> __device__ __forceinline__ cx<float> st_cvt<float, float>(cx<float> v) { return v; }
+template <> __device__ __forceinline__ cx<double> st_cvt<double, float>(cx<float> v) { return mk<double>(v.re, v.im); }
+template <> __device__ __forceinline__ h2 st_cvt<f16, double>(cx<double> v) {
+  h2 r; r.re = (f16)v.re; r.im = (f16)v.im; return r;
+}
+template <> __device__ __forceinline__ b2 st_cvt<bf16, double>(cx<double> v) {
+  b2 r; r.re = (bf16)v.re; r.im = (bf16)v.im; return r;
+}
+
+// ---- fine-lattice geometry -------------------------------------------------
+struct Geom {
+  int L[4];      // extents T,Z,Y,X
+  int b[4];      // block extents
+  int nb[4];     // blocks per direction
+  int nblocks;   // number of blocks
+  int bs;        // sites per block
+  int half;      // bs/2
+  long V;        // sites
+};
+
+// local coordinates of a slot
+__host__ __device__ __forceinline__ void slot_local(const Geom& g, int s, int l[4]) {
+  int p = s >= g.half ? 1 : 0;
+  int idx = s - p * g.half;
+  int bx2 = g.b[3] >> 1;
+  int lx2 = idx % bx2;
+  int r = idx / bx2;
+  l[2] = r % g.b[2];
+  r /= g.b[2];
+  l[1] = r % g.b[1];
+  l[0] = r / g.b[1];
+  l[3] = 2 * lx2 + ((p + l[0] + l[1] + l[2]) & 1);
+}
+
+__host__ __device__ __forceinline__ int local_slot(const Geom& g, const int l[4]) {
+  int p = (l[0] + l[1] + l[2] + l[3]) & 1;
+  int idx = ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * (g.b[3] >> 1) + (l[3] >> 1);
+  return p * g.half + idx;
+}
+
+__host__ __device__ __forceinline__ void block_coords(const Geom& g, int B, int c[4]) {
+  c[3] = B % g.nb[3];
+  int r = B / g.nb[3];
+  c[2] = r % g.nb[2];
+  r /= g.nb[2];
+  c[1] = r % g.nb[1];
+  c[0] = r / g.nb[1];
+}
+
+__host__ __device__ __forceinline__ int block_index(const Geom& g, const int c[4]) {
+  return ((c[0] * g.nb[1] + c[1]) * g.nb[2] + c[2]) * g.nb[3] + c[3];
+}
+
+// global coordinates of (block, slot)
+__host__ __device__ __forceinline__ void site_coords(const Geom& g, int B, int s, int x[4]) {
+  int bc[4], l[4];
+  block_coords(g, B, bc);
+  slot_local(g, s, l);
+  for (int d = 0; d < 4; ++d) x[d] = bc[d] * g.b[d] + l[d];
+}
+
+// (block, slot) of global coordinates
+__host__ __device__ __forceinline__ void coords_site(const Geom& g, const int x[4], int& B, int& s) {
+  int bc[4], l[4];
+  for (int d = 0; d < 4; ++d) {
+    bc[d] = x[d] / g.b[d];
+    l[d] = x[d] - bc[d] * g.b[d];
+  }
+  B = block_index(g, bc);
+  s = local_slot(g, l);
+}
+
+// neighbour of (B,s) one step in direction mu with sign dir (+1 / -1), periodic
+__host__ __device__ __forceinline__ void neighbour(const Geom& g, int B, int s, int mu, int dir, int& Bn, int& sn) {
+  int x[4];
+  site_coords(g, B, s, x);
+  x[mu] += dir;
+  if (x[mu] == g.L[mu]) x[mu] = 0;
+  if (x[mu] < 0) x[mu] = g.L[mu] - 1;
+  coords_site(g, x, Bn, sn);
+}
+
+__host__ __device__ __forceinline__ long lex_index(const Geom& g, const int x[4]) {
+  return (((long)x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+}
+
+// ---- host-side error types ------------------------------------------------
+struct HipError : std::runtime_error {
+  hipError_t code;
+  HipError(hipError_t e, const char* expr, const char* file, int line)
+      : std::runtime_error(std::string(hipGetErrorString(e)) + " in " + expr + " (" + file + ":" +
+                           std::to_string(line) + ")"),
+        code(e) {}
+};
+
+// status codes of the C ABI
+enum Status { OK = 0, NOT_CONVERGED = 1, INVALID_ARG = -1, BAD_STATE = -2, HIP_FAIL = -3, OUT_OF_MEMORY = -4, NUMERICAL = -5 };
+
+struct Error : std::runtime_error {
+  int status;
+  Error(int st, const std::string& msg) : std::runtime_error(msg), status(st) {}
+};
+
+}  // namespace ddamg
+
+#define HIP_CHECK(expr)                                                          \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess) throw ::ddamg::HipError(_e, #expr, __FILE__, __LINE__); \
+  } while (0)

@@ -1,0 +1,1067 @@
+// Fine-lattice kernels: layout transforms, clover term, the twisted-mass
+// Wilson-clover operator D(mu) = D_W + i mu Gamma5 (paper Sec. 1), the SAP
+// smoother with odd-even block MR (Sec. 1 smoother, Sec. 3 odd-even in the
+// smoother), Gamma5-compatible restriction / prolongation and block
+// orthonormalisation (Sec. 1 aggregation), and the Galerkin assembly of the
+// first coarse operator D_c = P^dag D_W P (Sec. 1, Eq. 1 context).
+//
+// Operator conventions (the paper fixes gamma5 = diag(-1,-1,1,1) and TZYX
+// order only):
+//   (D psi)(x) = T(x) psi(x) - 1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu)
+//                                        + (1+g_mu) U_mu(x-mu)^dag psi(x-mu)]
+//   T(x) = (m0+4) + A(x) + i tw gamma5,   A = (i c_sw/4) sum sigma_{mu nu} F_{mu nu}
+// Chiral gamma basis: g_k = [[0,-i s_k],[i s_k,0]] (k = X,Y,Z), g_T = [[0,-1],[-1,0]].
+// With g_mu = [[0,B],[B^dag,0]] the projector (1 -+ g_mu) has rank 2: only the
+// half spinor h = psi_up -+ B psi_dn is transported by U, the lower half is
+// rebuilt from it.  Per direction and sign the reconstruction is a pair of
+// phases in {1, i, -1, -i} and a spin permutation (tables below).
+#include "kernels.hpp"
+
+namespace ddamg {
+
+// phase codes: 0:+1 1:+i 2:-1 3:-i
+template <int K, class R>
+__device__ __forceinline__ cx<R> ph(cx<R> a) {
+  if constexpr (K == 0) return a;
+  else if constexpr (K == 1) return times_i(a);
+  else if constexpr (K == 2) return -a;
+  else return times_mi(a);
+}
+
+// Spin-projection tables for -1/2 (1 -+ g_mu): h0 = psi0 + a0 psi_p0,
+// h1 = psi1 + a1 psi_p1;  out0 -= h0'/2, out1 -= h1'/2, out2 += c2/2 * h_q2',
+// out3 += c3/2 * h_q3'  (h' = U h forward, U^dag h backward).
+struct ProjT {
+  int a0, p0, a1, p1, c2, q2, c3, q3;
+};
+__host__ __device__ constexpr ProjT proj_tab(int bwd, int mu) {
+  constexpr ProjT t[2][4] = {
+      {{0, 2, 0, 3, 2, 0, 2, 1}, {1, 2, 3, 3, 1, 0, 3, 1}, {0, 3, 2, 2, 0, 1, 2, 0}, {1, 3, 1, 2, 1, 1, 1, 0}},
+      {{2, 2, 2, 3, 0, 0, 0, 1}, {3, 2, 1, 3, 3, 0, 1, 1}, {2, 3, 0, 2, 2, 1, 0, 0}, {3, 3, 3, 2, 3, 1, 3, 0}}};
+  return t[bwd][mu];
+}
+
+// accumulate -1/2 (1 -+ g_mu) W psi into out (W = U forward, U^dag backward)
+template <int BWD, int MU, class R>
+__device__ __forceinline__ void hop_accum_t(const cx<R> psi[12], const cx<R> u[9], cx<R> out[12]) {
+  constexpr ProjT t = proj_tab(BWD, MU);
+  cx<R> h[2][3], w[2][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h[0][c] = psi[c] + ph<t.a0>(psi[3 * t.p0 + c]);
+    h[1][c] = psi[3 + c] + ph<t.a1>(psi[3 * t.p1 + c]);
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if constexpr (BWD) cjmac(acc, u[3 * b + a], h[s][b]);
+        else cmac(acc, u[3 * a + b], h[s][b]);
+      }
+      w[s][a] = acc;
+    }
+  const R hf = R(0.5);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    out[a] -= hf * w[0][a];
+    out[3 + a] -= hf * w[1][a];
+    out[6 + a] += hf * ph<t.c2>(w[t.q2][a]);
+    out[9 + a] += hf * ph<t.c3>(w[t.q3][a]);
+  }
+}
+
+template <int BWD, class R>
+__device__ __forceinline__ void hop_accum(int mu, const cx<R> psi[12], const cx<R> u[9], cx<R> out[12]) {
+  switch (mu) {
+    case 0: hop_accum_t<BWD, 0>(psi, u, out); break;
+    case 1: hop_accum_t<BWD, 1>(psi, u, out); break;
+    case 2: hop_accum_t<BWD, 2>(psi, u, out); break;
+    default: hop_accum_t<BWD, 3>(psi, u, out); break;
+  }
+}
+
+template <class R, class S>
+__device__ __forceinline__ void load_link(const typename store_traits<S>::elem* U, const Geom& g, int B, int s, int mu,
+                                          cx<R> u[9]) {
+  long base = ((long)(B * 4 + mu) * 9) * g.bs + s;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[k] = ld<R, S>(U, base + (long)k * g.bs);
+}
+
+template <class R>
+__device__ __forceinline__ void load_spinor(const cx<R>* f, const Geom& g, int B, int s, cx<R> p[12]) {
+  long base = (long)B * 12 * g.bs + s;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c] = f[base + (long)c * g.bs];
+}
+
+template <class R>
+__device__ __forceinline__ void store_spinor(cx<R>* f, const Geom& g, int B, int s, const cx<R> p[12]) {
+  long base = (long)B * 12 * g.bs + s;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) f[base + (long)c * g.bs] = p[c];
+}
+
+// packed Hermitian 6x6: 6 real diagonal entries, then the 15 upper entries
+// (i<j, row-major) as (re,im) pairs
+__host__ __device__ __forceinline__ int herm_idx(int i, int j) { return 5 * i - (i * (i - 1)) / 2 + (j - i - 1); }
+
+template <class R>
+__device__ __forceinline__ void herm_mv(const R* hp, long stride, const cx<R> x[6], cx<R> y[6]) {
+  R h[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) h[k] = hp[(long)k * stride];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    cx<R> acc = h[i] * x[i];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (j == i) continue;
+      if (j > i) {
+        int k = 6 + 2 * herm_idx(i, j);
+        cmac(acc, mk<R>(h[k], h[k + 1]), x[j]);
+      } else {
+        int k = 6 + 2 * herm_idx(j, i);
+        cjmac(acc, mk<R>(h[k], h[k + 1]), x[j]);
+      }
+    }
+    y[i] = acc;
+  }
+}
+
+// T psi at (B,s): (m0+4+A) psi + i tw gamma5 psi
+template <class R>
+__device__ __forceinline__ void site_term(const R* H, const Geom& g, int B, int s, R tw, const cx<R> psi[12],
+                                          cx<R> out[12]) {
+  const R* hp = H + (long)B * 72 * g.bs + s;
+  herm_mv(hp, g.bs, psi, out);
+  herm_mv(hp + 36L * g.bs, g.bs, psi + 6, out + 6);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    out[c] += tw * times_mi(psi[c]);
+    out[6 + c] += tw * times_i(psi[6 + c]);
+  }
+}
+
+// T^{-1} psi on an odd slot: per chirality (H -+ i tw) M psi with M = (H^2+tw^2)^{-1}
+// (H is Hermitian, so (H + i a)^{-1} = (H - i a)(H^2 + a^2)^{-1}); chirality 0 has
+// the twist -i tw, chirality 1 +i tw.
+template <class R>
+__device__ __forceinline__ void site_inv(const R* H, const R* Minv, const Geom& g, int B, int s, R tw,
+                                         const cx<R> psi[12], cx<R> out[12]) {
+  const R* hp = H + (long)B * 72 * g.bs + s;
+  const R* mp = Minv + (long)B * 72 * g.half + (s - g.half);
+  cx<R> t[12];
+  herm_mv(mp, g.half, psi, t);
+  herm_mv(mp + 36L * g.half, g.half, psi + 6, t + 6);
+  herm_mv(hp, g.bs, t, out);
+  herm_mv(hp + 36L * g.bs, g.bs, t + 6, out + 6);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    out[c] += tw * times_i(t[c]);
+    out[6 + c] += tw * times_mi(t[6 + c]);
+  }
+}
+
+struct SiteNbr {
+  int bc[4], l[4];
+};
+
+__device__ __forceinline__ void nbr_of(const Geom& g, const SiteNbr& sn, int mu, int dir, int& Bn, int& snb) {
+  int bc[4] = {sn.bc[0], sn.bc[1], sn.bc[2], sn.bc[3]};
+  int l[4] = {sn.l[0], sn.l[1], sn.l[2], sn.l[3]};
+  l[mu] += dir;
+  if (l[mu] == g.b[mu]) {
+    l[mu] = 0;
+    bc[mu] = (bc[mu] + 1 == g.nb[mu]) ? 0 : bc[mu] + 1;
+  } else if (l[mu] < 0) {
+    l[mu] = g.b[mu] - 1;
+    bc[mu] = (bc[mu] == 0) ? g.nb[mu] - 1 : bc[mu] - 1;
+  }
+  Bn = block_index(g, bc);
+  snb = local_slot(g, l);
+}
+
+// hopping part of D at (B,s) with all neighbours read from global memory
+template <int MU, class R, class S>
+__device__ __forceinline__ void hop_global_dir(const typename store_traits<S>::elem* U, const cx<R>* in, const Geom& g,
+                                               int B, int s, const SiteNbr& me, cx<R> out[12]) {
+  cx<R> psi[12], u[9];
+  int Bn, sn;
+  nbr_of(g, me, MU, +1, Bn, sn);
+  load_spinor(in, g, Bn, sn, psi);
+  load_link<R, S>(U, g, B, s, MU, u);
+  hop_accum_t<0, MU>(psi, u, out);
+  nbr_of(g, me, MU, -1, Bn, sn);
+  load_spinor(in, g, Bn, sn, psi);
+  load_link<R, S>(U, g, Bn, sn, MU, u);
+  hop_accum_t<1, MU>(psi, u, out);
+}
+
+template <class R, class S>
+__device__ __forceinline__ void hop_global(const typename store_traits<S>::elem* U, const cx<R>* in, const Geom& g,
+                                           int B, int s, const SiteNbr& me, cx<R> out[12]) {
+  hop_global_dir<0, R, S>(U, in, g, B, s, me, out);
+  hop_global_dir<1, R, S>(U, in, g, B, s, me, out);
+  hop_global_dir<2, R, S>(U, in, g, B, s, me, out);
+  hop_global_dir<3, R, S>(U, in, g, B, s, me, out);
+}
+
+__device__ __forceinline__ void me_of(const Geom& g, int B, int s, SiteNbr& me) {
+  block_coords(g, B, me.bc);
+  slot_local(g, s, me.l);
+}
+
+// ---------------------------------------------------------------------------
+// D(tw) psi, full lattice, one work-item per site
+template <class R, class S>
+__global__ void __launch_bounds__(256) k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U,
+                                               const R* __restrict__ H, R tw, const cx<R>* __restrict__ in,
+                                               cx<R>* __restrict__ out) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  SiteNbr me;
+  me_of(g, B, s, me);
+  cx<R> psi[12], acc[12];
+  load_spinor(in, g, B, s, psi);
+  site_term(H, g, B, s, tw, psi, acc);
+  hop_global<R, S>(U, in, g, B, s, me, acc);
+  store_spinor(out, g, B, s, acc);
+}
+
+template <class R, class S>
+void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<R>* in, cx<R>* out, hipStream_t st) {
+  long n = g.V;
+  int blocks = (int)((n + 255) / 256);
+  hipLaunchKernelGGL((k_dirac<R, S>), dim3(blocks), dim3(256), 0, st, g,
+                     (const typename store_traits<S>::elem*)U, H, (R)tw, in, out);
+}
+template void launch_dirac<double, double>(const Geom&, const void*, const double*, double, const cx<double>*,
+                                           cx<double>*, hipStream_t);
+template void launch_dirac<float, float>(const Geom&, const void*, const float*, double, const cx<float>*,
+                                         cx<float>*, hipStream_t);
+template void launch_dirac<float, f16>(const Geom&, const void*, const float*, double, const cx<float>*,
+                                          cx<float>*, hipStream_t);
+template void launch_dirac<float, bf16>(const Geom&, const void*, const float*, double,
+                                                  const cx<float>*, cx<float>*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// workgroup reduction helpers (deterministic: fixed shuffle and wave order)
+
+// ---------------------------------------------------------------------------
+// SAP: one colour sweep.  One workgroup per block of the colour, one thread per
+// (even slot i, odd slot half+i).  r = b - D x on the block, then n_mr MR steps
+// on the block-local even-site Schur complement S = T_ee - D_eo T_oo^{-1} D_oe
+// (hops leaving the block dropped), odd reconstruction, x += e.
+template <class R, class S>
+__device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::elem* U, const Geom& g, int B, int s,
+                                              const SiteNbr& me, const cx<R>* lds, int lds_off, cx<R> out[12]) {
+  // lds holds a 12 x half field of the opposite parity (component-major)
+  cx<R> psi[12], u[9];
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    if (me.l[mu] + 1 < g.b[mu]) {
+      int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
+      l[mu] += 1;
+      int sn = local_slot(g, l) - lds_off;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) psi[c] = lds[c * g.half + sn];
+      load_link<R, S>(U, g, B, s, mu, u);
+      hop_accum<0>(mu, psi, u, out);
+    }
+    if (me.l[mu] > 0) {
+      int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
+      l[mu] -= 1;
+      int slot = local_slot(g, l);
+      int sn = slot - lds_off;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) psi[c] = lds[c * g.half + sn];
+      load_link<R, S>(U, g, B, slot, mu, u);
+      hop_accum<1>(mu, psi, u, out);
+    }
+  }
+}
+
+template <class R, class S>
+__global__ void __launch_bounds__(256) k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U,
+                                             const R* __restrict__ H, const R* __restrict__ Minv, R tw,
+                                             const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr) {
+  extern __shared__ char smem_raw[];
+  cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x half
+  cx<R>* od = ev + 12 * g.half;                     // 12 x half
+  cx<R>* ro = od + 12 * g.half;                     // 12 x half
+  __shared__ double red[3][16];
+  // block of this colour: same trick as for sites, nb[3] is even
+  int w = blockIdx.x;
+  int B;
+  {
+    int B0 = 2 * w;
+    int bc[4];
+    block_coords(g, B0, bc);
+    int par = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
+    B = B0 + ((par ^ colour) & 1);
+  }
+  int i = threadIdx.x;
+  const int se = i, so = g.half + i;
+  SiteNbr me_e, me_o;
+  me_of(g, B, se, me_e);
+  me_of(g, B, so, me_o);
+  cx<R> re[12], tmp[12], psi[12];
+  // residual on both slots
+  load_spinor(x, g, B, se, psi);
+  site_term(H, g, B, se, tw, psi, tmp);
+  hop_global<R, S>(U, x, g, B, se, me_e, tmp);
+  load_spinor(b, g, B, se, re);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) re[c] -= tmp[c];
+  {
+    cx<R> r_o[12];
+    load_spinor(x, g, B, so, psi);
+    site_term(H, g, B, so, tw, psi, tmp);
+    hop_global<R, S>(U, x, g, B, so, me_o, tmp);
+    load_spinor(b, g, B, so, r_o);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      r_o[c] -= tmp[c];
+      ro[c * g.half + i] = r_o[c];
+    }
+    // t_o = T_oo^{-1} r_o
+    site_inv(H, Minv, g, B, so, tw, r_o, tmp);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) od[c * g.half + i] = tmp[c];
+  }
+  __syncthreads();
+  // rho = r_e - D_eo t_o   (the hop already carries the -1/2)
+  cx<R> rho[12], eps[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
+  hop_block_lds<R, S>(U, g, B, se, me_e, od, g.half, tmp);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    rho[c] = re[c] - tmp[c];
+    eps[c] = mk<R>(0, 0);
+  }
+  const int lane = i & 63, wv = i >> 6, nw = (g.half + 63) >> 6;
+  for (int k = 0; k < n_mr; ++k) {
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ev[c * g.half + i] = rho[c];
+    __syncthreads();
+    // odd: w = T_oo^{-1} D_oe rho
+#pragma unroll
+    for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
+    hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, tmp);
+    site_inv(H, Minv, g, B, so, tw, tmp, psi);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) od[c * g.half + i] = psi[c];
+    __syncthreads();
+    // even: q = T_ee rho - D_eo w
+    cx<R> q[12];
+    site_term(H, g, B, se, tw, rho, q);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
+    hop_block_lds<R, S>(U, g, B, se, me_e, od, g.half, tmp);
+    double qr_re = 0, qr_im = 0, qq = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      q[c] -= tmp[c];
+      qr_re += (double)q[c].re * rho[c].re + (double)q[c].im * rho[c].im;
+      qr_im += (double)q[c].re * rho[c].im - (double)q[c].im * rho[c].re;
+      qq += (double)q[c].re * q[c].re + (double)q[c].im * q[c].im;
+    }
+    {
+      int nact = min(64, (int)blockDim.x - wv * 64);
+      qr_re = wave_sum_n(qr_re, nact);
+      qr_im = wave_sum_n(qr_im, nact);
+      qq = wave_sum_n(qq, nact);
+    }
+    if (lane == 0) {
+      red[0][wv] = qr_re;
+      red[1][wv] = qr_im;
+      red[2][wv] = qq;
+    }
+    __syncthreads();
+    double sr = 0, si = 0, sq = 0;
+    for (int v = 0; v < nw; ++v) {
+      sr += red[0][v];
+      si += red[1][v];
+      sq += red[2][v];
+    }
+    cx<R> alpha = mk<R>(0, 0);
+    if (sq > 0) alpha = mk<R>((R)(sr / sq), (R)(si / sq));
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      eps[c] += alpha * rho[c];
+      rho[c] -= alpha * q[c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 12; ++c) ev[c * g.half + i] = eps[c];
+  __syncthreads();
+  // odd reconstruction e_o = T_oo^{-1} (r_o - D_oe e_e)
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
+  hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, tmp);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] = ro[c * g.half + i] - tmp[c];
+  site_inv(H, Minv, g, B, so, tw, psi, tmp);
+  // x += e
+  load_spinor(x, g, B, se, psi);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] += eps[c];
+  store_spinor(x, g, B, se, psi);
+  load_spinor(x, g, B, so, psi);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] += tmp[c];
+  store_spinor(x, g, B, so, psi);
+}
+
+template <class R, class S>
+void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+                cx<R>* x, int n_mr, hipStream_t st) {
+  size_t sm = 3 * 12 * (size_t)g.half * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_sap<R, S>), dim3(g.nblocks / 2), dim3(g.half), sm, st, g, colour,
+                     (const typename store_traits<S>::elem*)U, H, Minv, (R)tw, b, x, n_mr);
+}
+template void launch_sap<double, double>(const Geom&, int, const void*, const double*, const double*, double,
+                                         const cx<double>*, cx<double>*, int, hipStream_t);
+template void launch_sap<float, float>(const Geom&, int, const void*, const float*, const float*, double,
+                                       const cx<float>*, cx<float>*, int, hipStream_t);
+template void launch_sap<float, f16>(const Geom&, int, const void*, const float*, const float*, double,
+                                        const cx<float>*, cx<float>*, int, hipStream_t);
+template void launch_sap<float, bf16>(const Geom&, int, const void*, const float*, const float*, double,
+                                                const cx<float>*, cx<float>*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// host TZYX lexicographic <-> block layout
+template <class R>
+__global__ void k_spinor_from_lex(Geom g, const cx<double>* __restrict__ lex, cx<R>* __restrict__ out, int ncomp) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  int x[4];
+  site_coords(g, B, s, x);
+  long li = lex_index(g, x);
+  for (int c = 0; c < ncomp; ++c) {
+    cx<double> v = lex[li * ncomp + c];
+    out[((long)B * ncomp + c) * g.bs + s] = mk<R>((R)v.re, (R)v.im);
+  }
+}
+
+template <class R>
+__global__ void k_spinor_to_lex(Geom g, const cx<R>* __restrict__ in, cx<double>* __restrict__ lex, int ncomp) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  int x[4];
+  site_coords(g, B, s, x);
+  long li = lex_index(g, x);
+  for (int c = 0; c < ncomp; ++c) {
+    cx<R> v = in[((long)B * ncomp + c) * g.bs + s];
+    lex[li * ncomp + c] = mk<double>(v.re, v.im);
+  }
+}
+
+template <class R>
+void launch_from_lex(const Geom& g, const cx<double>* lex, cx<R>* out, int ncomp, hipStream_t st) {
+  hipLaunchKernelGGL(k_spinor_from_lex<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g, lex, out, ncomp);
+}
+template <class R>
+void launch_to_lex(const Geom& g, const cx<R>* in, cx<double>* lex, int ncomp, hipStream_t st) {
+  hipLaunchKernelGGL(k_spinor_to_lex<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g, in, lex, ncomp);
+}
+template void launch_from_lex<double>(const Geom&, const cx<double>*, cx<double>*, int, hipStream_t);
+template void launch_from_lex<float>(const Geom&, const cx<double>*, cx<float>*, int, hipStream_t);
+template void launch_to_lex<double>(const Geom&, const cx<double>*, cx<double>*, int, hipStream_t);
+template void launch_to_lex<float>(const Geom&, const cx<float>*, cx<double>*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// clover term from the links: per site the six F_{mu nu} (mu<nu) from the four
+// same-orientation plaquette leaves, then the two chirality blocks
+// A_chi = (i c_sw / 2) sum_{mu<nu} sigma^chi_{mu nu} (x) F_{mu nu}; stored as
+// H = (m0+4) + A, packed Hermitian.
+struct Mat3 {
+  cx<double> m[9];
+};
+__device__ __forceinline__ Mat3 mul(const Mat3& a, const Mat3& b) {
+  Mat3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cx<double> acc = mk(0.0, 0.0);
+      for (int k = 0; k < 3; ++k) cmac(acc, a.m[3 * i + k], b.m[3 * k + j]);
+      r.m[3 * i + j] = acc;
+    }
+  return r;
+}
+__device__ __forceinline__ Mat3 dagm(const Mat3& a) {
+  Mat3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) r.m[3 * i + j] = conj(a.m[3 * j + i]);
+  return r;
+}
+
+__device__ __forceinline__ Mat3 link_at(const cx<double>* U, const Geom& g, const int x0[4], int d0, int s0, int d1,
+                                        int s1, int mu) {
+  int x[4] = {x0[0], x0[1], x0[2], x0[3]};
+  if (s0) x[d0] = (x[d0] + s0 + g.L[d0]) % g.L[d0];
+  if (s1) x[d1] = (x[d1] + s1 + g.L[d1]) % g.L[d1];
+  int B, s;
+  coords_site(g, x, B, s);
+  Mat3 r;
+  long base = ((long)(B * 4 + mu) * 9) * g.bs + s;
+  for (int k = 0; k < 9; ++k) r.m[k] = U[base + (long)k * g.bs];
+  return r;
+}
+
+// sigma^chi_{mu nu} for mu<nu, pair index p (01,02,03,12,13,23), 2x2 per chirality
+__constant__ double c_sigma[6][2][4][2];
+
+__global__ void k_clover(Geom g, const cx<double>* __restrict__ U, double csw, double diag, double* __restrict__ H) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  int x[4];
+  site_coords(g, B, s, x);
+  cx<double> A[2][6][6];
+  for (int c = 0; c < 2; ++c)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) A[c][i][j] = mk(0.0, 0.0);
+  int p = 0;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int nu = mu + 1; nu < 4; ++nu, ++p) {
+      Mat3 Umx = link_at(U, g, x, mu, 0, nu, 0, mu), Unx = link_at(U, g, x, mu, 0, nu, 0, nu);
+      // leaf 1: U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+      Mat3 Q = mul(mul(Umx, link_at(U, g, x, mu, 1, nu, 0, nu)),
+                   mul(dagm(link_at(U, g, x, mu, 0, nu, 1, mu)), dagm(Unx)));
+      // leaf 2: U_nu(x) U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
+      Mat3 L2 = mul(mul(Unx, dagm(link_at(U, g, x, mu, -1, nu, 1, mu))),
+                    mul(dagm(link_at(U, g, x, mu, -1, nu, 0, nu)), link_at(U, g, x, mu, -1, nu, 0, mu)));
+      // leaf 3: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_nu(x-nu)
+      Mat3 L3 = mul(mul(dagm(link_at(U, g, x, mu, -1, nu, 0, mu)), dagm(link_at(U, g, x, mu, -1, nu, -1, nu))),
+                    mul(link_at(U, g, x, mu, -1, nu, -1, mu), link_at(U, g, x, mu, 0, nu, -1, nu)));
+      // leaf 4: U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^dag
+      Mat3 L4 = mul(mul(dagm(link_at(U, g, x, mu, 0, nu, -1, nu)), link_at(U, g, x, mu, 0, nu, -1, mu)),
+                    mul(link_at(U, g, x, mu, 1, nu, -1, nu), dagm(Umx)));
+      for (int k = 0; k < 9; ++k) Q.m[k] = Q.m[k] + L2.m[k] + L3.m[k] + L4.m[k];
+      // F = (Q - Q^dag)/8;  contribution (i c_sw/2) sigma (x) F
+      cx<double> F[9];
+      for (int a = 0; a < 3; ++a)
+        for (int bb = 0; bb < 3; ++bb) F[3 * a + bb] = 0.125 * (Q.m[3 * a + bb] - conj(Q.m[3 * bb + a]));
+      for (int c = 0; c < 2; ++c)
+        for (int s1 = 0; s1 < 2; ++s1)
+          for (int s2 = 0; s2 < 2; ++s2) {
+            cx<double> sg = mk(c_sigma[p][c][2 * s1 + s2][0], c_sigma[p][c][2 * s1 + s2][1]);
+            cx<double> f = (0.5 * csw) * times_i(sg);
+            for (int a = 0; a < 3; ++a)
+              for (int bb = 0; bb < 3; ++bb) A[c][3 * s1 + a][3 * s2 + bb] += f * F[3 * a + bb];
+          }
+    }
+  double* hp = H + (long)B * 72 * g.bs + s;
+  for (int c = 0; c < 2; ++c) {
+    double* h = hp + 36L * c * g.bs;
+    for (int i = 0; i < 6; ++i) h[(long)i * g.bs] = diag + A[c][i][i].re;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        int k = 6 + 2 * herm_idx(i, j);
+        cx<double> v = 0.5 * (A[c][i][j] + conj(A[c][j][i]));
+        h[(long)k * g.bs] = v.re;
+        h[(long)(k + 1) * g.bs] = v.im;
+      }
+  }
+}
+
+void set_sigma_table(const double* tab /* [6][2][4][2] */) {
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_sigma), tab, sizeof(double) * 6 * 2 * 4 * 2));
+}
+
+void launch_clover(const Geom& g, const cx<double>* U, double csw, double diag, double* H, hipStream_t st) {
+  hipLaunchKernelGGL(k_clover, dim3((g.V + 127) / 128), dim3(128), 0, st, g, U, csw, diag, H);
+}
+
+// user-supplied clover term [V][2][6][6] (lexicographic) -> packed H = diag + A
+__global__ void k_clover_from_lex(Geom g, const cx<double>* __restrict__ lex, double diag, double* __restrict__ H) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  int x[4];
+  site_coords(g, B, s, x);
+  long li = lex_index(g, x);
+  double* hp = H + (long)B * 72 * g.bs + s;
+  for (int c = 0; c < 2; ++c) {
+    const cx<double>* a = lex + (li * 2 + c) * 36;
+    double* h = hp + 36L * c * g.bs;
+    for (int i = 0; i < 6; ++i) h[(long)i * g.bs] = diag + a[6 * i + i].re;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        int k = 6 + 2 * herm_idx(i, j);
+        cx<double> v = 0.5 * (a[6 * i + j] + conj(a[6 * j + i]));
+        h[(long)k * g.bs] = v.re;
+        h[(long)(k + 1) * g.bs] = v.im;
+      }
+  }
+}
+void launch_clover_from_lex(const Geom& g, const cx<double>* lex, double diag, double* H, hipStream_t st) {
+  hipLaunchKernelGGL(k_clover_from_lex, dim3((g.V + 127) / 128), dim3(128), 0, st, g, lex, diag, H);
+}
+
+// packed H (without m0+4) back to [V][2][6][6] lexicographic
+__global__ void k_clover_to_lex(Geom g, const double* __restrict__ H, double diag, cx<double>* __restrict__ lex) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  int x[4];
+  site_coords(g, B, s, x);
+  long li = lex_index(g, x);
+  const double* hp = H + (long)B * 72 * g.bs + s;
+  for (int c = 0; c < 2; ++c) {
+    cx<double>* a = lex + (li * 2 + c) * 36;
+    const double* h = hp + 36L * c * g.bs;
+    for (int i = 0; i < 6; ++i) a[6 * i + i] = mk(h[(long)i * g.bs] - diag, 0.0);
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        int k = 6 + 2 * herm_idx(i, j);
+        cx<double> v = mk(h[(long)k * g.bs], h[(long)(k + 1) * g.bs]);
+        a[6 * i + j] = v;
+        a[6 * j + i] = conj(v);
+      }
+  }
+}
+void launch_clover_to_lex(const Geom& g, const double* H, double diag, cx<double>* lex, hipStream_t st) {
+  hipLaunchKernelGGL(k_clover_to_lex, dim3((g.V + 127) / 128), dim3(128), 0, st, g, H, diag, lex);
+}
+
+// links [V][4][3][3] lexicographic -> block layout FP64
+__global__ void k_links_from_lex(Geom g, const cx<double>* __restrict__ lex, cx<double>* __restrict__ U) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  int x[4];
+  site_coords(g, B, s, x);
+  long li = lex_index(g, x);
+  for (int mu = 0; mu < 4; ++mu)
+    for (int k = 0; k < 9; ++k) U[((long)(B * 4 + mu) * 9 + k) * g.bs + s] = lex[(li * 4 + mu) * 9 + k];
+}
+void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, hipStream_t st) {
+  hipLaunchKernelGGL(k_links_from_lex, dim3((g.V + 255) / 256), dim3(256), 0, st, g, lex, U);
+}
+
+// ---------------------------------------------------------------------------
+// odd-site inverse factor M_chi = (H_chi^2 + tw^2)^{-1} (Hermitian positive
+// definite), by Cholesky; stored packed like H.
+__global__ void k_odd_inverse(Geom g, const double* __restrict__ H, double tw, double* __restrict__ M) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long nodd = (long)g.nblocks * g.half;
+  if (gid >= nodd) return;
+  int B = (int)(gid / g.half), io = (int)(gid - (long)B * g.half);
+  int s = g.half + io;
+  const double* hp = H + (long)B * 72 * g.bs + s;
+  for (int c = 0; c < 2; ++c) {
+    cx<double> h[6][6], G[6][6], L[6][6], Inv[6][6];
+    const double* hc = hp + 36L * c * g.bs;
+    for (int i = 0; i < 6; ++i) h[i][i] = mk(hc[(long)i * g.bs], 0.0);
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        int k = 6 + 2 * herm_idx(i, j);
+        h[i][j] = mk(hc[(long)k * g.bs], hc[(long)(k + 1) * g.bs]);
+        h[j][i] = conj(h[i][j]);
+      }
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        cx<double> acc = mk(i == j ? tw * tw : 0.0, 0.0);
+        for (int k = 0; k < 6; ++k) cmac(acc, h[i][k], h[k][j]);
+        G[i][j] = acc;
+      }
+    // Cholesky G = L L^dag
+    for (int j = 0; j < 6; ++j) {
+      double d = G[j][j].re;
+      for (int k = 0; k < j; ++k) d -= norm2(L[j][k]);
+      d = sqrt(d);
+      L[j][j] = mk(d, 0.0);
+      for (int i = j + 1; i < 6; ++i) {
+        cx<double> acc = G[i][j];
+        for (int k = 0; k < j; ++k) acc = acc - L[i][k] * conj(L[j][k]);
+        L[i][j] = (1.0 / d) * acc;
+      }
+      for (int i = 0; i < j; ++i) L[i][j] = mk(0.0, 0.0);
+    }
+    // inverse: solve L L^dag X = I column by column
+    for (int col = 0; col < 6; ++col) {
+      cx<double> y[6];
+      for (int i = 0; i < 6; ++i) {
+        cx<double> acc = mk(i == col ? 1.0 : 0.0, 0.0);
+        for (int k = 0; k < i; ++k) acc = acc - L[i][k] * y[k];
+        y[i] = (1.0 / L[i][i].re) * acc;
+      }
+      for (int i = 5; i >= 0; --i) {
+        cx<double> acc = y[i];
+        for (int k = i + 1; k < 6; ++k) acc = acc - conj(L[k][i]) * Inv[k][col];
+        Inv[i][col] = (1.0 / L[i][i].re) * acc;
+      }
+    }
+    double* mp = M + (long)B * 72 * g.half + io + 36L * c * g.half;
+    for (int i = 0; i < 6; ++i) mp[(long)i * g.half] = Inv[i][i].re;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        int k = 6 + 2 * herm_idx(i, j);
+        cx<double> v = 0.5 * (Inv[i][j] + conj(Inv[j][i]));
+        mp[(long)k * g.half] = v.re;
+        mp[(long)(k + 1) * g.half] = v.im;
+      }
+  }
+}
+void launch_odd_inverse(const Geom& g, const double* H, double tw, double* M, hipStream_t st) {
+  long n = (long)g.nblocks * g.half;
+  hipLaunchKernelGGL(k_odd_inverse, dim3((n + 127) / 128), dim3(128), 0, st, g, H, tw, M);
+}
+
+// ---------------------------------------------------------------------------
+// restriction P^dag on the fine level: one workgroup per block (= aggregate),
+// one thread per slot; output r_c[site][s*Nv + i].
+template <class R>
+__global__ void __launch_bounds__(256) k_restrict_fine(Geom g, int Nv, const cx<R>* __restrict__ Q, long vstride,
+                                                       const cx<R>* __restrict__ r, const int* __restrict__ f2c,
+                                                       cx<R>* __restrict__ rc) {
+  __shared__ double red[16][4][2];
+  int B = blockIdx.x, s = threadIdx.x;
+  int lane = s & 63, wv = s >> 6, nw = (g.bs + 63) >> 6;
+  cx<R> rv[12];
+  load_spinor(r, g, B, s, rv);
+  int site = f2c[B];
+  for (int i0 = 0; i0 < Nv; i0 += 8) {
+    int ni = min(8, Nv - i0);
+    double acc[8][2][2];
+    for (int ii = 0; ii < 8; ++ii) {
+      acc[ii][0][0] = acc[ii][0][1] = acc[ii][1][0] = acc[ii][1][1] = 0.0;
+      if (ii < ni) {
+        const cx<R>* q = Q + (long)(i0 + ii) * vstride;
+        long base = (long)B * 12 * g.bs + s;
+        for (int c = 0; c < 12; ++c) {
+          cx<R> qv = q[base + (long)c * g.bs];
+          int h = c / 6;
+          acc[ii][h][0] += (double)qv.re * rv[c].re + (double)qv.im * rv[c].im;
+          acc[ii][h][1] += (double)qv.re * rv[c].im - (double)qv.im * rv[c].re;
+        }
+      }
+    }
+    for (int ii = 0; ii < 8; ++ii)
+      for (int h = 0; h < 2; ++h)
+        for (int p = 0; p < 2; ++p) {
+          double v = wave_sum_n(acc[ii][h][p], min(64, g.bs - wv * 64));
+          if (lane == 0) red[2 * ii + h][wv][p] = v;
+        }
+    __syncthreads();
+    if (s < 2 * ni) {
+      int ii = s >> 1, h = s & 1;
+      double re = 0, im = 0;
+      for (int v = 0; v < nw; ++v) {
+        re += red[s][v][0];
+        im += red[s][v][1];
+      }
+      rc[(long)site * 2 * Nv + h * Nv + i0 + ii] = mk<R>((R)re, (R)im);
+    }
+    __syncthreads();
+  }
+}
+
+template <class R>
+void launch_restrict_fine(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* r, const int* f2c,
+                          cx<R>* rc, hipStream_t st) {
+  hipLaunchKernelGGL(k_restrict_fine<R>, dim3(g.nblocks), dim3(g.bs), 0, st, g, Nv, Q, vstride, r, f2c, rc);
+}
+template void launch_restrict_fine<double>(const Geom&, int, const cx<double>*, long, const cx<double>*,
+                                           const int*, cx<double>*, hipStream_t);
+template void launch_restrict_fine<float>(const Geom&, int, const cx<float>*, long, const cx<float>*, const int*,
+                                          cx<float>*, hipStream_t);
+
+// prolongation P: x (+)= sum_i Q_i e_c(s(comp)*Nv + i)
+template <class R>
+__global__ void __launch_bounds__(256) k_prolong_fine(Geom g, int Nv, const cx<R>* __restrict__ Q, long vstride,
+                                                      const cx<R>* __restrict__ ec, const int* __restrict__ f2c,
+                                                      cx<R>* __restrict__ x, int accumulate) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  const cx<R>* e = ec + (long)f2c[B] * 2 * Nv;
+  cx<R> acc[12];
+  if (accumulate) load_spinor(x, g, B, s, acc);
+  else
+    for (int c = 0; c < 12; ++c) acc[c] = mk<R>(0, 0);
+  long base = (long)B * 12 * g.bs + s;
+  for (int i = 0; i < Nv; ++i) {
+    cx<R> e0 = e[i], e1 = e[Nv + i];
+    const cx<R>* q = Q + (long)i * vstride + base;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) cmac(acc[c], q[(long)c * g.bs], e0);
+#pragma unroll
+    for (int c = 6; c < 12; ++c) cmac(acc[c], q[(long)c * g.bs], e1);
+  }
+  store_spinor(x, g, B, s, acc);
+}
+template <class R>
+void launch_prolong_fine(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* ec, const int* f2c,
+                         cx<R>* x, int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_fine<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g, Nv, Q, vstride, ec, f2c, x,
+                     accumulate);
+}
+template void launch_prolong_fine<double>(const Geom&, int, const cx<double>*, long, const cx<double>*, const int*,
+                                          cx<double>*, int, hipStream_t);
+template void launch_prolong_fine<float>(const Geom&, int, const cx<float>*, long, const cx<float>*, const int*,
+                                         cx<float>*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// block orthonormalisation (classical Gram-Schmidt, twice) per aggregate half,
+// FP64 arithmetic; columns in the order v_1..v_Nv, diag(R) = norms (real > 0).
+// One workgroup per (block, half), one thread per slot (6 rows each).
+template <class RO>
+__global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<double>* __restrict__ V, long vstride,
+                                                 RO* __restrict__ Qout_raw, long qstride, int* __restrict__ fail) {
+  cx<RO>* Qout = reinterpret_cast<cx<RO>*>(Qout_raw);
+  __shared__ double red[32][4][2];
+  __shared__ double dsh[32][2];
+  int B = blockIdx.x >> 1, h = blockIdx.x & 1;
+  int s = threadIdx.x, lane = s & 63, wv = s >> 6, nw = (g.bs + 63) >> 6;
+  long base = (long)B * 12 * g.bs + (long)(6 * h) * g.bs + s;
+  auto reduce = [&](double a, double b, int slot) {
+    int nact = min(64, g.bs - wv * 64);
+    a = wave_sum_n(a, nact);
+    b = wave_sum_n(b, nact);
+    if (lane == 0) {
+      red[slot][wv][0] = a;
+      red[slot][wv][1] = b;
+    }
+  };
+  for (int i = 0; i < Nv; ++i) {
+    cx<double> v[6];
+    for (int c = 0; c < 6; ++c) v[c] = V[(long)i * vstride + base + (long)c * g.bs];
+    double n0 = 0;
+    for (int c = 0; c < 6; ++c) n0 += norm2(v[c]);
+    reduce(n0, 0.0, 0);
+    __syncthreads();
+    double nrm0 = 0;
+    for (int w = 0; w < nw; ++w) nrm0 += red[0][w][0];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < i; ++j) {
+        double ar = 0, ai = 0;
+        for (int c = 0; c < 6; ++c) {
+          cx<RO> q = Qout[(long)j * qstride + base + (long)c * g.bs];
+          ar += (double)q.re * v[c].re + (double)q.im * v[c].im;
+          ai += (double)q.re * v[c].im - (double)q.im * v[c].re;
+        }
+        reduce(ar, ai, j);
+      }
+      __syncthreads();
+      if (s < i) {
+        double re = 0, im = 0;
+        for (int w = 0; w < nw; ++w) {
+          re += red[s][w][0];
+          im += red[s][w][1];
+        }
+        dsh[s][0] = re;
+        dsh[s][1] = im;
+      }
+      __syncthreads();
+      for (int j = 0; j < i; ++j) {
+        cx<double> d = mk(dsh[j][0], dsh[j][1]);
+        for (int c = 0; c < 6; ++c) {
+          cx<RO> q = Qout[(long)j * qstride + base + (long)c * g.bs];
+          v[c] = v[c] - d * mk<double>(q.re, q.im);
+        }
+      }
+      __syncthreads();
+    }
+    double n1 = 0;
+    for (int c = 0; c < 6; ++c) n1 += norm2(v[c]);
+    reduce(n1, 0.0, 0);
+    __syncthreads();
+    double nrm = 0;
+    for (int w = 0; w < nw; ++w) nrm += red[0][w][0];
+    __syncthreads();
+    if (!(nrm > 1e-24 * nrm0) && s == 0) atomicOr(fail, 1);
+    double inv = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
+    for (int c = 0; c < 6; ++c) {
+      cx<double> q = inv * v[c];
+      Qout[(long)i * qstride + base + (long)c * g.bs] = mk<RO>((RO)q.re, (RO)q.im);
+    }
+  }
+}
+template <class RO>
+void launch_qr_fine(const Geom& g, int Nv, const cx<double>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_qr_fine<RO>, dim3(2 * g.nblocks), dim3(g.bs), 0, st, g, Nv, V, vstride, (RO*)Q, qstride,
+                     fail);
+}
+template void launch_qr_fine<double>(const Geom&, int, const cx<double>*, long, cx<double>*, long, int*, hipStream_t);
+template void launch_qr_fine<float>(const Geom&, int, const cx<double>*, long, cx<float>*, long, int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Galerkin assembly of the first coarse operator, FP64.  One workgroup per
+// (block, kind): kind 0 = self block (site terms Q^dag H Q and the links inside
+// the block), kind 1+mu = forward block for the links leaving the block across
+// its upper mu face.  Output blocks column-major: element (k,l) at l*n + k.
+// The self kind also writes X (internal forward links) for the Gamma5 fix-up
+// S += Gamma5 X^dag Gamma5 done by k_self_fixup.
+template <class RQ>
+__global__ void __launch_bounds__(256) k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U,
+                                                       const double* __restrict__ H,
+                                                       const cx<RQ>* __restrict__ Q, long qstride,
+                                                       const int* __restrict__ f2c, cx<double>* __restrict__ Dc,
+                                                       cx<double>* __restrict__ Xs) {
+  const int n = 2 * Nv;
+  __shared__ cx<double> qx[32 * 12];   // Q_i(x)[c]
+  __shared__ cx<double> W[64 * 12];    // W[l][c]
+  int B = blockIdx.x / 5, kind = blockIdx.x % 5;
+  int t = threadIdx.x;
+  const int nent = n * n;
+  cx<double> accS[16], accX[16];
+  for (int m = 0; m < 16; ++m) accS[m] = accX[m] = mk(0.0, 0.0);
+  int bc[4];
+  block_coords(g, B, bc);
+  for (int sx = 0; sx < g.bs; ++sx) {
+    int l[4];
+    slot_local(g, sx, l);
+    if (kind > 0 && l[kind - 1] != g.b[kind - 1] - 1) continue;
+    __syncthreads();
+    for (int e = t; e < Nv * 12; e += 256) {
+      int i = e / 12, c = e % 12;
+      cx<RQ> v = Q[(long)i * qstride + ((long)B * 12 + c) * g.bs + sx];
+      qx[e] = mk<double>(v.re, v.im);
+    }
+    __syncthreads();
+    if (kind == 0) {
+      // site term W[l] = H_{half(l)} Q_{i_l}(x) on half(l), zero elsewhere
+      const double* hp = H + (long)B * 72 * g.bs + sx;
+      for (int e = t; e < n * 12; e += 256) {
+        int col = e / 12, c = e % 12;
+        int hcol = col >= Nv ? 1 : 0, i = col - hcol * Nv;
+        cx<double> acc = mk(0.0, 0.0);
+        if (c / 6 == hcol) {
+          const double* h = hp + 36L * hcol * g.bs;
+          int r = c % 6;
+          for (int j = 0; j < 6; ++j) {
+            cx<double> hv;
+            if (j == r) hv = mk(h[(long)r * g.bs], 0.0);
+            else if (j > r) {
+              int k = 6 + 2 * herm_idx(r, j);
+              hv = mk(h[(long)k * g.bs], h[(long)(k + 1) * g.bs]);
+            } else {
+              int k = 6 + 2 * herm_idx(j, r);
+              hv = mk(h[(long)k * g.bs], -h[(long)(k + 1) * g.bs]);
+            }
+            cmac(acc, hv, qx[i * 12 + 6 * hcol + j]);
+          }
+        }
+        W[col * 12 + c] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        int e = t + 256 * m;
+        if (e < nent) {
+          int col = e / n, row = e % n;
+          int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
+          cx<double> acc = accS[m];
+          for (int c = 0; c < 6; ++c) cjmac(acc, qx[ir * 12 + 6 * hr + c], W[col * 12 + 6 * hr + c]);
+          accS[m] = acc;
+        }
+      }
+    }
+    // links: kind 0 -> internal forward links of every direction, kind 1+mu -> the face link
+    for (int mu = 0; mu < 4; ++mu) {
+      bool take = (kind == 0) ? (l[mu] + 1 < g.b[mu]) : (mu == kind - 1);
+      if (!take) continue;
+      int By, sy;
+      {
+        SiteNbr me;
+        for (int d = 0; d < 4; ++d) {
+          me.bc[d] = bc[d];
+          me.l[d] = l[d];
+        }
+        nbr_of(g, me, mu, +1, By, sy);
+      }
+      __syncthreads();
+      // W[col] = -1/2 (1-g_mu) U_mu(x) Q_col(y)
+      if (t < n) {
+        int col = t, hcol = col >= Nv ? 1 : 0, i = col - hcol * Nv;
+        cx<double> psi[12], out[12], u[9];
+        for (int c = 0; c < 12; ++c) {
+          psi[c] = mk(0.0, 0.0);
+          out[c] = mk(0.0, 0.0);
+        }
+        for (int c = 0; c < 6; ++c) {
+          cx<RQ> v = Q[(long)i * qstride + ((long)By * 12 + 6 * hcol + c) * g.bs + sy];
+          psi[6 * hcol + c] = mk<double>(v.re, v.im);
+        }
+        long ub = ((long)(B * 4 + mu) * 9) * g.bs + sx;
+        for (int k = 0; k < 9; ++k) u[k] = U[ub + (long)k * g.bs];
+        hop_accum<0>(mu, psi, u, out);
+        for (int c = 0; c < 12; ++c) W[col * 12 + c] = out[c];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        int e = t + 256 * m;
+        if (e < nent) {
+          int col = e / n, row = e % n;
+          int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
+          cx<double> acc = mk(0.0, 0.0);
+          for (int c = 0; c < 6; ++c) cjmac(acc, qx[ir * 12 + 6 * hr + c], W[col * 12 + 6 * hr + c]);
+          if (kind == 0) accX[m] += acc;
+          else accS[m] += acc;
+        }
+      }
+    }
+  }
+  long site = f2c[B];
+  cx<double>* out = Dc + ((long)site * 5 + kind) * nent;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    int e = t + 256 * m;
+    if (e < nent) {
+      out[e] = accS[m] + accX[m];
+      if (kind == 0) Xs[(long)site * nent + e] = accX[m];
+    }
+  }
+}
+template <class RQ>
+void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, const cx<RQ>* Q, long qstride,
+                          const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st) {
+  hipLaunchKernelGGL(k_assemble_fine<RQ>, dim3(5 * g.nblocks), dim3(256), 0, st, g, Nv, U, H, Q, qstride, f2c, Dc,
+                     Xs);
+}
+template void launch_assemble_fine<double>(const Geom&, int, const cx<double>*, const double*, const cx<double>*,
+                                           long, const int*, cx<double>*, cx<double>*, hipStream_t);
+template void launch_assemble_fine<float>(const Geom&, int, const cx<double>*, const double*, const cx<float>*,
+                                          long, const int*, cx<double>*, cx<double>*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// precision copies of operator data
+template <class S>
+__global__ void k_cvt_cx(long n, const cx<double>* __restrict__ in, typename store_traits<S>::elem* __restrict__ out) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = st_cvt<S, double>(in[i]);
+}
+template <class S>
+void launch_cvt_cx(long n, const cx<double>* in, void* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_cvt_cx<S>, dim3((n + 255) / 256), dim3(256), 0, st, n, in,
+                     (typename store_traits<S>::elem*)out);
+}
+template void launch_cvt_cx<double>(long, const cx<double>*, void*, hipStream_t);
+template void launch_cvt_cx<float>(long, const cx<double>*, void*, hipStream_t);
+template void launch_cvt_cx<f16>(long, const cx<double>*, void*, hipStream_t);
+template void launch_cvt_cx<bf16>(long, const cx<double>*, void*, hipStream_t);
+
+__global__ void k_cvt_real(long n, const double* __restrict__ in, float* __restrict__ out) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+void launch_cvt_real(long n, const double* in, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_cvt_real, dim3((n + 255) / 256), dim3(256), 0, st, n, in, out);
+}
+
+}  // namespace ddamg

@@ -1,0 +1,129 @@
+// Launch wrappers of every kernel of the library (host-callable).
+#pragma once
+#include "common.hpp"
+
+namespace ddamg {
+
+// ---- device helpers shared by the kernel files -------------------------------
+#ifdef __HIPCC__
+// Sum over the active lanes 0..nact-1 of a wavefront; the full sum ends up in
+// lane 0 (xor butterfly that skips partners beyond the active range).
+template <class T>
+__device__ __forceinline__ T wave_sum_n(T v, int nact) {
+  int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_xor(v, off, 64);
+    if ((lane ^ off) < nact) v += o;
+  }
+  return v;
+}
+#endif
+
+// coarse-level geometry as seen by the kernels
+struct CGeom {
+  int n;           // complex components per site (2 Nv of the level above)
+  int nsites;      // sites
+  int neven;       // even sites (stored first)
+  const int* nbr;  // [nsites][8]: +T +Z +Y +X -T -Z -Y -X
+};
+
+// ---------------------------------------------------------------- fine level
+template <class R, class S>
+void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<R>* in, cx<R>* out, hipStream_t st);
+template <class R, class S>
+void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+                cx<R>* x, int n_mr, hipStream_t st);
+template <class R>
+void launch_from_lex(const Geom& g, const cx<double>* lex, cx<R>* out, int ncomp, hipStream_t st);
+template <class R>
+void launch_to_lex(const Geom& g, const cx<R>* in, cx<double>* lex, int ncomp, hipStream_t st);
+void set_sigma_table(const double* tab);
+void launch_clover(const Geom& g, const cx<double>* U, double csw, double diag, double* H, hipStream_t st);
+void launch_clover_from_lex(const Geom& g, const cx<double>* lex, double diag, double* H, hipStream_t st);
+void launch_clover_to_lex(const Geom& g, const double* H, double diag, cx<double>* lex, hipStream_t st);
+void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, hipStream_t st);
+void launch_odd_inverse(const Geom& g, const double* H, double tw, double* M, hipStream_t st);
+template <class R>
+void launch_restrict_fine(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* r, const int* f2c,
+                          cx<R>* rc, hipStream_t st);
+template <class R>
+void launch_prolong_fine(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* ec, const int* f2c,
+                         cx<R>* x, int accumulate, hipStream_t st);
+template <class RO>
+void launch_qr_fine(const Geom& g, int Nv, const cx<double>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
+                    hipStream_t st);
+template <class RQ>
+void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, const cx<RQ>* Q, long qstride,
+                          const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st);
+template <class S>
+void launch_cvt_cx(long n, const cx<double>* in, void* out, hipStream_t st);
+void launch_cvt_real(long n, const double* in, float* out, hipStream_t st);
+
+// -------------------------------------------------------------- coarse levels
+// D_c blocks: [site][5][n][n] column-major (self without twist, forward T,Z,Y,X)
+template <class R, class S>
+void launch_coarse_apply(const CGeom& cg, const void* D, double tw, const cx<R>* in, cx<R>* out, hipStream_t st);
+// r = b - D x
+template <class R, class S>
+void launch_coarse_residual(const CGeom& cg, const void* D, double tw, const cx<R>* b, const cx<R>* x, cx<R>* r,
+                            hipStream_t st);
+// SAP colour sweep with block MR (no odd-even): x += e on blocks of the colour
+template <class R, class S>
+void launch_coarse_sap(const CGeom& cg, const void* D, double tw, int nblk_colour, int bsz, const int* blk_sites,
+                       const int* blk_nbr, const cx<R>* r, cx<R>* x, int n_mr, hipStream_t st);
+// restriction / prolongation between coarse levels
+template <class R>
+void launch_restrict_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<R>* Q, long qstride,
+                            const cx<R>* r, cx<R>* rc, hipStream_t st);
+template <class R>
+void launch_prolong_coarse(int n, int Nv, int nsites, const int* site_agg, const cx<R>* Q, long qstride,
+                           const cx<R>* ec, cx<R>* x, int accumulate, hipStream_t st);
+template <class RO>
+void launch_qr_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<double>* V, long vstride,
+                      cx<RO>* Q, long qstride, int* fail, hipStream_t st);
+template <class RQ>
+void launch_assemble_coarse(const CGeom& cg, int Nv, int nagg, const int ab[4], const int* agg_sites,
+                            const cx<double>* D, const cx<RQ>* Q, long qstride, cx<double>* Dn, cx<double>* Xs,
+                            hipStream_t st);
+void launch_self_fixup(int n, int nsites, cx<double>* D, const cx<double>* Xs, hipStream_t st);
+// inverse of the site blocks (S + i tw Gamma5) on odd sites of the coarsest level
+template <class R>
+void launch_coarse_odd_inverse(const CGeom& cg, const cx<double>* D, double tw, cx<double>* scratch, cx<R>* Minv,
+                               hipStream_t st);
+// odd-even Schur pieces on the coarsest level
+template <class R, class S>
+void launch_coarse_hop_inv_odd(const CGeom& cg, const void* D, const cx<R>* Minv, const cx<R>* in, cx<R>* out,
+                               int unused, hipStream_t st);
+template <class R, class S>
+void launch_coarse_hop_inv_odd_base(const CGeom& cg, const void* D, const cx<R>* Minv, const cx<R>* in,
+                                    const cx<R>* base, cx<R>* out, hipStream_t st);
+template <class R, class S>
+void launch_coarse_schur_even(const CGeom& cg, const void* D, double tw, const cx<R>* v, const cx<R>* t, cx<R>* out,
+                              int mode, hipStream_t st);
+
+// ---------------------------------------------------------------------- BLAS
+// partial sums of <V_i, w> (i < k) into partial[i][nwg]; then reduced into out
+template <class R>
+void launch_multidot(const cx<R>* V, long ldv, int k, const cx<R>* w, long N, cx<double>* partial, int nwg,
+                     hipStream_t st);
+void launch_reduce(const cx<double>* partial, int k, int nwg, cx<double>* out, int mode, hipStream_t st);
+template <class R>
+void launch_multi_axpy(const cx<R>* V, long ldv, int k, const cx<double>* coef, double sign, cx<R>* w, long N,
+                       hipStream_t st);
+template <class R>
+void launch_scale_by_inv(const cx<R>* in, const cx<double>* s, cx<R>* out, long N, hipStream_t st);
+template <class RA, class RB>
+void launch_copy_cvt(const cx<RA>* in, cx<RB>* out, long N, hipStream_t st);
+template <class R>
+void launch_axpby(long N, double a, const cx<R>* x, double b, cx<R>* y, hipStream_t st);  // y = a x + b y
+template <class R>
+void launch_sub(long N, const cx<R>* a, const cx<R>* b, cx<R>* out, hipStream_t st);     // out = a - b
+template <class R>
+void launch_zero(long N, cx<R>* x, hipStream_t st);
+void launch_givens(cx<double>* H, int ldh, double* cs, cx<double>* sn, cx<double>* g, int j, double* resid,
+                   hipStream_t st);
+void launch_trisolve(const cx<double>* H, int ldh, const cx<double>* g, cx<double>* y, int j, hipStream_t st);
+void launch_set_scalar(cx<double>* dst, const cx<double>* src_norm2_sqrt, hipStream_t st);
+
+}  // namespace ddamg

@@ -1,0 +1,917 @@
+// Host orchestration of the DD-alpha-AMG solver (paper Sec. 1, Eq. 1):
+// flexible GMRES on the fine level, preconditioned by the multigrid cycle
+//   x = k SAP iterations after  x = P D_c^{-1} P^dag (v - D x_j)  after j SAP
+// iterations; coarse solves by FGMRES preconditioned with the next level's
+// cycle, and odd-even GMRES on the coarsest level (Sec. 3).  The adaptive
+// setup builds the test vectors that span P (Sec. 1; setup iterations as in
+// Listing 1).  All arithmetic runs in the kernels; this file only sequences
+// launches and moves at most one scalar per Krylov iteration to the host.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "solver.hpp"
+
+namespace ddamg {
+
+// ---------------------------------------------------------------------------
+// small helper kernels: permutations between lexicographic and ordered coarse
+// site numbering, odd-site inverse application
+template <class RA, class RB>
+__global__ void k_permute(int n, int nsites, const int* __restrict__ map, const cx<RA>* __restrict__ in,
+                          cx<RB>* __restrict__ out, int scatter) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)nsites * n) return;
+  int s = (int)(gid / n), k = (int)(gid - (long)s * n);
+  long src, dst;
+  if (scatter) {  // out[map[s]] = in[s]
+    src = gid;
+    dst = (long)map[s] * n + k;
+  } else {        // out[s] = in[map[s]]
+    src = (long)map[s] * n + k;
+    dst = gid;
+  }
+  cx<RA> v = in[src];
+  out[dst] = mk<RB>((RB)v.re, (RB)v.im);
+}
+template <class RA, class RB>
+static void permute(int n, int nsites, const int* map, const cx<RA>* in, cx<RB>* out, int scatter, hipStream_t st) {
+  long tot = (long)nsites * n;
+  hipLaunchKernelGGL((k_permute<RA, RB>), dim3((tot + 255) / 256), dim3(256), 0, st, n, nsites, map, in, out,
+                     scatter);
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_minv_odd(CGeom cg, const cx<R>* __restrict__ Minv, const cx<R>* __restrict__ in,
+                                                  cx<R>* __restrict__ out) {
+  __shared__ cx<R> us[4][64];
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int io = blockIdx.x * 4 + wv;
+  int site = cg.neven + io;
+  bool valid = site < cg.nsites;
+  const int n = cg.n;
+  if (valid && lane < n) us[wv][lane] = in[(long)site * n + lane];
+  __syncthreads();
+  if (valid && lane < n) {
+    const cx<R>* M = Minv + (long)io * n * n;
+    cx<R> acc = mk<R>(0, 0);
+    for (int l = 0; l < n; ++l) cmac(acc, M[(long)l * n + lane], us[wv][l]);
+    out[(long)site * n + lane] = acc;
+  }
+}
+
+__global__ void k_all_finite(long n, const double* __restrict__ a, int* __restrict__ flag) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(a[i])) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+hipEvent_t KernelTimer::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
+void KernelTimer::begin(int kind, hipEvent_t* a) {
+  (void)kind;
+  *a = nullptr;
+  if (!on) return;
+  *a = get();
+  HIP_CHECK(hipEventRecord(*a, st));
+}
+void KernelTimer::end(int kind, hipEvent_t a) {
+  if (!on || !a) return;
+  hipEvent_t b = get();
+  HIP_CHECK(hipEventRecord(b, st));
+  recs.push_back({kind, a, b});
+  if (recs.size() > 4096) flush();
+}
+void KernelTimer::flush() {
+  if (recs.empty()) return;
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (auto& r : recs) {
+    float t = 0;
+    HIP_CHECK(hipEventElapsedTime(&t, r.a, r.b));
+    count[r.kind] += 1;
+    ms[r.kind] += t;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+}
+void KernelTimer::reset() {
+  for (int i = 0; i < 4; ++i) {
+    count[i] = 0;
+    ms[i] = 0;
+  }
+}
+KernelTimer::~KernelTimer() {
+  for (auto& r : recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+struct TimeScope {
+  KernelTimer& t;
+  int kind;
+  hipEvent_t a;
+  TimeScope(KernelTimer& t_, int k) : t(t_), kind(k) { t.begin(k, &a); }
+  ~TimeScope() { t.end(kind, a); }
+};
+
+// ---------------------------------------------------------------------------
+template <class R>
+void KrylovWS<R>::init(int m_, long ld_, long N, bool flex) {
+  m = m_;
+  ld = ld_;
+  flexible = flex;
+  V.ensure(sizeof(cx<R>) * (size_t)(m + 1) * ld);
+  if (flex) Z.ensure(sizeof(cx<R>) * (size_t)m * ld);
+  tmp.ensure(sizeof(cx<R>) * (size_t)ld);
+  H.ensure(sizeof(cx<double>) * (size_t)(m + 1) * m);
+  cs.ensure(sizeof(double) * m);
+  sn.ensure(sizeof(cx<double>) * m);
+  g.ensure(sizeof(cx<double>) * (m + 1));
+  y.ensure(sizeof(cx<double>) * (m + 1));
+  nwg = (int)std::min<long>(1024, std::max<long>(1, (N + 255) / 256));
+  part.ensure(sizeof(cx<double>) * (size_t)nwg * (m + 1));
+  scal.ensure(sizeof(cx<double>) * 4);
+  resid.ensure(sizeof(double));
+  if (!h_resid) HIP_CHECK(hipHostMalloc((void**)&h_resid, sizeof(double) * 4, hipHostMallocDefault));
+}
+template <class R>
+KrylovWS<R>::~KrylovWS() {
+  if (h_resid) (void)hipHostFree(h_resid);
+}
+template struct KrylovWS<double>;
+template struct KrylovWS<float>;
+
+template <class R>
+KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(const cx<R>*, cx<R>*)>& A,
+                    const std::function<void(const cx<R>*, cx<R>*)>* M, const cx<R>* b, cx<R>* x, double tol,
+                    int max_iter, bool fixed, bool x_is_zero) {
+  hipStream_t st = c.st;
+  const int m = ws.m;
+  const long ld = ws.ld;
+  int nwg = (int)std::min<long>(ws.nwg, std::max<long>(1, (N + 255) / 256));
+  cx<R>* V = ws.V.template as<cx<R>>();
+  cx<R>* Z = M ? ws.Z.template as<cx<R>>() : V;
+  cx<R>* r = ws.tmp.template as<cx<R>>();
+  cx<double>* H = ws.H.template as<cx<double>>();
+  cx<double>* scal = ws.scal.template as<cx<double>>();
+  cx<double>* part = ws.part.template as<cx<double>>();
+  auto norm_to = [&](const cx<R>* v, cx<double>* dst) {
+    launch_multidot<R>(v, 0, 1, v, N, part, nwg, st);
+    launch_reduce(part, 1, nwg, dst, 2, st);
+  };
+  auto read = [&](const void* dptr) -> double {
+    HIP_CHECK(hipMemcpyAsync(ws.h_resid, dptr, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    return ws.h_resid[0];
+  };
+  KrylovResult res;
+  norm_to(b, scal);
+  double bnorm = read(scal);
+  if (bnorm == 0.0) {
+    launch_zero<R>(N, x, st);
+    res.converged = true;
+    return res;
+  }
+  if (x_is_zero) {
+    launch_zero<R>(N, x, st);
+    launch_copy_cvt<R, R>(b, r, N, st);
+  } else {
+    A(x, r);
+    launch_sub<R>(N, b, r, r, st);
+  }
+  norm_to(r, scal + 1);
+  double beta = read(scal + 1);
+  int it = 0;
+  while (true) {
+    if (!fixed && beta <= tol * bnorm) break;
+    if (it >= max_iter) break;
+    int mm = fixed ? std::min(m, max_iter - it) : m;
+    launch_scale_by_inv<R>(r, scal + 1, V, N, st);
+    launch_zero<double>(m + 1, ws.g.template as<cx<double>>(), st);
+    launch_set_scalar(ws.g.template as<cx<double>>(), scal + 1, st);
+    int jd = 0;
+    for (int j = 0; j < mm; ++j) {
+      cx<R>* Vj = V + (long)j * ld;
+      cx<R>* Vn = V + (long)(j + 1) * ld;
+      cx<R>* z = Vj;
+      if (M) {
+        z = Z + (long)j * ld;
+        (*M)(Vj, z);
+      }
+      A(z, Vn);
+      cx<double>* hcol = H + (long)j * (m + 1);
+      launch_multidot<R>(V, ld, j + 1, Vn, N, part, nwg, st);
+      launch_reduce(part, j + 1, nwg, hcol, 0, st);
+      launch_multi_axpy<R>(V, ld, j + 1, hcol, -1.0, Vn, N, st);
+      launch_multidot<R>(V, ld, j + 1, Vn, N, part, nwg, st);
+      launch_reduce(part, j + 1, nwg, ws.y.template as<cx<double>>(), 0, st);
+      launch_reduce(part, j + 1, nwg, hcol, 1, st);
+      launch_multi_axpy<R>(V, ld, j + 1, ws.y.template as<cx<double>>(), -1.0, Vn, N, st);
+      norm_to(Vn, hcol + j + 1);
+      launch_scale_by_inv<R>(Vn, hcol + j + 1, Vn, N, st);
+      launch_givens(H, m + 1, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), ws.g.template as<cx<double>>(), j,
+                    ws.resid.template as<double>(), st);
+      ++it;
+      jd = j + 1;
+      if (!fixed) {
+        double est = read(ws.resid.p);
+        if (est <= tol * bnorm) break;
+      }
+      if (it >= max_iter) break;
+    }
+    launch_trisolve(H, m + 1, ws.g.template as<cx<double>>(), ws.y.template as<cx<double>>(), jd, st);
+    launch_multi_axpy<R>(Z, ld, jd, ws.y.template as<cx<double>>(), 1.0, x, N, st);
+    A(x, r);
+    launch_sub<R>(N, b, r, r, st);
+    norm_to(r, scal + 1);
+    beta = read(scal + 1);
+    if (fixed && it >= max_iter) break;
+    if (beta == 0.0) break;
+  }
+  res.iters = it;
+  res.resid = beta / bnorm;
+  res.converged = beta <= tol * bnorm;
+  return res;
+}
+template KrylovResult fgmres<double>(Ctx&, KrylovWS<double>&, long,
+                                     const std::function<void(const cx<double>*, cx<double>*)>&,
+                                     const std::function<void(const cx<double>*, cx<double>*)>*, const cx<double>*,
+                                     cx<double>*, double, int, bool, bool);
+template KrylovResult fgmres<float>(Ctx&, KrylovWS<float>&, long,
+                                    const std::function<void(const cx<float>*, cx<float>*)>&,
+                                    const std::function<void(const cx<float>*, cx<float>*)>*, const cx<float>*,
+                                    cx<float>*, double, int, bool, bool);
+
+// ---------------------------------------------------------------------------
+void Ctx::ensure_32() {
+  if (have_32) return;
+  U32.ensure(sizeof(cx<float>) * (size_t)g.V * 36);
+  H32.ensure(sizeof(float) * (size_t)g.V * 72);
+  M32.ensure(sizeof(float) * (size_t)g.V * 36);
+  launch_cvt_cx<float>((long)g.V * 36, U64.as<cx<double>>(), U32.p, st);
+  launch_cvt_real((long)g.V * 72, H64.as<double>(), H32.as<float>(), st);
+  launch_cvt_real((long)g.V * 36, M64.as<double>(), M32.as<float>(), st);
+  have_32 = true;
+}
+void Ctx::ensure_16(int kind) {
+  ensure_32();
+  if (u16_kind == kind) return;
+  U16.ensure(4 * (size_t)g.V * 36);
+  if (kind == DDAMG_FP16) launch_cvt_cx<f16>((long)g.V * 36, U64.as<cx<double>>(), U16.p, st);
+  else launch_cvt_cx<bf16>((long)g.V * 36, U64.as<cx<double>>(), U16.p, st);
+  u16_kind = kind;
+}
+void Ctx::rebuild_odd_inverse() {
+  launch_odd_inverse(g, H64.as<double>(), mu, M64.as<double>(), st);
+  if (have_32) launch_cvt_real((long)g.V * 36, M64.as<double>(), M32.as<float>(), st);
+}
+void Ctx::dirac64(const cx<double>* in, cx<double>* out, double tw) {
+  TimeScope ts(timer, 0);
+  launch_dirac<double, double>(g, U64.p, H64.as<double>(), tw, in, out, st);
+}
+void Ctx::upload_fine(const void* src, int on_device, cx<double>* dst64) {
+  const cx<double>* s = (const cx<double>*)src;
+  if (!on_device) {
+    lex.ensure(sizeof(cx<double>) * fine_len());
+    HIP_CHECK(hipMemcpyAsync(lex.p, src, sizeof(cx<double>) * fine_len(), hipMemcpyHostToDevice, st));
+    s = lex.as<cx<double>>();
+  }
+  launch_from_lex<double>(g, s, dst64, 12, st);
+}
+void Ctx::download_fine(const cx<double>* src64, void* dst, int on_device) {
+  if (on_device) {
+    launch_to_lex<double>(g, src64, (cx<double>*)dst, 12, st);
+    return;
+  }
+  lex.ensure(sizeof(cx<double>) * fine_len());
+  launch_to_lex<double>(g, src64, lex.as<cx<double>>(), 12, st);
+  HIP_CHECK(hipMemcpyAsync(dst, lex.p, sizeof(cx<double>) * fine_len(), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+static void lex_coords(const int L[4], int s, int x[4]) {
+  x[3] = s % L[3];
+  s /= L[3];
+  x[2] = s % L[2];
+  s /= L[2];
+  x[1] = s % L[1];
+  x[0] = s / L[1];
+}
+static int lex_of(const int L[4], const int x[4]) { return ((x[0] * L[1] + x[1]) * L[2] + x[2]) * L[3] + x[3]; }
+
+static void build_order(CoarseGeo& G) {
+  G.nsites = G.L[0] * G.L[1] * G.L[2] * G.L[3];
+  G.order.assign(G.nsites, 0);
+  G.lexof.assign(G.nsites, 0);
+  int k = 0;
+  for (int par = 0; par < 2; ++par)
+    for (int s = 0; s < G.nsites; ++s) {
+      int x[4];
+      lex_coords(G.L, s, x);
+      if (((x[0] + x[1] + x[2] + x[3]) & 1) == par) {
+        G.order[s] = k;
+        G.lexof[k] = s;
+        ++k;
+      }
+    }
+  G.neven = 0;
+  for (int s = 0; s < G.nsites; ++s) {
+    int x[4];
+    lex_coords(G.L, s, x);
+    if (((x[0] + x[1] + x[2] + x[3]) & 1) == 0) ++G.neven;
+  }
+  std::vector<int> nb((size_t)G.nsites * 8);
+  for (int o = 0; o < G.nsites; ++o) {
+    int x[4];
+    lex_coords(G.L, G.lexof[o], x);
+    for (int mu = 0; mu < 4; ++mu)
+      for (int d = 0; d < 2; ++d) {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[mu] = (y[mu] + (d == 0 ? 1 : -1) + G.L[mu]) % G.L[mu];
+        nb[(size_t)o * 8 + d * 4 + mu] = G.order[lex_of(G.L, y)];
+      }
+  }
+  G.nbr.alloc(sizeof(int) * nb.size());
+  HIP_CHECK(hipMemcpy(G.nbr.p, nb.data(), sizeof(int) * nb.size(), hipMemcpyHostToDevice));
+  G.d_order.alloc(sizeof(int) * G.nsites);
+  HIP_CHECK(hipMemcpy(G.d_order.p, G.order.data(), sizeof(int) * G.nsites, hipMemcpyHostToDevice));
+}
+
+// aggregation tables of level G towards the next level Gn (blocks ab)
+static void build_agg(CoarseGeo& G, const CoarseGeo& Gn, const int ab[4]) {
+  for (int d = 0; d < 4; ++d) G.ab[d] = ab[d];
+  G.asz = ab[0] * ab[1] * ab[2] * ab[3];
+  G.nagg = Gn.nsites;
+  std::vector<int> as((size_t)G.nagg * G.asz), sa(G.nsites);
+  for (int A = 0; A < G.nagg; ++A) {
+    int X[4];
+    lex_coords(Gn.L, Gn.lexof[A], X);
+    for (int j = 0; j < G.asz; ++j) {
+      int l[4];
+      lex_coords(ab, j, l);
+      int x[4];
+      for (int d = 0; d < 4; ++d) x[d] = X[d] * ab[d] + l[d];
+      int o = G.order[lex_of(G.L, x)];
+      as[(size_t)A * G.asz + j] = o;
+      sa[o] = A;
+    }
+  }
+  G.agg_sites.alloc(sizeof(int) * as.size());
+  HIP_CHECK(hipMemcpy(G.agg_sites.p, as.data(), sizeof(int) * as.size(), hipMemcpyHostToDevice));
+  G.site_agg.alloc(sizeof(int) * sa.size());
+  HIP_CHECK(hipMemcpy(G.site_agg.p, sa.data(), sizeof(int) * sa.size(), hipMemcpyHostToDevice));
+}
+
+static void build_sap_blocks(CoarseGeo& G, const int sb[4]) {
+  int nb[4];
+  for (int d = 0; d < 4; ++d) {
+    G.sb[d] = sb[d];
+    if (sb[d] <= 0 || G.L[d] % sb[d]) throw Error(INVALID_ARG, "coarse SAP block does not divide the coarse lattice");
+    nb[d] = G.L[d] / sb[d];
+    if (nb[d] % 2) throw Error(INVALID_ARG, "coarse SAP needs an even number of blocks per direction");
+  }
+  G.ssz = sb[0] * sb[1] * sb[2] * sb[3];
+  if (G.ssz > 16) throw Error(INVALID_ARG, "coarse SAP blocks are limited to 16 sites");
+  G.nsblk = nb[0] * nb[1] * nb[2] * nb[3];
+  std::vector<int> sites, nbr;
+  for (int col = 0; col < 2; ++col) {
+    G.nsblk_col[col] = 0;
+    for (int Bl = 0; Bl < G.nsblk; ++Bl) {
+      int Bc[4];
+      lex_coords(nb, Bl, Bc);
+      if (((Bc[0] + Bc[1] + Bc[2] + Bc[3]) & 1) != col) continue;
+      G.nsblk_col[col]++;
+      for (int j = 0; j < G.ssz; ++j) {
+        int l[4];
+        lex_coords(sb, j, l);
+        int x[4];
+        for (int d = 0; d < 4; ++d) x[d] = Bc[d] * sb[d] + l[d];
+        sites.push_back(G.order[lex_of(G.L, x)]);
+        for (int dir = 0; dir < 2; ++dir)
+          for (int mu = 0; mu < 4; ++mu) {
+            int m2[4] = {l[0], l[1], l[2], l[3]};
+            m2[mu] += dir == 0 ? 1 : -1;
+            nbr.push_back((m2[mu] >= 0 && m2[mu] < sb[mu]) ? lex_of(sb, m2) : -1);
+          }
+      }
+    }
+  }
+  G.sap_sites.alloc(sizeof(int) * sites.size());
+  HIP_CHECK(hipMemcpy(G.sap_sites.p, sites.data(), sizeof(int) * sites.size(), hipMemcpyHostToDevice));
+  G.sap_nbr.alloc(sizeof(int) * nbr.size());
+  HIP_CHECK(hipMemcpy(G.sap_nbr.p, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+template <class R, class S>
+struct MG : MGBase {
+  Ctx& c;
+  ddamg_params p;
+  int L;
+  std::vector<std::unique_ptr<CoarseGeo>> geos;  // index = level (0 unused)
+  DevBuf f2c;
+  const void* U = nullptr;
+  const R* Hf = nullptr;
+  const R* Mf = nullptr;
+  int Nv[3] = {0, 0, 0};
+  DevBuf Vraw[3], Q[3];
+  DevBuf D64[4], DS[4], Minvc, Xs, invscr;
+  double tw[4] = {0, 0, 0, 0};
+  DevBuf fx, fb, fr;              // fine R vectors
+  DevBuf rc[4], ec[4], wk[4][4];  // coarse vectors per level
+  KrylovWS<R> kws[4];
+  std::function<void(const cx<R>*, cx<R>*)> Aop[4], Mop[4];
+
+  MG(Ctx& c_, const ddamg_params& p_) : c(c_), p(p_), L(p_.levels) {
+    const Geom& g = c.g;
+    for (int l = 0; l < L - 1; ++l) Nv[l] = p.nvec[l];
+    if (L < 2 || L > 3) throw Error(INVALID_ARG, "levels must be 2 or 3");
+    for (int d = 0; d < 4; ++d)
+      if (p.block[0][d] != g.b[d]) throw Error(INVALID_ARG, "block[0] must equal the block given to ddamg_create");
+    if (Nv[0] < 1 || 2 * Nv[0] > 64 || Nv[0] > g.bs * 6)
+      throw Error(INVALID_ARG, "nvec[0] must satisfy 1 <= nvec <= 32 and nvec <= 6 * block sites");
+    geos.resize(L);
+    // level 1
+    geos[1].reset(new CoarseGeo());
+    for (int d = 0; d < 4; ++d) geos[1]->L[d] = g.nb[d];
+    geos[1]->n = 2 * Nv[0];
+    build_order(*geos[1]);
+    for (int l = 2; l < L; ++l) {
+      CoarseGeo& Gp = *geos[l - 1];
+      geos[l].reset(new CoarseGeo());
+      for (int d = 0; d < 4; ++d) {
+        int b = p.block[l - 1][d];
+        if (b <= 0 || Gp.L[d] % b) throw Error(INVALID_ARG, "block does not divide the coarse lattice");
+        geos[l]->L[d] = Gp.L[d] / b;
+      }
+      if (Nv[l - 1] < 1 || 2 * Nv[l - 1] > 64) throw Error(INVALID_ARG, "nvec must satisfy 1 <= nvec <= 32");
+      int asz = p.block[l - 1][0] * p.block[l - 1][1] * p.block[l - 1][2] * p.block[l - 1][3];
+      if (Nv[l - 1] > asz * Gp.n / 2) throw Error(INVALID_ARG, "nvec exceeds the rows of an aggregate half");
+      if (asz * Gp.n / 2 > 1024) throw Error(INVALID_ARG, "coarse aggregate too large");
+      geos[l]->n = 2 * Nv[l - 1];
+      build_order(*geos[l]);
+      build_agg(Gp, *geos[l], p.block[l - 1]);
+      build_sap_blocks(Gp, p.coarse_sap_block);
+    }
+    for (int d = 0; d < 4; ++d)
+      if (geos[L - 1]->L[d] % 2) throw Error(INVALID_ARG, "the coarsest lattice needs even extents (odd-even)");
+    // fine block -> level-1 ordered index
+    {
+      std::vector<int> m(g.nblocks);
+      for (int B = 0; B < g.nblocks; ++B) m[B] = geos[1]->order[B];
+      f2c.alloc(sizeof(int) * g.nblocks);
+      HIP_CHECK(hipMemcpy(f2c.p, m.data(), sizeof(int) * g.nblocks, hipMemcpyHostToDevice));
+    }
+    // operator data of the fine level in this precision
+    if constexpr (std::is_same<R, double>::value) {
+      U = c.U64.p;
+      Hf = c.H64.as<double>();
+      Mf = c.M64.as<double>();
+    } else {
+      if constexpr (std::is_same<S, float>::value) {
+        c.ensure_32();
+        U = c.U32.p;
+      } else {
+        c.ensure_16(std::is_same<S, f16>::value ? DDAMG_FP16 : DDAMG_BF16);
+        U = c.U16.p;
+      }
+      Hf = c.H32.template as<float>();
+      Mf = c.M32.template as<float>();
+    }
+    set_twists(c.mu);
+    // allocations
+    long fl = c.fine_len();
+    fx.alloc(sizeof(cx<R>) * fl);
+    fb.alloc(sizeof(cx<R>) * fl);
+    fr.alloc(sizeof(cx<R>) * fl);
+    Vraw[0].alloc(sizeof(cx<double>) * fl * Nv[0]);
+    Q[0].alloc(sizeof(cx<R>) * fl * Nv[0]);
+    size_t maxnn = 0;
+    for (int l = 1; l < L; ++l) {
+      CoarseGeo& G = *geos[l];
+      long len = (long)G.nsites * G.n;
+      size_t nn = (size_t)G.n * G.n;
+      maxnn = std::max(maxnn, nn * G.nsites);
+      D64[l].alloc(sizeof(cx<double>) * nn * 5 * G.nsites);
+      if (!std::is_same<S, double>::value) DS[l].alloc(sizeof(typename store_traits<S>::elem) * nn * 5 * G.nsites);
+      rc[l].alloc(sizeof(cx<R>) * len);
+      ec[l].alloc(sizeof(cx<R>) * len);
+      for (int k = 0; k < 4; ++k) wk[l][k].alloc(sizeof(cx<R>) * len);
+      if (l < L - 1) {
+        Vraw[l].alloc(sizeof(cx<double>) * len * Nv[l]);
+        Q[l].alloc(sizeof(cx<R>) * len * Nv[l]);
+        kws[l].init(p.inter_restart, len, len, true);
+      } else {
+        kws[l].init(p.coarse_restart, len, (long)G.neven * G.n, false);
+        Minvc.alloc(sizeof(cx<R>) * nn * (G.nsites - G.neven));
+        invscr.alloc(sizeof(cx<double>) * nn * 2 * (G.nsites - G.neven));
+      }
+    }
+    Xs.alloc(sizeof(cx<double>) * maxnn);
+    for (int l = 1; l < L; ++l) {
+      CoarseGeo& G = *geos[l];
+      CGeom cg = G.cg();
+      const void* Dp = Dst(l);
+      if (l == L - 1) {
+        cx<R>* t = wk[l][0].template as<cx<R>>();
+        Aop[l] = [this, cg, l, t](const cx<R>* in, cx<R>* out) {
+          launch_coarse_hop_inv_odd<R, S>(cg, Dst(l), Minvc.template as<cx<R>>(), in, t, 0, c.st);
+          launch_coarse_schur_even<R, S>(cg, Dst(l), tw[l], in, t, out, 0, c.st);
+        };
+      } else {
+        Aop[l] = [this, cg, l](const cx<R>* in, cx<R>* out) {
+          TimeScope ts(c.timer, 2);
+          launch_coarse_apply<R, S>(cg, Dst(l), tw[l], in, out, c.st);
+        };
+        Mop[l] = [this, l](const cx<R>* in, cx<R>* out) { vcycle(l, in, out); };
+      }
+      (void)Dp;
+    }
+  }
+
+  const void* Dst(int l) const {
+    if constexpr (std::is_same<S, double>::value) return D64[l].p;
+    else return DS[l].p;
+  }
+
+  void set_twists(double mu) {
+    tw[0] = mu;
+    for (int l = 1; l < L; ++l) tw[l] = (l == L - 1) ? p.coarse_mu_factor * mu : mu;
+  }
+
+  int nlev() const override { return L; }
+  const CoarseGeo& geo(int l) const override { return *geos[l]; }
+
+  // ---- level operations ----------------------------------------------------
+  void fine_dirac(const cx<R>* in, cx<R>* out) {
+    TimeScope ts(c.timer, 0);
+    launch_dirac<R, S>(c.g, U, Hf, tw[0], in, out, c.st);
+  }
+  void fine_sap(const cx<R>* b, cx<R>* x, int iters, int nmr) {
+    for (int it = 0; it < iters; ++it)
+      for (int col = 0; col < 2; ++col) {
+        TimeScope ts(c.timer, 1);
+        launch_sap<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, c.st);
+      }
+  }
+  void coarse_sap(int l, const cx<R>* b, cx<R>* x, int iters) {
+    CoarseGeo& G = *geos[l];
+    CGeom cg = G.cg();
+    cx<R>* r = wk[l][1].template as<cx<R>>();
+    for (int it = 0; it < iters; ++it)
+      for (int col = 0; col < 2; ++col) {
+        {
+          TimeScope ts(c.timer, 2);
+          launch_coarse_residual<R, S>(cg, Dst(l), tw[l], b, x, r, c.st);
+        }
+        int off = col == 0 ? 0 : G.nsblk_col[0];
+        launch_coarse_sap<R, S>(cg, Dst(l), tw[l], G.nsblk_col[col], G.ssz, G.sap_sites.template as<int>() + off * G.ssz,
+                                G.sap_nbr.template as<int>() + (long)off * G.ssz * 8, r, x, p.coarse_mr_steps, c.st);
+      }
+  }
+  void restrict_(int l, const cx<R>* in, cx<R>* out) {
+    TimeScope ts(c.timer, 3);
+    if (l == 0) {
+      launch_restrict_fine<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), c.fine_len(), in, f2c.template as<int>(), out,
+                              c.st);
+    } else {
+      CoarseGeo& G = *geos[l];
+      launch_restrict_coarse<R>(G.n, Nv[l], G.nagg, G.asz, G.agg_sites.template as<int>(), Q[l].template as<cx<R>>(),
+                                (long)G.nsites * G.n, in, out, c.st);
+    }
+  }
+  void prolong_(int l, const cx<R>* in, cx<R>* out, int acc) {
+    TimeScope ts(c.timer, 3);
+    if (l == 0) {
+      launch_prolong_fine<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), c.fine_len(), in, f2c.template as<int>(), out, acc,
+                             c.st);
+    } else {
+      CoarseGeo& G = *geos[l];
+      launch_prolong_coarse<R>(G.n, Nv[l], G.nsites, G.site_agg.template as<int>(), Q[l].template as<cx<R>>(),
+                               (long)G.nsites * G.n, in, out, acc, c.st);
+    }
+  }
+
+  void coarse_solve(int l, const cx<R>* b, cx<R>* x) {
+    CoarseGeo& G = *geos[l];
+    CGeom cg = G.cg();
+    KrylovResult kr;
+    if (l == L - 1) {
+      cx<R>* t = wk[l][2].template as<cx<R>>();
+      cx<R>* rhs = wk[l][3].template as<cx<R>>();
+      // t_o = D_oo^{-1} b_o ;  rhs_e = b_e - D_eo t_o
+      hipLaunchKernelGGL(k_minv_odd<R>, dim3((G.nsites - G.neven + 3) / 4), dim3(256), 0, c.st, cg,
+                         Minvc.template as<cx<R>>(), b, t);
+      launch_coarse_schur_even<R, S>(cg, Dst(l), tw[l], b, t, rhs, 1, c.st);
+      kr = fgmres<R>(c, kws[l], (long)G.neven * G.n, Aop[l], nullptr, rhs, x, p.coarse_tol, p.coarse_max_iter,
+                     p.fixed_iters != 0, true);
+      // x_o = D_oo^{-1} (b_o - D_oe x_e)
+      launch_coarse_hop_inv_odd_base<R, S>(cg, Dst(l), Minvc.template as<cx<R>>(), x, b, x, c.st);
+    } else {
+      kr = fgmres<R>(c, kws[l], (long)G.nsites * G.n, Aop[l], &Mop[l], b, x, p.inter_tol, p.inter_max_iter,
+                     p.fixed_iters != 0, true);
+    }
+    coarse_iters[l] += kr.iters;
+  }
+
+  // x = cycle(v) on level l, x0 = 0
+  void vcycle(int l, const cx<R>* v, cx<R>* x) {
+    if (l == 0) {
+      ++vcycles;
+      const cx<R>* rin = v;
+      if (p.sap_pre > 0) {
+        launch_zero<R>(c.fine_len(), x, c.st);
+        fine_sap(v, x, p.sap_pre, p.mr_steps);
+        fine_dirac(x, fr.template as<cx<R>>());
+        launch_sub<R>(c.fine_len(), v, fr.template as<cx<R>>(), fr.template as<cx<R>>(), c.st);
+        rin = fr.template as<cx<R>>();
+      }
+      restrict_(0, rin, rc[1].template as<cx<R>>());
+      coarse_solve(1, rc[1].template as<cx<R>>(), ec[1].template as<cx<R>>());
+      prolong_(0, ec[1].template as<cx<R>>(), x, p.sap_pre > 0);
+      fine_sap(v, x, p.sap_post, p.mr_steps);
+    } else {
+      restrict_(l, v, rc[l + 1].template as<cx<R>>());
+      coarse_solve(l + 1, rc[l + 1].template as<cx<R>>(), ec[l + 1].template as<cx<R>>());
+      prolong_(l, ec[l + 1].template as<cx<R>>(), x, 0);
+      coarse_sap(l, v, x, p.coarse_sap_post);
+    }
+  }
+
+  void precond(const cx<double>* v, cx<double>* z) override {
+    if constexpr (std::is_same<R, double>::value) {
+      vcycle(0, v, z);
+    } else {
+      long n = c.fine_len();
+      launch_copy_cvt<double, R>(v, fb.template as<cx<R>>(), n, c.st);
+      vcycle(0, fb.template as<cx<R>>(), fx.template as<cx<R>>());
+      launch_copy_cvt<R, double>(fx.template as<cx<R>>(), z, n, c.st);
+    }
+  }
+
+  void set_mu(double mu) override {
+    set_twists(mu);
+    CoarseGeo& G = *geos[L - 1];
+    launch_coarse_odd_inverse<R>(G.cg(), D64[L - 1].template as<cx<double>>(), tw[L - 1],
+                                 invscr.template as<cx<double>>(), Minvc.template as<cx<R>>(), c.st);
+  }
+
+  // ---- setup ---------------------------------------------------------------
+  long level_len(int l) const { return l == 0 ? c.fine_len() : (long)geos[l]->nsites * geos[l]->n; }
+
+  void upload_level(int l, const void* src, int on_device, cx<double>* dst) {
+    if (l == 0) {
+      c.upload_fine(src, on_device, dst);
+      return;
+    }
+    CoarseGeo& G = *geos[l];
+    long len = level_len(l);
+    const cx<double>* s = (const cx<double>*)src;
+    if (!on_device) {
+      c.lex.ensure(sizeof(cx<double>) * std::max(len, c.fine_len()));
+      HIP_CHECK(hipMemcpyAsync(c.lex.p, src, sizeof(cx<double>) * len, hipMemcpyHostToDevice, c.st));
+      s = c.lex.template as<cx<double>>();
+    }
+    permute<double, double>(G.n, G.nsites, G.d_order.template as<int>(), s, dst, 1, c.st);
+  }
+  void download_level(int l, const cx<double>* src, cx<double>* host) {
+    if (l == 0) {
+      c.download_fine(src, host, 0);
+      return;
+    }
+    CoarseGeo& G = *geos[l];
+    long len = level_len(l);
+    c.lex.ensure(sizeof(cx<double>) * std::max(len, c.fine_len()));
+    permute<double, double>(G.n, G.nsites, G.d_order.template as<int>(), src, c.lex.template as<cx<double>>(), 0,
+                            c.st);
+    HIP_CHECK(hipMemcpyAsync(host, c.lex.p, sizeof(cx<double>) * len, hipMemcpyDeviceToHost, c.st));
+    HIP_CHECK(hipStreamSynchronize(c.st));
+  }
+
+  void check_flag(const char* what) {
+    int h = 0;
+    HIP_CHECK(hipMemcpyAsync(&h, c.iflag.p, sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIP_CHECK(hipStreamSynchronize(c.st));
+    if (h) throw Error(NUMERICAL, what);
+  }
+
+  void build_next(int l) {
+    HIP_CHECK(hipMemsetAsync(c.iflag.p, 0, sizeof(int), c.st));
+    long len = level_len(l);
+    CoarseGeo& Gn = *geos[l + 1];
+    if (l == 0) {
+      launch_qr_fine<R>(c.g, Nv[0], Vraw[0].template as<cx<double>>(), len, Q[0].template as<cx<R>>(), len,
+                        c.iflag.template as<int>(), c.st);
+    } else {
+      CoarseGeo& G = *geos[l];
+      launch_qr_coarse<R>(G.n, Nv[l], G.nagg, G.asz, G.agg_sites.template as<int>(), Vraw[l].template as<cx<double>>(),
+                          len, Q[l].template as<cx<R>>(), len, c.iflag.template as<int>(), c.st);
+    }
+    check_flag("rank-deficient aggregate in the block orthonormalisation");
+    assemble_next(l);
+  }
+
+  void assemble_next(int l) {
+    long len = level_len(l);
+    CoarseGeo& Gn = *geos[l + 1];
+    if (l == 0) {
+      launch_assemble_fine<R>(c.g, Nv[0], c.U64.template as<cx<double>>(), c.H64.template as<double>(),
+                              Q[0].template as<cx<R>>(), len, f2c.template as<int>(), D64[1].template as<cx<double>>(),
+                              Xs.template as<cx<double>>(), c.st);
+    } else {
+      CoarseGeo& G = *geos[l];
+      launch_assemble_coarse<R>(G.cg(), Nv[l], G.nagg, G.ab, G.agg_sites.template as<int>(),
+                                D64[l].template as<cx<double>>(), Q[l].template as<cx<R>>(), len,
+                                D64[l + 1].template as<cx<double>>(), Xs.template as<cx<double>>(), c.st);
+    }
+    launch_self_fixup(Gn.n, Gn.nsites, D64[l + 1].template as<cx<double>>(), Xs.template as<cx<double>>(), c.st);
+    if constexpr (!std::is_same<S, double>::value)
+      launch_cvt_cx<S>((long)Gn.n * Gn.n * 5 * Gn.nsites, D64[l + 1].template as<cx<double>>(), DS[l + 1].p, c.st);
+    if (l + 1 == L - 1)
+      launch_coarse_odd_inverse<R>(Gn.cg(), D64[l + 1].template as<cx<double>>(), tw[l + 1],
+                                   invscr.template as<cx<double>>(), Minvc.template as<cx<R>>(), c.st);
+  }
+
+  // the level-l work vectors used as input/output of setup cycles
+  cx<R>* setup_in(int l) { return l == 0 ? fb.template as<cx<R>>() : wk[l][2].template as<cx<R>>(); }
+  cx<R>* setup_out(int l) { return l == 0 ? fx.template as<cx<R>>() : wk[l][3].template as<cx<R>>(); }
+  cx<R>* setup_zero(int l) { return l == 0 ? fr.template as<cx<R>>() : wk[l][0].template as<cx<R>>(); }
+
+  void smooth_level(int l, const cx<R>* b, cx<R>* x, int iters) {
+    if (l == 0) fine_sap(b, x, iters, p.mr_steps);
+    else coarse_sap(l, b, x, iters);
+  }
+
+  DevBuf npart;  // partial sums + scalar for normalisation
+  void normalise(cx<double>* v, long len) {
+    const int nwg = 1024;
+    npart.ensure(sizeof(cx<double>) * (nwg + 1));
+    cx<double>* part = npart.template as<cx<double>>();
+    cx<double>* sc = part + nwg;
+    int nw = (int)std::min<long>(nwg, (len + 255) / 256);
+    launch_multidot<double>(v, 0, 1, v, len, part, nw, c.st);
+    launch_reduce(part, 1, nw, sc, 2, c.st);
+    launch_scale_by_inv<double>(v, sc, v, len, c.st);
+  }
+
+  void iterate(int l) {
+    long len = level_len(l);
+    for (int i = 0; i < Nv[l]; ++i) {
+      cx<double>* vi = Vraw[l].template as<cx<double>>() + (long)i * len;
+      launch_copy_cvt<double, R>(vi, setup_in(l), len, c.st);
+      vcycle(l, setup_in(l), setup_out(l));
+      launch_copy_cvt<R, double>(setup_out(l), vi, len, c.st);
+      normalise(vi, len);
+    }
+    build_next(l);
+  }
+
+  void build(const void* const* vecs, int on_device, bool run_setup) override {
+    for (int l = 0; l < L - 1; ++l) {
+      long len = level_len(l);
+      for (int i = 0; i < Nv[l]; ++i) {
+        const char* src = (const char*)vecs[l] + sizeof(cx<double>) * (size_t)len * i;
+        cx<double>* vi = Vraw[l].template as<cx<double>>() + (long)i * len;
+        upload_level(l, src, on_device, vi);
+        if (run_setup && p.init_sap_iters > 0) {
+          launch_zero<R>(len, setup_zero(l), c.st);
+          launch_copy_cvt<double, R>(vi, setup_out(l), len, c.st);
+          smooth_level(l, setup_zero(l), setup_out(l), p.init_sap_iters);
+          launch_copy_cvt<R, double>(setup_out(l), vi, len, c.st);
+        }
+      }
+      build_next(l);
+    }
+    if (!run_setup) return;
+    for (int it = 0; it < p.setup_iters; ++it) {
+      iterate(0);
+      if (L == 3) {
+        assemble_next(1);
+        for (int t = 0; t < p.coarse_setup_iters; ++t) iterate(1);
+      }
+    }
+    c.sync();
+  }
+
+  // ---- parity helpers (host FP64 in/out) --------------------------------------
+  void get_interp(int l, cx<double>* host) override {
+    long len = level_len(l);
+    DevBuf t;
+    t.alloc(sizeof(cx<double>) * len);
+    for (int i = 0; i < Nv[l]; ++i) {
+      launch_copy_cvt<R, double>(Q[l].template as<cx<R>>() + (long)i * len, t.as<cx<double>>(), len, c.st);
+      download_level(l, t.as<cx<double>>(), host + (long)i * len);
+    }
+  }
+  void restrict_host(int l, const cx<double>* in, cx<double>* out) override {
+    long len = level_len(l), lenc = level_len(l + 1);
+    DevBuf a, b;
+    a.alloc(sizeof(cx<double>) * len);
+    b.alloc(sizeof(cx<double>) * lenc);
+    upload_level(l, in, 0, a.as<cx<double>>());
+    cx<R>* ar = setup_in(l);
+    launch_copy_cvt<double, R>(a.as<cx<double>>(), ar, len, c.st);
+    restrict_(l, ar, rc[l + 1].template as<cx<R>>());
+    launch_copy_cvt<R, double>(rc[l + 1].template as<cx<R>>(), b.as<cx<double>>(), lenc, c.st);
+    download_level(l + 1, b.as<cx<double>>(), out);
+  }
+  void prolong_host(int l, const cx<double>* in, cx<double>* out) override {
+    long len = level_len(l), lenc = level_len(l + 1);
+    DevBuf a, b;
+    a.alloc(sizeof(cx<double>) * lenc);
+    b.alloc(sizeof(cx<double>) * len);
+    upload_level(l + 1, in, 0, a.as<cx<double>>());
+    launch_copy_cvt<double, R>(a.as<cx<double>>(), ec[l + 1].template as<cx<R>>(), lenc, c.st);
+    prolong_(l, ec[l + 1].template as<cx<R>>(), setup_out(l), 0);
+    launch_copy_cvt<R, double>(setup_out(l), b.as<cx<double>>(), len, c.st);
+    download_level(l, b.as<cx<double>>(), out);
+  }
+  void get_coarse_op(int l, cx<double>* S_, cx<double>* F_) override {
+    CoarseGeo& G = *geos[l];
+    size_t nn = (size_t)G.n * G.n;
+    std::vector<cx<double>> h(nn * 5 * G.nsites);
+    HIP_CHECK(hipMemcpyAsync(h.data(), D64[l].p, sizeof(cx<double>) * h.size(), hipMemcpyDeviceToHost, c.st));
+    HIP_CHECK(hipStreamSynchronize(c.st));
+    for (int s = 0; s < G.nsites; ++s) {
+      int o = G.order[s];
+      for (int blk = 0; blk < 5; ++blk) {
+        const cx<double>* src = h.data() + ((size_t)o * 5 + blk) * nn;
+        cx<double>* dst = blk == 0 ? S_ + (size_t)s * nn : F_ + ((size_t)(blk - 1) * G.nsites + s) * nn;
+        for (int r = 0; r < G.n; ++r)
+          for (int k = 0; k < G.n; ++k) dst[(size_t)r * G.n + k] = src[(size_t)k * G.n + r];
+      }
+    }
+  }
+  void apply_coarse_host(int l, const cx<double>* in, cx<double>* out) override {
+    CoarseGeo& G = *geos[l];
+    long len = level_len(l);
+    DevBuf a;
+    a.alloc(sizeof(cx<double>) * len);
+    upload_level(l, in, 0, a.as<cx<double>>());
+    cx<R>* x = wk[l][2].template as<cx<R>>();
+    cx<R>* y = wk[l][3].template as<cx<R>>();
+    launch_copy_cvt<double, R>(a.as<cx<double>>(), x, len, c.st);
+    launch_coarse_apply<R, S>(G.cg(), Dst(l), tw[l], x, y, c.st);
+    launch_copy_cvt<R, double>(y, a.as<cx<double>>(), len, c.st);
+    download_level(l, a.as<cx<double>>(), out);
+  }
+  void coarse_sap_host(int l, const cx<double>* b, cx<double>* x, int iters) override {
+    long len = level_len(l);
+    DevBuf a;
+    a.alloc(sizeof(cx<double>) * len);
+    upload_level(l, b, 0, a.as<cx<double>>());
+    cx<R>* bb = wk[l][2].template as<cx<R>>();
+    cx<R>* xx = wk[l][3].template as<cx<R>>();
+    launch_copy_cvt<double, R>(a.as<cx<double>>(), bb, len, c.st);
+    upload_level(l, x, 0, a.as<cx<double>>());
+    launch_copy_cvt<double, R>(a.as<cx<double>>(), xx, len, c.st);
+    coarse_sap(l, bb, xx, iters);
+    launch_copy_cvt<R, double>(xx, a.as<cx<double>>(), len, c.st);
+    download_level(l, a.as<cx<double>>(), x);
+  }
+  void coarse_solve_host(int l, const cx<double>* b, cx<double>* x) override {
+    long len = level_len(l);
+    DevBuf a;
+    a.alloc(sizeof(cx<double>) * len);
+    upload_level(l, b, 0, a.as<cx<double>>());
+    launch_copy_cvt<double, R>(a.as<cx<double>>(), rc[l].template as<cx<R>>(), len, c.st);
+    coarse_solve(l, rc[l].template as<cx<R>>(), ec[l].template as<cx<R>>());
+    launch_copy_cvt<R, double>(ec[l].template as<cx<R>>(), a.as<cx<double>>(), len, c.st);
+    download_level(l, a.as<cx<double>>(), x);
+  }
+};
+
+std::unique_ptr<MGBase> make_mg(Ctx& c) {
+  switch (c.p.precision) {
+    case DDAMG_FP64: return std::unique_ptr<MGBase>(new MG<double, double>(c, c.p));
+    case DDAMG_FP32: return std::unique_ptr<MGBase>(new MG<float, float>(c, c.p));
+    case DDAMG_FP16: return std::unique_ptr<MGBase>(new MG<float, f16>(c, c.p));
+    case DDAMG_BF16: return std::unique_ptr<MGBase>(new MG<float, bf16>(c, c.p));
+    default: throw Error(INVALID_ARG, "unknown precision");
+  }
+}
+
+// exported for the API file
+void check_finite(Ctx& c, const double* dev, long n) {
+  HIP_CHECK(hipMemsetAsync(c.iflag.p, 0, sizeof(int), c.st));
+  hipLaunchKernelGGL(k_all_finite, dim3((n + 255) / 256), dim3(256), 0, c.st, n, dev, c.iflag.as<int>());
+  int h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, c.iflag.p, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  HIP_CHECK(hipStreamSynchronize(c.st));
+  if (h) throw Error(NUMERICAL, "input contains NaN or Inf");
+}
+
+}  // namespace ddamg

@@ -1,0 +1,170 @@
+// Host-side orchestration: device buffers, the multigrid hierarchy, Krylov
+// solvers and the context behind the C interface.
+#pragma once
+#include <chrono>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "ddamg.h"
+
+namespace ddamg {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  void alloc(size_t b) {
+    release();
+    if (b) {
+      hipError_t e = hipMalloc(&p, b);
+      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        p = nullptr;
+        throw Error(OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
+      }
+      HIP_CHECK(e);
+      bytes = b;
+    }
+  }
+  void ensure(size_t b) {
+    if (bytes < b) alloc(b);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { release(); }
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// per-kernel timing with event pairs recorded on the stream
+struct KernelTimer {
+  bool on = false;
+  hipStream_t st = nullptr;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  long count[4] = {0, 0, 0, 0};
+  double ms[4] = {0, 0, 0, 0};
+  hipEvent_t get();
+  void begin(int kind, hipEvent_t* a);
+  void end(int kind, hipEvent_t a);
+  void flush();
+  void reset();
+  ~KernelTimer();
+};
+
+struct Ctx;
+
+// Krylov workspace: basis vectors in precision R, all scalars FP64 on device
+template <class R>
+struct KrylovWS {
+  int m = 0;
+  long ld = 0;  // allocated length of one vector
+  bool flexible = false;
+  DevBuf V, Z, tmp, H, cs, sn, g, y, part, scal, resid;
+  double* h_resid = nullptr;  // pinned host mirror
+  int nwg = 0;
+  void init(int m_, long ld_, long N, bool flex);
+  ~KrylovWS();
+};
+
+using OpR64 = std::function<void(const cx<double>*, cx<double>*)>;
+using OpR32 = std::function<void(const cx<float>*, cx<float>*)>;
+
+struct KrylovResult {
+  int iters = 0;
+  double resid = 0;  // relative (true residual at exit)
+  bool converged = false;
+};
+
+// (F)GMRES(m): A, M act on vectors of length N (ld-strided basis); b, x may be
+// longer than N (only the first N entries take part).
+template <class R>
+KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(const cx<R>*, cx<R>*)>& A,
+                    const std::function<void(const cx<R>*, cx<R>*)>* M, const cx<R>* b, cx<R>* x, double tol,
+                    int max_iter, bool fixed, bool x_is_zero);
+
+struct CoarseGeo {
+  int L[4];
+  int n = 0;
+  int nsites = 0, neven = 0;
+  std::vector<int> order;  // lex -> ordered index
+  std::vector<int> lexof;  // ordered -> lex
+  DevBuf nbr;              // [nsites][8]
+  DevBuf d_order;          // lex -> ordered (device)
+  // aggregation to the next level
+  int ab[4] = {0, 0, 0, 0};
+  int nagg = 0, asz = 0;
+  DevBuf agg_sites;  // [nagg][asz] ordered indices of this level, aggregate = next level ordered index
+  DevBuf site_agg;   // [nsites] -> next-level ordered index
+  // SAP blocks (intermediate levels)
+  int sb[4] = {0, 0, 0, 0};
+  int nsblk = 0, ssz = 0, nsblk_col[2] = {0, 0};
+  DevBuf sap_sites;  // [nsblk][ssz], colour-0 blocks first
+  DevBuf sap_nbr;    // [nsblk][ssz][8]
+  CGeom cg() const { return CGeom{n, nsites, neven, nbr.as<int>()}; }
+};
+
+struct MGBase {
+  virtual ~MGBase() = default;
+  virtual void build(const void* const* vecs, int on_device, bool run_setup) = 0;
+  virtual void precond(const cx<double>* v, cx<double>* z) = 0;  // fine block layout FP64
+  virtual void set_mu(double mu) = 0;
+  virtual int nlev() const = 0;
+  virtual const CoarseGeo& geo(int l) const = 0;  // l >= 1
+  virtual void get_interp(int l, cx<double>* host) = 0;
+  virtual void restrict_host(int l, const cx<double>* in, cx<double>* out) = 0;
+  virtual void prolong_host(int l, const cx<double>* in, cx<double>* out) = 0;
+  virtual void get_coarse_op(int l, cx<double>* S, cx<double>* F) = 0;
+  virtual void apply_coarse_host(int l, const cx<double>* in, cx<double>* out) = 0;
+  virtual void coarse_sap_host(int l, const cx<double>* b, cx<double>* x, int iters) = 0;
+  virtual void coarse_solve_host(int l, const cx<double>* b, cx<double>* x) = 0;
+  long coarse_iters[4] = {0, 0, 0, 0};
+  long vcycles = 0;
+};
+
+struct Ctx {
+  hipStream_t st = nullptr;
+  Geom g{};
+  double kappa = 0, csw = 0, mu = 0, m0 = 0;
+  bool have_gauge = false, have_setup = false;
+  DevBuf U64, H64, M64;        // fine operator, FP64
+  DevBuf U32, H32, M32;        // FP32 copies
+  DevBuf U16;                  // 16-bit link copy
+  int u16_kind = -1;           // DDAMG_FP16 or DDAMG_BF16
+  bool have_32 = false;
+  DevBuf lex;                  // host-layout FP64 staging (one fine field)
+  DevBuf f64a, f64b, f64c;     // fine FP64 block-layout vectors
+  DevBuf f32a, f32b;           // fine FP32 block-layout vectors
+  DevBuf iflag;                // int error flag
+  ddamg_params p{};
+  std::unique_ptr<MGBase> mg;
+  KrylovWS<double> outer;
+  KernelTimer timer;
+  std::string err;
+
+  long fine_len() const { return g.V * 12; }
+  void ensure_32();
+  void ensure_16(int kind);
+  void rebuild_odd_inverse();
+  void sync() { HIP_CHECK(hipStreamSynchronize(st)); }
+  // fine FP64 operator D(tw) in block layout
+  void dirac64(const cx<double>* in, cx<double>* out, double tw);
+  // host/device lex FP64 field -> block layout
+  void upload_fine(const void* src, int on_device, cx<double>* dst64);
+  void download_fine(const cx<double>* src64, void* dst, int on_device);
+};
+
+std::unique_ptr<MGBase> make_mg(Ctx& c);
+
+}  // namespace ddamg

@@ -1,0 +1,344 @@
+"""ctypes binding of libddamg.so (declared in include/ddamg.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  Arrays may be numpy complex128 arrays (host) or torch complex128
+CUDA tensors (device, used on the context stream).  There is no CPU fallback:
+if the shared library is missing this module raises at import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddamg.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ddamg.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, NOT_CONVERGED, INVALID_ARG, BAD_STATE, HIP_ERROR, OUT_OF_MEMORY, NUMERICAL = 0, 1, -1, -2, -3, -4, -5
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int),
+        ("block", (ctypes.c_int * 4) * 3),
+        ("nvec", ctypes.c_int * 3),
+        ("coarse_sap_block", ctypes.c_int * 4),
+        ("sap_pre", ctypes.c_int),
+        ("sap_post", ctypes.c_int),
+        ("mr_steps", ctypes.c_int),
+        ("coarse_sap_post", ctypes.c_int),
+        ("coarse_mr_steps", ctypes.c_int),
+        ("init_sap_iters", ctypes.c_int),
+        ("setup_iters", ctypes.c_int),
+        ("coarse_setup_iters", ctypes.c_int),
+        ("coarse_mu_factor", ctypes.c_double),
+        ("restart", ctypes.c_int),
+        ("max_iter", ctypes.c_int),
+        ("inter_restart", ctypes.c_int),
+        ("inter_max_iter", ctypes.c_int),
+        ("inter_tol", ctypes.c_double),
+        ("coarse_restart", ctypes.c_int),
+        ("coarse_max_iter", ctypes.c_int),
+        ("coarse_tol", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("fixed_iters", ctypes.c_int),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("resid", ctypes.c_double),
+        ("coarse_iters", ctypes.c_long * 4),
+        ("vcycles", ctypes.c_long),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return dict(iters=self.iters, converged=bool(self.converged), resid=self.resid,
+                    coarse_iters=list(self.coarse_iters), vcycles=self.vcycles, seconds=self.seconds)
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_SIGS = {
+    "ddamg_default_params": (None, [ctypes.POINTER(Params)]),
+    "ddamg_create": (_i, [ctypes.POINTER(_i), ctypes.POINTER(_i), _d, _d, _d, _vp, ctypes.POINTER(_vp)]),
+    "ddamg_destroy": (None, [_vp]),
+    "ddamg_last_error": (ctypes.c_char_p, [_vp]),
+    "ddamg_set_gauge": (_i, [_vp, _vp, _i]),
+    "ddamg_set_clover": (_i, [_vp, _vp, _i]),
+    "ddamg_get_clover": (_i, [_vp, _vp]),
+    "ddamg_set_mu": (_i, [_vp, _d]),
+    "ddamg_setup": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
+    "ddamg_set_test_vectors": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
+    "ddamg_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(Stats), _i]),
+    "ddamg_apply_dirac": (_i, [_vp, _vp, _vp, _i, _i, _i]),
+    "ddamg_sap": (_i, [_vp, _vp, _vp, _i, _i, _i, _i]),
+    "ddamg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "ddamg_get_interpolation": (_i, [_vp, _i, _vp]),
+    "ddamg_restrict": (_i, [_vp, _i, _vp, _vp]),
+    "ddamg_prolong": (_i, [_vp, _i, _vp, _vp]),
+    "ddamg_get_coarse_op": (_i, [_vp, _i, _vp, _vp]),
+    "ddamg_apply_coarse": (_i, [_vp, _i, _vp, _vp]),
+    "ddamg_coarse_sap": (_i, [_vp, _i, _vp, _vp, _i]),
+    "ddamg_coarse_solve": (_i, [_vp, _i, _vp, _vp]),
+    "ddamg_vcycle": (_i, [_vp, _vp, _vp]),
+    "ddamg_bench_dirac": (_i, [_vp, _i, _i]),
+    "ddamg_timing": (_i, [_vp, _i]),
+    "ddamg_timing_query": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+class DDAMGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    _lib.ddamg_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "block":
+            for l, b in enumerate(v):
+                for d in range(4):
+                    p.block[l][d] = int(b[d])
+        elif k in ("nvec", "coarse_sap_block"):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = int(x)
+        elif k == "precision":
+            setattr(p, k, PRECISIONS[v] if isinstance(v, str) else int(v))
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """(pointer, on_device) of a numpy array or a torch tensor."""
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), int(a.is_cuda)
+    if not (isinstance(a, np.ndarray) and a.flags["C_CONTIGUOUS"]):
+        raise ValueError("array must be C-contiguous")
+    return ctypes.c_void_p(a.ctypes.data), 0
+
+
+def _c128(a):
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.complex128:
+            raise TypeError("tensor must be complex128")
+        return a.contiguous()
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+class DDAMG:
+    """One lattice, one gauge field, one multigrid hierarchy.
+
+    dims = (T, Z, Y, X); block = fine SAP block and first aggregate.
+    stream: a hipStream_t as int (torch.cuda.current_stream().cuda_stream),
+    or None for the null stream."""
+
+    def __init__(self, dims, block, kappa, csw, mu, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.block = tuple(int(b) for b in block)
+        self.V = int(np.prod(self.dims))
+        d = (ctypes.c_int * 4)(*self.dims)
+        b = (ctypes.c_int * 4)(*self.block)
+        h = ctypes.c_void_p()
+        st = _lib.ddamg_create(d, b, float(kappa), float(csw), float(mu),
+                               ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if st != OK:
+            raise DDAMGError(st, "ddamg_create failed")
+        self._h = h
+        self.params = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ddamg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, allow=(OK,)):
+        if st not in allow:
+            raise DDAMGError(st, _lib.ddamg_last_error(self._h).decode())
+        return st
+
+    # ---- setup ------------------------------------------------------------
+    def set_gauge(self, U):
+        U = _c128(U)
+        p, dev = _ptr(U)
+        self._check(_lib.ddamg_set_gauge(self._h, p, dev))
+        self._keep = U
+
+    def set_clover(self, A=None):
+        if A is None:
+            self._check(_lib.ddamg_set_clover(self._h, None, 0))
+            return
+        A = _c128(A)
+        p, dev = _ptr(A)
+        self._check(_lib.ddamg_set_clover(self._h, p, dev))
+
+    def get_clover(self):
+        out = np.empty(self.dims + (2, 6, 6), dtype=np.complex128)
+        self._check(_lib.ddamg_get_clover(self._h, _ptr(out)[0]))
+        return out
+
+    def set_mu(self, mu):
+        self._check(_lib.ddamg_set_mu(self._h, float(mu)))
+
+    def _vec_ptrs(self, vecs):
+        arrs = [_c128(v) for v in vecs]
+        ptrs = (ctypes.c_void_p * 3)()
+        dev = 0
+        for i, a in enumerate(arrs):
+            p, dev = _ptr(a)
+            ptrs[i] = p
+        return arrs, ptrs, dev
+
+    def setup(self, params: Params, init_vectors):
+        arrs, ptrs, dev = self._vec_ptrs(init_vectors)
+        self._check(_lib.ddamg_setup(self._h, ctypes.byref(params), ptrs, dev))
+        self.params = params
+
+    def set_test_vectors(self, params: Params, vectors):
+        arrs, ptrs, dev = self._vec_ptrs(vectors)
+        self._check(_lib.ddamg_set_test_vectors(self._h, ctypes.byref(params), ptrs, dev))
+        self.params = params
+
+    # ---- solve ------------------------------------------------------------
+    def solve(self, b, tol=1e-10, x=None, allow_not_converged=False):
+        b = _c128(b)
+        nrhs = 1 if b.ndim == 6 else b.shape[0]
+        if x is None:
+            if _is_torch(b):
+                import torch
+                x = torch.empty_like(b)
+            else:
+                x = np.empty_like(b)
+        pb, dev = _ptr(b)
+        px, _ = _ptr(x)
+        st = Stats()
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        self._check(_lib.ddamg_solve(self._h, pb, px, nrhs, float(tol), ctypes.byref(st), dev), allow)
+        return x, st.as_dict()
+
+    # ---- single operators ---------------------------------------------------
+    def apply_dirac(self, psi, sign=+1, precision="fp64"):
+        psi = _c128(psi)
+        out = np.empty_like(psi) if not _is_torch(psi) else psi.new_empty(psi.shape)
+        pi, dev = _ptr(psi)
+        self._check(_lib.ddamg_apply_dirac(self._h, pi, _ptr(out)[0], int(sign), PRECISIONS[precision], dev))
+        return out
+
+    def sap(self, b, x0, iters, mr_steps=4, precision="fp64"):
+        b = _c128(b)
+        x = np.array(x0, dtype=np.complex128, copy=True)
+        self._check(_lib.ddamg_sap(self._h, _ptr(b)[0], _ptr(x)[0], int(iters), int(mr_steps),
+                                   PRECISIONS[precision], 0))
+        return x
+
+    def level_info(self, level):
+        d = (ctypes.c_int * 4)()
+        n = ctypes.c_int()
+        self._check(_lib.ddamg_level_info(self._h, int(level), d, ctypes.byref(n)))
+        return tuple(d), n.value
+
+    def _level_shape(self, level):
+        d, n = self.level_info(level)
+        return tuple(d) + ((4, 3) if level == 0 else (n,))
+
+    def get_interpolation(self, level):
+        nv = self.params.nvec[level]
+        out = np.empty((nv,) + self._level_shape(level), dtype=np.complex128)
+        self._check(_lib.ddamg_get_interpolation(self._h, int(level), _ptr(out)[0]))
+        return out
+
+    def restrict(self, level, r):
+        r = _c128(r)
+        out = np.empty(self._level_shape(level + 1), dtype=np.complex128)
+        self._check(_lib.ddamg_restrict(self._h, int(level), _ptr(r)[0], _ptr(out)[0]))
+        return out
+
+    def prolong(self, level, e):
+        e = _c128(e)
+        out = np.empty(self._level_shape(level), dtype=np.complex128)
+        self._check(_lib.ddamg_prolong(self._h, int(level), _ptr(e)[0], _ptr(out)[0]))
+        return out
+
+    def get_coarse_op(self, level):
+        d, n = self.level_info(level)
+        S = np.empty(tuple(d) + (n, n), dtype=np.complex128)
+        F = np.empty((4,) + tuple(d) + (n, n), dtype=np.complex128)
+        self._check(_lib.ddamg_get_coarse_op(self._h, int(level), _ptr(S)[0], _ptr(F)[0]))
+        return S, F
+
+    def apply_coarse(self, level, y):
+        y = _c128(y)
+        out = np.empty_like(y)
+        self._check(_lib.ddamg_apply_coarse(self._h, int(level), _ptr(y)[0], _ptr(out)[0]))
+        return out
+
+    def coarse_sap(self, level, b, x0, iters):
+        b = _c128(b)
+        x = np.array(x0, dtype=np.complex128, copy=True)
+        self._check(_lib.ddamg_coarse_sap(self._h, int(level), _ptr(b)[0], _ptr(x)[0], int(iters)))
+        return x
+
+    def coarse_solve(self, level, b):
+        b = _c128(b)
+        x = np.empty_like(b)
+        self._check(_lib.ddamg_coarse_solve(self._h, int(level), _ptr(b)[0], _ptr(x)[0]))
+        return x
+
+    def vcycle(self, v):
+        v = _c128(v)
+        out = np.empty_like(v)
+        self._check(_lib.ddamg_vcycle(self._h, _ptr(v)[0], _ptr(out)[0]))
+        return out
+
+    # ---- measurement ---------------------------------------------------------
+    def bench_dirac(self, napply, precision="fp64"):
+        self._check(_lib.ddamg_bench_dirac(self._h, PRECISIONS[precision], int(napply)))
+
+    def timing(self, enable):
+        self._check(_lib.ddamg_timing(self._h, int(bool(enable))))
+
+    def timing_query(self, kind):
+        c = ctypes.c_long()
+        ms = ctypes.c_double()
+        self._check(_lib.ddamg_timing_query(self._h, int(kind), ctypes.byref(c), ctypes.byref(ms)))
+        return c.value, ms.value

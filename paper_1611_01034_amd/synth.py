@@ -29,19 +29,27 @@ _GM[7][0, 0] = _GM[7][1, 1] = 1 / np.sqrt(3)
 _GM[7][2, 2] = -2 / np.sqrt(3)
 
 
-def su3_near_identity(n: int, eps: float, rng: np.random.Generator) -> np.ndarray:
+def su3_near_identity(n: int, eps: float, rng: np.random.Generator, chunk: int = 1 << 22) -> np.ndarray:
     """n matrices U = exp(i*eps*H), H = sum_a h_a lambda_a / 2 with h_a ~ N(0,1).
 
-    The exponential is taken through the eigendecomposition of the Hermitian H,
-    and the result is re-projected onto det U = 1 (removes rounding drift).
+    The matrix exponential is taken in FP64 with torch.matrix_exp on the CPU
+    (batched, multithreaded) in fixed-size chunks, so a field is a pure
+    function of (n, eps, seed).  exp of a traceless Hermitian matrix times i
+    lies in SU(3) up to rounding; the determinant phase is divided out.
     """
-    h = rng.standard_normal((n, 8))
-    H = np.einsum("na,aij->nij", h, _GM) * 0.5
-    w, v = np.linalg.eigh(H)
-    U = np.einsum("nij,nj,nkj->nik", v, np.exp(1j * eps * w), v.conj())
-    det = np.linalg.det(U)
-    U = U / (det ** (1.0 / 3.0))[:, None, None]
-    return U
+    import torch
+
+    out = np.empty((n, 3, 3), dtype=np.complex128)
+    for a in range(0, n, chunk):
+        m = min(chunk, n - a)
+        h = rng.standard_normal((m, 8))
+        H = np.einsum("na,aij->nij", h, _GM) * 0.5
+        U = torch.matrix_exp(torch.from_numpy(1j * eps * H)).numpy()
+        det = (U[:, 0, 0] * (U[:, 1, 1] * U[:, 2, 2] - U[:, 1, 2] * U[:, 2, 1])
+               - U[:, 0, 1] * (U[:, 1, 0] * U[:, 2, 2] - U[:, 1, 2] * U[:, 2, 0])
+               + U[:, 0, 2] * (U[:, 1, 0] * U[:, 2, 1] - U[:, 1, 1] * U[:, 2, 0]))
+        out[a:a + m] = U / (det ** (1.0 / 3.0))[:, None, None]
+    return out
 
 
 def gauge_field(dims, eps: float, seed: int) -> np.ndarray:

@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C interface against the CPU oracle.
+
+Tolerances: FP64 operator applies <= 1e-12 relative (element by element over
+the whole field); FP64 compositions of a few operators (SAP, V-cycle with
+fixed iteration counts) <= 1e-10; FP32 storage: the relative error of one
+apply is bounded by a few units of 2^-24 times the number of terms summed,
+<= 2e-6; FP16 / BF16 links: <= 4e-3 / 3e-2.
+"""
+import numpy as np
+import pytest
+
+from oracle import aggregation as agg
+from oracle import coarse, dirac, mg, sap, stencil
+from paper_1611_01034_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KAPPA, CSW, MU = 0.13729, 1.57551, 0.0009
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+@pytest.fixture(scope="module")
+def dd():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_01034_amd import ddamg
+    return ddamg
+
+
+def make(dd, dims, block, seed=1001, mu=MU, eps=0.3):
+    U = synth.gauge_field(dims, eps, seed)
+    ctx = dd.DDAMG(dims, block, KAPPA, CSW, mu)
+    ctx.set_gauge(U)
+    return ctx, dirac.WilsonClover(U, KAPPA, CSW, mu), U
+
+
+CASES = [((4, 4, 4, 4), (2, 2, 2, 2)), ((4, 8, 4, 12), (2, 2, 2, 2)), ((8, 8, 8, 16), (4, 4, 4, 4)),
+         ((8, 4, 8, 8), (4, 2, 4, 2))]
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+def test_clover_term(dd, dims, block):
+    ctx, op, _ = make(dd, dims, block)
+    got = ctx.get_clover()
+    want = dirac.clover_blocks(op.A)
+    assert np.abs(got - want).max() < 1e-13
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+@pytest.mark.parametrize("sign", [1, -1])
+def test_dirac_fp64(dd, dims, block, sign):
+    ctx, op, _ = make(dd, dims, block, mu=0.05)
+    psi = synth.spinor(dims, 7)
+    got = ctx.apply_dirac(psi, sign=sign)
+    want = op.apply(psi, sign * op.mu)
+    assert rel(got, want) < 1e-12
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("fp16", 4e-3), ("bf16", 3e-2)])
+def test_dirac_reduced(dd, prec, tol):
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, op, _ = make(dd, dims, block)
+    psi = synth.spinor(dims, 8)
+    err = rel(ctx.apply_dirac(psi, precision=prec), op.apply(psi))
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+def test_sap_fp64(dd, dims, block):
+    ctx, op, _ = make(dd, dims, block, mu=0.02)
+    fl = stencil.FineLevel(op)
+    b = synth.spinor(dims, 9)
+    x0 = synth.spinor(dims, 10)
+    got = ctx.sap(b, x0, iters=2, mr_steps=4)
+    want = sap.sap(fl, b.reshape(dims + (12,)), x0.reshape(dims + (12,)), block, 4, 2)
+    assert rel(got.reshape(dims + (12,)), want) < 1e-11
+
+
+def test_sap_fp32(dd):
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, op, _ = make(dd, dims, block)
+    fl = stencil.FineLevel(op)
+    b = synth.spinor(dims, 11)
+    x0 = np.zeros_like(b)
+    got = ctx.sap(b, x0, iters=1, mr_steps=4, precision="fp32")
+    want = sap.sap(fl, b.reshape(dims + (12,)), x0.reshape(dims + (12,)), block, 4, 1)
+    assert rel(got.reshape(dims + (12,)), want) < 1e-5
+
+
+def _two_level(dd, dims, block, nv, delta=1.0, mu=MU, **kw):
+    ctx, op, U = make(dd, dims, block, mu=mu)
+    V = synth.gaussian((nv,) + dims + (12,), 1501)
+    p = dd.default_params(levels=2, block=[block], nvec=[nv], coarse_mu_factor=delta, **kw)
+    ctx.set_test_vectors(p, [V.reshape((nv,) + dims + (4, 3))])
+    op_params = mg.Params(levels=2, blocks=[block], nvec=[nv], delta=delta,
+                          coarse_max_iter=p.coarse_max_iter, coarse_restart=p.coarse_restart,
+                          coarse_tol=p.coarse_tol, sap_post=p.sap_post, mr_steps=p.mr_steps,
+                          fixed=bool(p.fixed_iters))
+    h = mg.Hierarchy(op, op_params).set_test_vectors([V])
+    return ctx, op, h, V
+
+
+@pytest.mark.parametrize("dims,block,nv", [((4, 4, 4, 4), (2, 2, 2, 2), 8), ((8, 8, 8, 16), (4, 4, 4, 4), 20),
+                                          ((8, 4, 8, 8), (4, 2, 4, 2), 12)])
+def test_interpolation_transfer_and_coarse_operator(dd, dims, block, nv):
+    ctx, op, h, V = _two_level(dd, dims, block, nv, delta=5.0)
+    Q = ctx.get_interpolation(0).reshape((nv,) + dims + (12,))
+    assert rel(Q, h.levels[0].Q) < 1e-12
+    r = synth.gaussian(dims + (12,), 21)
+    rc = ctx.restrict(0, r.reshape(dims + (4, 3)))
+    assert rel(rc, agg.restrict(h.levels[0].Q, r, block)) < 1e-12
+    e = synth.gaussian(rc.shape, 22)
+    x = ctx.prolong(0, e).reshape(dims + (12,))
+    assert rel(x, agg.prolong(h.levels[0].Q, e, block)) < 1e-12
+    S, F = ctx.get_coarse_op(1)
+    Dc = h.levels[1].op
+    assert rel(S, Dc.S) < 1e-12
+    assert rel(F, Dc.F) < 1e-12
+    y = synth.gaussian(Dc.dims + (Dc.n,), 23)
+    assert rel(ctx.apply_coarse(1, y), Dc.apply(y)) < 1e-12
+
+
+def test_coarsest_solve_fixed_iterations(dd):
+    dims, block, nv = (8, 8, 8, 16), (4, 4, 4, 4), 8
+    ctx, op, h, V = _two_level(dd, dims, block, nv, delta=3.0, fixed_iters=1, coarse_max_iter=40,
+                               coarse_restart=15)
+    Dc = h.levels[1].op
+    b = synth.gaussian(Dc.dims + (Dc.n,), 31)
+    got = ctx.coarse_solve(1, b)
+    want = h.coarse_solve(1, b)
+    assert rel(got, want) < 1e-10
+
+
+def test_vcycle_fixed_iterations(dd):
+    dims, block, nv = (8, 8, 8, 16), (4, 4, 4, 4), 8
+    ctx, op, h, V = _two_level(dd, dims, block, nv, delta=5.0, fixed_iters=1, coarse_max_iter=20,
+                               coarse_restart=10)
+    v = synth.gaussian(dims + (12,), 41)
+    got = ctx.vcycle(v.reshape(dims + (4, 3))).reshape(dims + (12,))
+    want = h.vcycle(0, v)
+    assert rel(got, want) < 1e-10
+
+
+def test_solve_c1_matches_dense_lu(dd):
+    # 4^4, eps 0.3, mu 0.0009, delta 1, Nv 8, 2^4 aggregates, 3 setup iterations
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    ctx, op, _ = make(dd, dims, block)
+    V0 = synth.spinor(dims, 1501, nvec=8)
+    ctx.setup(dd.default_params(levels=2, block=[block], nvec=[8], setup_iters=3), [V0])
+    b = synth.spinor(dims, 1101)
+    x, st = ctx.solve(b, tol=1e-10)
+    r = rel(op.apply(x), b)
+    assert st["converged"] and r <= 1e-10
+    D = op.dense()
+    xs = np.linalg.solve(D, b.reshape(-1)).reshape(b.shape)
+    sv = np.linalg.svd(D, compute_uv=False)
+    assert rel(x, xs) <= (sv.max() / sv.min()) * 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_solve_reduced_precision_reaches_fp64_tolerance(dd, prec):
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, op, _ = make(dd, dims, block)
+    V0 = synth.spinor(dims, 2501, nvec=12)
+    ctx.setup(dd.default_params(levels=2, block=[block], nvec=[12], setup_iters=2, precision=prec,
+                                coarse_mu_factor=5.0), [V0])
+    b = synth.spinor(dims, 2101)
+    x, st = ctx.solve(b, tol=1e-10)
+    assert st["converged"] and rel(op.apply(x), b) <= 1e-10
+
+
+def test_minus_mu_reuses_setup(dd):
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, op, _ = make(dd, dims, block)
+    V0 = synth.spinor(dims, 2501, nvec=12)
+    ctx.setup(dd.default_params(levels=2, block=[block], nvec=[12], setup_iters=2, coarse_mu_factor=3.0), [V0])
+    b = synth.spinor(dims, 2102)
+    x1, s1 = ctx.solve(b, tol=1e-10)
+    ctx.set_mu(-MU)
+    x2, s2 = ctx.solve(b, tol=1e-10)
+    assert rel(op.apply(x1, MU), b) <= 1e-10 and rel(op.apply(x2, -MU), b) <= 1e-10
+    assert abs(s1["iters"] - s2["iters"]) <= max(2, 0.2 * s1["iters"])
+
+
+# ------------------------------------------------------------------ 3 levels
+
+def _three_level(dd, **kw):
+    dims, b0, b1 = (8, 8, 8, 8), (2, 2, 2, 2), (2, 2, 2, 2)
+    nv0, nv1 = 6, 8
+    ctx, op, U = make(dd, dims, b0)
+    V0 = synth.gaussian((nv0,) + dims + (12,), 3501)
+    cd = agg.coarse_dims(dims, b0)
+    V1 = synth.gaussian((nv1,) + cd + (2 * nv0,), 3502)
+    p = dd.default_params(levels=3, block=[b0, b1], nvec=[nv0, nv1], coarse_mu_factor=5.0, **kw)
+    ctx.set_test_vectors(p, [V0.reshape((nv0,) + dims + (4, 3)), V1])
+    op_params = mg.Params(levels=3, blocks=[b0, b1], nvec=[nv0, nv1], delta=5.0, fixed=bool(p.fixed_iters),
+                          coarse_max_iter=p.coarse_max_iter, coarse_restart=p.coarse_restart,
+                          inter_max_iter=p.inter_max_iter, inter_restart=p.inter_restart,
+                          coarse_sap_post=p.coarse_sap_post, coarse_mr_steps=p.coarse_mr_steps)
+    h = mg.Hierarchy(op, op_params).set_test_vectors([V0, V1])
+    return ctx, op, h
+
+
+def test_three_level_operators(dd):
+    ctx, op, h = _three_level(dd)
+    for l in (1, 2):
+        S, F = ctx.get_coarse_op(l)
+        assert rel(S, h.levels[l].op.S) < 1e-12
+        assert rel(F, h.levels[l].op.F) < 1e-12
+    Q1 = ctx.get_interpolation(1)
+    assert rel(Q1, h.levels[1].Q) < 1e-12
+    st1 = h.levels[1].op
+    b = synth.gaussian(st1.dims + (st1.n,), 51)
+    x0 = synth.gaussian(st1.dims + (st1.n,), 52)
+    got = ctx.coarse_sap(1, b, x0, 2)
+    want = sap.sap(st1, b, x0, (2, 2, 2, 2), h.p.coarse_mr_steps, 2, schur=False)
+    assert rel(got, want) < 1e-11
+
+
+def test_three_level_vcycle_fixed(dd):
+    ctx, op, h = _three_level(dd, fixed_iters=1, coarse_max_iter=8, coarse_restart=8, inter_max_iter=3,
+                              inter_restart=3)
+    v = synth.gaussian(op.dims + (12,), 61)
+    got = ctx.vcycle(v.reshape(op.dims + (4, 3))).reshape(op.dims + (12,))
+    want = h.vcycle(0, v)
+    assert rel(got, want) < 1e-10
