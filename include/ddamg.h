@@ -181,10 +181,12 @@ int ddamg_vcycle(ddamg_ctx* ctx, const void* in, void* out);
  * library's own layout (inputs already in HBM), on the context stream;
  * returns immediately after enqueueing. */
 int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply);
-/* Per-kernel timing with HIP events on the context stream (kind: 0 = D(mu)
- * fine apply, 1 = fine SAP sweep, 2 = coarse operator apply, 3 = restriction
- * + prolongation).  enable = 1 starts recording, 0 stops; query returns launch
- * count and total milliseconds so far (synchronises the stream). */
+/* Per-kernel timing with HIP events on the context stream.  kind: 0 = FP64
+ * D(mu) (outer operator), 1 = fine SAP colour sweep, 2 = coarse operator
+ * apply (intermediate levels, residuals included), 3 = restriction and
+ * prolongation, 4 = reduced-precision fine D(mu), 5 = coarsest odd-even Schur
+ * apply.  enable = 1 resets and starts recording, 0 stops; query returns the
+ * launch count and total milliseconds so far (synchronises the stream). */
 int ddamg_timing(ddamg_ctx* ctx, int enable);
 int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms);
 

@@ -229,3 +229,25 @@ def plane_wave_symbol(p, m0: float, mu: float):
     for d in range(4):
         M = M + 1j * np.sin(p[d]) * GAMMA[d]
     return M + 1j * mu * GAMMA5
+
+
+def apply_at_sites(U, psi, kappa, csw, mu, sites):
+    """(D(mu) psi)(x) at a few sites of an arbitrarily large lattice.
+
+    For each site the 3^4 neighbourhood (offsets -1..1 in every direction,
+    periodic in the big lattice) of links and spinors is gathered and the
+    operator is applied on that patch; at the patch centre every term of D
+    (site term with its clover leaves, the eight hops) only touches sites
+    inside the patch, so the centre value is the exact one.  U and psi may
+    be numpy arrays or anything indexable the same way (e.g. memory maps).
+    """
+    dims = U.shape[:4]
+    out = []
+    for x in sites:
+        idx = [np.array([(x[d] + o) % dims[d] for o in (-1, 0, 1)]) for d in range(4)]
+        ix = np.ix_(*idx)
+        Up = np.asarray(U[ix])
+        pp = np.asarray(psi[ix])
+        op = WilsonClover(Up, kappa, csw, mu)
+        out.append(op.apply(pp)[1, 1, 1, 1])
+    return np.stack(out)

@@ -181,6 +181,7 @@ int ddamg_create(const int dims[4], const int block[4], double kappa, double csw
     }
     g.bs = bs;
     g.half = bs / 2;
+    g.ndir = 4;
     g.nblocks = g.nb[0] * g.nb[1] * g.nb[2] * g.nb[3];
     c.kappa = kappa;
     c.csw = csw;
@@ -361,6 +362,10 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
       c.download_fine(c.f64b.as<cx<double>>(), xs, on_device);
     }
     c.sync();
+    // the outer Krylov basis is the largest allocation; give it back between solves
+    c.outer.V.release();
+    c.outer.Z.release();
+    c.outer.tmp.release();
     if (stats) {
       stats->iters = total_it;
       stats->converged = all_conv ? 1 : 0;
@@ -570,11 +575,11 @@ int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply) {
       const cx<float>* in = (i & 1) ? c.f32b.as<cx<float>>() : c.f32a.as<cx<float>>();
       cx<float>* out = (i & 1) ? c.f32a.as<cx<float>>() : c.f32b.as<cx<float>>();
       hipEvent_t a;
-      c.timer.begin(0, &a);
+      c.timer.begin(4, &a);
       if (precision == DDAMG_FP32) launch_dirac<float, float>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
       else if (precision == DDAMG_FP16) launch_dirac<float, f16>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
       else launch_dirac<float, bf16>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
-      c.timer.end(0, a);
+      c.timer.end(4, a);
     }
     return DDAMG_OK;
   });
@@ -597,7 +602,7 @@ int ddamg_timing(ddamg_ctx* ctx, int enable) {
 }
 
 int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms) {
-  if (!ctx || kind < 0 || kind > 3) return DDAMG_INVALID_ARG;
+  if (!ctx || kind < 0 || kind >= KernelTimer::NKIND) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {
     Ctx& c = ctx->c;
     c.timer.flush();

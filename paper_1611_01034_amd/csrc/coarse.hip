@@ -275,9 +275,9 @@ void launch_prolong_coarse(int n, int Nv, int nsites, const int* site_agg, const
 // ---------------------------------------------------------------------------
 // block orthonormalisation on a coarse level (CGS2, FP64), one workgroup per
 // (aggregate, half), one thread per row (site j, component c of the half)
-template <class RO>
+template <class RI, class RO>
 __global__ void __launch_bounds__(1024) k_qr_coarse(int n, int Nv, int asz, const int* __restrict__ agg_sites,
-                                                    const cx<double>* __restrict__ V, long vstride,
+                                                    const cx<RI>* __restrict__ V, long vstride,
                                                     RO* __restrict__ Qraw, long qstride, int* __restrict__ fail) {
   cx<RO>* Qout = reinterpret_cast<cx<RO>*>(Qraw);
   __shared__ double red[32][16][2];
@@ -302,7 +302,11 @@ __global__ void __launch_bounds__(1024) k_qr_coarse(int n, int Nv, int asz, cons
     }
   };
   for (int i = 0; i < Nv; ++i) {
-    cx<double> v = act ? V[(long)i * vstride + idx] : mk(0.0, 0.0);
+    cx<double> v = mk(0.0, 0.0);
+    if (act) {
+      cx<RI> vi = V[(long)i * vstride + idx];
+      v = mk<double>(vi.re, vi.im);
+    }
     reduce(norm2(v), 0.0, 0);
     __syncthreads();
     double nrm0 = 0;
@@ -346,12 +350,12 @@ __global__ void __launch_bounds__(1024) k_qr_coarse(int n, int Nv, int asz, cons
     if (act) Qout[(long)i * qstride + idx] = mk<RO>((RO)(inv * v.re), (RO)(inv * v.im));
   }
 }
-template <class RO>
-void launch_qr_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<double>* V, long vstride,
+template <class RI, class RO>
+void launch_qr_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<RI>* V, long vstride,
                       cx<RO>* Q, long qstride, int* fail, hipStream_t st) {
   int rows = asz * (n / 2);
   int threads = ((rows + 63) / 64) * 64;
-  hipLaunchKernelGGL(k_qr_coarse<RO>, dim3(2 * nagg), dim3(threads), 0, st, n, Nv, asz, agg_sites, V, vstride,
+  hipLaunchKernelGGL((k_qr_coarse<RI, RO>), dim3(2 * nagg), dim3(threads), 0, st, n, Nv, asz, agg_sites, V, vstride,
                      (RO*)Q, qstride, fail);
 }
 
@@ -666,8 +670,8 @@ INST_RS(float, bf16)
                                           cx<R>*, hipStream_t);                                                    \
   template void launch_prolong_coarse<R>(int, int, int, const int*, const cx<R>*, long, const cx<R>*, cx<R>*, int, \
                                          hipStream_t);                                                             \
-  template void launch_qr_coarse<R>(int, int, int, int, const int*, const cx<double>*, long, cx<R>*, long, int*,   \
-                                    hipStream_t);                                                                  \
+  template void launch_qr_coarse<R, R>(int, int, int, int, const int*, const cx<R>*, long, cx<R>*, long, int*,   \
+                                       hipStream_t);                                                               \
   template void launch_assemble_coarse<R>(const CGeom&, int, int, const int*, const int*, const cx<double>*,       \
                                           const cx<R>*, long, cx<double>*, cx<double>*, hipStream_t);              \
   template void launch_coarse_odd_inverse<R>(const CGeom&, const cx<double>*, double, cx<double>*, cx<R>*,         \

@@ -7,9 +7,7 @@
 // sites are stored parity-major: slot = parity*half + (lexicographic local
 // index >> 1), parity = (t+z+y+x) mod 2 (block origins are even, so local and
 // global parity agree).  A field with C complex components per site is stored
-// component-major inside each block: element (B, c, slot) at
-// (B*C + c)*bs + slot, so a wavefront reading one component of 64
-// consecutive slots reads one contiguous segment.
+// tiled inside each block (see fidx below).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -92,6 +90,15 @@ template <> __device__ __forceinline__ b2 st_cvt<bf16, double>(cx<double> v) {
 }
 
 // ---- fine-lattice geometry -------------------------------------------------
+// Inside a block, sites are grouped in tiles of TILE consecutive slots and a
+// field is stored tile by tile, component-major inside a tile: component c of
+// slot s of block B (field with C components) sits at
+//   ((B * bs/TILE + s/TILE) * C + c) * TILE + s % TILE.
+// A wavefront reading one component of 64 consecutive slots reads 64/TILE
+// contiguous segments of TILE elements (FP64: 128 B, one cache line each),
+// and the components of one site are a compile-time stride apart, so one
+// address plus immediate offsets serves a whole site.
+constexpr int TILE = 8;
 struct Geom {
   int L[4];      // extents T,Z,Y,X
   int b[4];      // block extents
@@ -100,6 +107,7 @@ struct Geom {
   int bs;        // sites per block
   int half;      // bs/2
   long V;        // sites
+  int ndir;      // 4 (kept as data so loops over directions stay rolled)
 };
 
 // local coordinates of a slot
@@ -162,6 +170,15 @@ __host__ __device__ __forceinline__ void neighbour(const Geom& g, int B, int s, 
   if (x[mu] == g.L[mu]) x[mu] = 0;
   if (x[mu] < 0) x[mu] = g.L[mu] - 1;
   coords_site(g, x, Bn, sn);
+}
+
+// index of component 0 of slot s of block B, field with C components
+__host__ __device__ __forceinline__ long fidx(const Geom& g, int B, int s, int C) {
+  return ((long)B * (g.bs / TILE) + (s / TILE)) * C * TILE + (s % TILE);
+}
+// same for a field that lives on the odd slots only (io = s - half)
+__host__ __device__ __forceinline__ long oidx(const Geom& g, int B, int io, int C) {
+  return ((long)B * (g.half / TILE) + (io / TILE)) * C * TILE + (io % TILE);
 }
 
 __host__ __device__ __forceinline__ long lex_index(const Geom& g, const int x[4]) {

@@ -17,6 +17,7 @@
 // phases in {1, i, -1, -i} and a spin permutation (tables below).
 #include "kernels.hpp"
 
+
 namespace ddamg {
 
 // phase codes: 0:+1 1:+i 2:-1 3:-i
@@ -86,23 +87,23 @@ __device__ __forceinline__ void hop_accum(int mu, const cx<R> psi[12], const cx<
 template <class R, class S>
 __device__ __forceinline__ void load_link(const typename store_traits<S>::elem* U, const Geom& g, int B, int s, int mu,
                                           cx<R> u[9]) {
-  long base = ((long)(B * 4 + mu) * 9) * g.bs + s;
+  long base = fidx(g, B, s, 36) + (long)mu * 9 * TILE;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) u[k] = ld<R, S>(U, base + (long)k * g.bs);
+  for (int k = 0; k < 9; ++k) u[k] = ld<R, S>(U, base + (long)k * TILE);
 }
 
 template <class R>
 __device__ __forceinline__ void load_spinor(const cx<R>* f, const Geom& g, int B, int s, cx<R> p[12]) {
-  long base = (long)B * 12 * g.bs + s;
+  long base = fidx(g, B, s, 12);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) p[c] = f[base + (long)c * g.bs];
+  for (int c = 0; c < 12; ++c) p[c] = f[base + (long)c * TILE];
 }
 
 template <class R>
 __device__ __forceinline__ void store_spinor(cx<R>* f, const Geom& g, int B, int s, const cx<R> p[12]) {
-  long base = (long)B * 12 * g.bs + s;
+  long base = fidx(g, B, s, 12);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) f[base + (long)c * g.bs] = p[c];
+  for (int c = 0; c < 12; ++c) f[base + (long)c * TILE] = p[c];
 }
 
 // packed Hermitian 6x6: 6 real diagonal entries, then the 15 upper entries
@@ -111,34 +112,28 @@ __host__ __device__ __forceinline__ int herm_idx(int i, int j) { return 5 * i - 
 
 template <class R>
 __device__ __forceinline__ void herm_mv(const R* hp, long stride, const cx<R> x[6], cx<R> y[6]) {
-  R h[36];
+  // streams the packed entries once: y_i += H_ij x_j and y_j += conj(H_ij) x_i
 #pragma unroll
-  for (int k = 0; k < 36; ++k) h[k] = hp[(long)k * stride];
+  for (int i = 0; i < 6; ++i) y[i] = hp[(long)i * stride] * x[i];
+  int k = 6;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    cx<R> acc = h[i] * x[i];
+  for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      if (j == i) continue;
-      if (j > i) {
-        int k = 6 + 2 * herm_idx(i, j);
-        cmac(acc, mk<R>(h[k], h[k + 1]), x[j]);
-      } else {
-        int k = 6 + 2 * herm_idx(j, i);
-        cjmac(acc, mk<R>(h[k], h[k + 1]), x[j]);
-      }
+    for (int j = i + 1; j < 6; ++j) {
+      cx<R> h = mk<R>(hp[(long)k * stride], hp[(long)(k + 1) * stride]);
+      k += 2;
+      cmac(y[i], h, x[j]);
+      cjmac(y[j], h, x[i]);
     }
-    y[i] = acc;
-  }
 }
 
 // T psi at (B,s): (m0+4+A) psi + i tw gamma5 psi
 template <class R>
 __device__ __forceinline__ void site_term(const R* H, const Geom& g, int B, int s, R tw, const cx<R> psi[12],
                                           cx<R> out[12]) {
-  const R* hp = H + (long)B * 72 * g.bs + s;
-  herm_mv(hp, g.bs, psi, out);
-  herm_mv(hp + 36L * g.bs, g.bs, psi + 6, out + 6);
+  const R* hp = H + fidx(g, B, s, 72);
+  herm_mv(hp, TILE, psi, out);
+  herm_mv(hp + 36L * TILE, TILE, psi + 6, out + 6);
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     out[c] += tw * times_mi(psi[c]);
@@ -152,13 +147,13 @@ __device__ __forceinline__ void site_term(const R* H, const Geom& g, int B, int 
 template <class R>
 __device__ __forceinline__ void site_inv(const R* H, const R* Minv, const Geom& g, int B, int s, R tw,
                                          const cx<R> psi[12], cx<R> out[12]) {
-  const R* hp = H + (long)B * 72 * g.bs + s;
-  const R* mp = Minv + (long)B * 72 * g.half + (s - g.half);
+  const R* hp = H + fidx(g, B, s, 72);
+  const R* mp = Minv + oidx(g, B, s - g.half, 72);
   cx<R> t[12];
-  herm_mv(mp, g.half, psi, t);
-  herm_mv(mp + 36L * g.half, g.half, psi + 6, t + 6);
-  herm_mv(hp, g.bs, t, out);
-  herm_mv(hp + 36L * g.bs, g.bs, t + 6, out + 6);
+  herm_mv(mp, TILE, psi, t);
+  herm_mv(mp + 36L * TILE, TILE, psi + 6, t + 6);
+  herm_mv(hp, TILE, t, out);
+  herm_mv(hp + 36L * TILE, TILE, t + 6, out + 6);
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     out[c] += tw * times_i(t[c]);
@@ -204,10 +199,17 @@ __device__ __forceinline__ void hop_global_dir(const typename store_traits<S>::e
 template <class R, class S>
 __device__ __forceinline__ void hop_global(const typename store_traits<S>::elem* U, const cx<R>* in, const Geom& g,
                                            int B, int s, const SiteNbr& me, cx<R> out[12]) {
-  hop_global_dir<0, R, S>(U, in, g, B, s, me, out);
-  hop_global_dir<1, R, S>(U, in, g, B, s, me, out);
-  hop_global_dir<2, R, S>(U, in, g, B, s, me, out);
-  hop_global_dir<3, R, S>(U, in, g, B, s, me, out);
+  // One direction per iteration of a loop whose trip count the compiler cannot
+  // see (g.ndir == 4): keeps the operands of a single hop live at a time.
+#pragma unroll 1
+  for (int mu = 0; mu < g.ndir; ++mu) {
+    switch (mu) {
+      case 0: hop_global_dir<0, R, S>(U, in, g, B, s, me, out); break;
+      case 1: hop_global_dir<1, R, S>(U, in, g, B, s, me, out); break;
+      case 2: hop_global_dir<2, R, S>(U, in, g, B, s, me, out); break;
+      default: hop_global_dir<3, R, S>(U, in, g, B, s, me, out); break;
+    }
+  }
 }
 
 __device__ __forceinline__ void me_of(const Geom& g, int B, int s, SiteNbr& me) {
@@ -218,7 +220,7 @@ __device__ __forceinline__ void me_of(const Geom& g, int B, int s, SiteNbr& me) 
 // ---------------------------------------------------------------------------
 // D(tw) psi, full lattice, one work-item per site
 template <class R, class S>
-__global__ void __launch_bounds__(256) k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 4, 8))) k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U,
                                                const R* __restrict__ H, R tw, const cx<R>* __restrict__ in,
                                                cx<R>* __restrict__ out) {
   long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -257,19 +259,20 @@ template void launch_dirac<float, bf16>(const Geom&, const void*, const float*, 
 // (even slot i, odd slot half+i).  r = b - D x on the block, then n_mr MR steps
 // on the block-local even-site Schur complement S = T_ee - D_eo T_oo^{-1} D_oe
 // (hops leaving the block dropped), odd reconstruction, x += e.
-template <class R, class S>
+template <class R, class S, bool SUB = false>
 __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::elem* U, const Geom& g, int B, int s,
                                               const SiteNbr& me, const cx<R>* lds, int lds_off, cx<R> out[12]) {
-  // lds holds a 12 x half field of the opposite parity (component-major)
+  // lds holds a 12 x half field of the opposite parity (component-major);
+  // hops leaving the block are dropped (Dirichlet cut of the SAP domain)
   cx<R> psi[12], u[9];
 #pragma unroll 1
-  for (int mu = 0; mu < 4; ++mu) {
+  for (int mu = 0; mu < g.ndir; ++mu) {
     if (me.l[mu] + 1 < g.b[mu]) {
       int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
       l[mu] += 1;
       int sn = local_slot(g, l) - lds_off;
 #pragma unroll
-      for (int c = 0; c < 12; ++c) psi[c] = lds[c * g.half + sn];
+      for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sn] : lds[c * g.half + sn];
       load_link<R, S>(U, g, B, s, mu, u);
       hop_accum<0>(mu, psi, u, out);
     }
@@ -279,99 +282,88 @@ __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::el
       int slot = local_slot(g, l);
       int sn = slot - lds_off;
 #pragma unroll
-      for (int c = 0; c < 12; ++c) psi[c] = lds[c * g.half + sn];
+      for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sn] : lds[c * g.half + sn];
       load_link<R, S>(U, g, B, slot, mu, u);
       hop_accum<1>(mu, psi, u, out);
     }
   }
 }
 
+// SAP colour sweep.  One workgroup per block of the colour, one thread per
+// site: threads [0, half) own the even slots, [half, bs) the odd slots.
+//   r = b - D x on the block;  rho = r_e - D_eo T_oo^{-1} r_o;
+//   n_mr MR steps on S = T_ee - D_eo T_oo^{-1} D_oe (block-local hops only);
+//   e_o = T_oo^{-1} (r_o - D_oe e_e);  x += e.
 template <class R, class S>
-__global__ void __launch_bounds__(256) k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U,
-                                             const R* __restrict__ H, const R* __restrict__ Minv, R tw,
-                                             const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 1 : 3, 8)))
+k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H,
+      const R* __restrict__ Minv, R tw, const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr) {
   extern __shared__ char smem_raw[];
-  cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x half
-  cx<R>* od = ev + 12 * g.half;                     // 12 x half
-  cx<R>* ro = od + 12 * g.half;                     // 12 x half
+  cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x half, even slots
+  cx<R>* od = ev + 12 * g.half;                     // 12 x half, odd slots
+  cx<R>* epsb = od + 12 * g.half;                   // 12 x half, accumulated correction (even)
   __shared__ double red[3][16];
-  // block of this colour: same trick as for sites, nb[3] is even
-  int w = blockIdx.x;
   int B;
   {
-    int B0 = 2 * w;
+    int B0 = 2 * blockIdx.x;
     int bc[4];
     block_coords(g, B0, bc);
     int par = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
     B = B0 + ((par ^ colour) & 1);
   }
-  int i = threadIdx.x;
-  const int se = i, so = g.half + i;
-  SiteNbr me_e, me_o;
-  me_of(g, B, se, me_e);
-  me_of(g, B, so, me_o);
-  cx<R> re[12], tmp[12], psi[12];
-  // residual on both slots
-  load_spinor(x, g, B, se, psi);
-  site_term(H, g, B, se, tw, psi, tmp);
-  hop_global<R, S>(U, x, g, B, se, me_e, tmp);
-  load_spinor(b, g, B, se, re);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) re[c] -= tmp[c];
+  const int t = threadIdx.x;
+  const bool even = t < g.half;
+  const int i = even ? t : t - g.half;  // index within the parity
+  const int lane = t & 63, wv = t >> 6, nw = (g.bs + 63) >> 6;
+  SiteNbr me;
+  me_of(g, B, t, me);
+  cx<R> r[12], tmp[12];
   {
-    cx<R> r_o[12];
-    load_spinor(x, g, B, so, psi);
-    site_term(H, g, B, so, tw, psi, tmp);
-    hop_global<R, S>(U, x, g, B, so, me_o, tmp);
-    load_spinor(b, g, B, so, r_o);
+    cx<R> psi[12];
+    load_spinor(x, g, B, t, psi);
+    site_term(H, g, B, t, tw, psi, tmp);
+    hop_global<R, S>(U, x, g, B, t, me, tmp);
+    load_spinor(b, g, B, t, r);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      r_o[c] -= tmp[c];
-      ro[c * g.half + i] = r_o[c];
+    for (int c = 0; c < 12; ++c) r[c] -= tmp[c];
+    if (!even) {
+      site_inv(H, Minv, g, B, t, tw, r, tmp);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) od[c * g.half + i] = tmp[c];
     }
-    // t_o = T_oo^{-1} r_o
-    site_inv(H, Minv, g, B, so, tw, r_o, tmp);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) od[c * g.half + i] = tmp[c];
   }
   __syncthreads();
-  // rho = r_e - D_eo t_o   (the hop already carries the -1/2)
-  cx<R> rho[12], eps[12];
+  if (even) {
+    hop_block_lds<R, S, true>(U, g, B, t, me, od, g.half, r);  // r now holds rho
 #pragma unroll
-  for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
-  hop_block_lds<R, S>(U, g, B, se, me_e, od, g.half, tmp);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    rho[c] = re[c] - tmp[c];
-    eps[c] = mk<R>(0, 0);
+    for (int c = 0; c < 12; ++c) epsb[c * g.half + i] = mk<R>(0, 0);
   }
-  const int lane = i & 63, wv = i >> 6, nw = (g.half + 63) >> 6;
   for (int k = 0; k < n_mr; ++k) {
+    if (even) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) ev[c * g.half + i] = r[c];
+    }
     __syncthreads();
+    if (!even) {  // w = T_oo^{-1} D_oe rho
+      cx<R> u[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ev[c * g.half + i] = rho[c];
+      for (int c = 0; c < 12; ++c) u[c] = mk<R>(0, 0);
+      hop_block_lds<R, S>(U, g, B, t, me, ev, 0, u);
+      site_inv(H, Minv, g, B, t, tw, u, tmp);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) od[c * g.half + i] = tmp[c];
+    }
     __syncthreads();
-    // odd: w = T_oo^{-1} D_oe rho
-#pragma unroll
-    for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
-    hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, tmp);
-    site_inv(H, Minv, g, B, so, tw, tmp, psi);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) od[c * g.half + i] = psi[c];
-    __syncthreads();
-    // even: q = T_ee rho - D_eo w
-    cx<R> q[12];
-    site_term(H, g, B, se, tw, rho, q);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
-    hop_block_lds<R, S>(U, g, B, se, me_e, od, g.half, tmp);
     double qr_re = 0, qr_im = 0, qq = 0;
+    if (even) {  // q = T_ee rho - D_eo w
+      site_term(H, g, B, t, tw, r, tmp);
+      hop_block_lds<R, S, true>(U, g, B, t, me, od, g.half, tmp);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      q[c] -= tmp[c];
-      qr_re += (double)q[c].re * rho[c].re + (double)q[c].im * rho[c].im;
-      qr_im += (double)q[c].re * rho[c].im - (double)q[c].im * rho[c].re;
-      qq += (double)q[c].re * q[c].re + (double)q[c].im * q[c].im;
+      for (int c = 0; c < 12; ++c) {
+        qr_re += (double)tmp[c].re * r[c].re + (double)tmp[c].im * r[c].im;
+        qr_im += (double)tmp[c].re * r[c].im - (double)tmp[c].im * r[c].re;
+        qq += (double)tmp[c].re * tmp[c].re + (double)tmp[c].im * tmp[c].im;
+      }
     }
     {
       int nact = min(64, (int)blockDim.x - wv * 64);
@@ -385,47 +377,43 @@ __global__ void __launch_bounds__(256) k_sap(Geom g, int colour, const typename 
       red[2][wv] = qq;
     }
     __syncthreads();
-    double sr = 0, si = 0, sq = 0;
-    for (int v = 0; v < nw; ++v) {
-      sr += red[0][v];
-      si += red[1][v];
-      sq += red[2][v];
-    }
-    cx<R> alpha = mk<R>(0, 0);
-    if (sq > 0) alpha = mk<R>((R)(sr / sq), (R)(si / sq));
+    if (even) {
+      double sr = 0, si = 0, sq = 0;
+      for (int v = 0; v < nw; ++v) {
+        sr += red[0][v];
+        si += red[1][v];
+        sq += red[2][v];
+      }
+      cx<R> alpha = mk<R>(0, 0);
+      if (sq > 0) alpha = mk<R>((R)(sr / sq), (R)(si / sq));
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      eps[c] += alpha * rho[c];
-      rho[c] -= alpha * q[c];
+      for (int c = 0; c < 12; ++c) {
+        epsb[c * g.half + i] += alpha * r[c];
+        r[c] -= alpha * tmp[c];
+      }
     }
+    __syncthreads();
   }
   __syncthreads();
+  cx<R> xv[12];
+  load_spinor(x, g, B, t, xv);
+  if (even) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) ev[c * g.half + i] = eps[c];
-  __syncthreads();
-  // odd reconstruction e_o = T_oo^{-1} (r_o - D_oe e_e)
+    for (int c = 0; c < 12; ++c) xv[c] += epsb[c * g.half + i];
+  } else {  // e_o = T_oo^{-1} (r_o - D_oe e_e)
+    hop_block_lds<R, S, true>(U, g, B, t, me, epsb, 0, r);
+    site_inv(H, Minv, g, B, t, tw, r, tmp);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) tmp[c] = mk<R>(0, 0);
-  hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, tmp);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) psi[c] = ro[c * g.half + i] - tmp[c];
-  site_inv(H, Minv, g, B, so, tw, psi, tmp);
-  // x += e
-  load_spinor(x, g, B, se, psi);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) psi[c] += eps[c];
-  store_spinor(x, g, B, se, psi);
-  load_spinor(x, g, B, so, psi);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) psi[c] += tmp[c];
-  store_spinor(x, g, B, so, psi);
+    for (int c = 0; c < 12; ++c) xv[c] += tmp[c];
+  }
+  store_spinor(x, g, B, t, xv);
 }
 
 template <class R, class S>
 void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
                 cx<R>* x, int n_mr, hipStream_t st) {
   size_t sm = 3 * 12 * (size_t)g.half * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_sap<R, S>), dim3(g.nblocks / 2), dim3(g.half), sm, st, g, colour,
+  hipLaunchKernelGGL((k_sap<R, S>), dim3(g.nblocks / 2), dim3(g.bs), sm, st, g, colour,
                      (const typename store_traits<S>::elem*)U, H, Minv, (R)tw, b, x, n_mr);
 }
 template void launch_sap<double, double>(const Geom&, int, const void*, const double*, const double*, double,
@@ -449,7 +437,7 @@ __global__ void k_spinor_from_lex(Geom g, const cx<double>* __restrict__ lex, cx
   long li = lex_index(g, x);
   for (int c = 0; c < ncomp; ++c) {
     cx<double> v = lex[li * ncomp + c];
-    out[((long)B * ncomp + c) * g.bs + s] = mk<R>((R)v.re, (R)v.im);
+    out[fidx(g, B, s, ncomp) + (long)c * TILE] = mk<R>((R)v.re, (R)v.im);
   }
 }
 
@@ -462,7 +450,7 @@ __global__ void k_spinor_to_lex(Geom g, const cx<R>* __restrict__ in, cx<double>
   site_coords(g, B, s, x);
   long li = lex_index(g, x);
   for (int c = 0; c < ncomp; ++c) {
-    cx<R> v = in[((long)B * ncomp + c) * g.bs + s];
+    cx<R> v = in[fidx(g, B, s, ncomp) + (long)c * TILE];
     lex[li * ncomp + c] = mk<double>(v.re, v.im);
   }
 }
@@ -513,8 +501,8 @@ __device__ __forceinline__ Mat3 link_at(const cx<double>* U, const Geom& g, cons
   int B, s;
   coords_site(g, x, B, s);
   Mat3 r;
-  long base = ((long)(B * 4 + mu) * 9) * g.bs + s;
-  for (int k = 0; k < 9; ++k) r.m[k] = U[base + (long)k * g.bs];
+  long base = fidx(g, B, s, 36) + (long)mu * 9 * TILE;
+  for (int k = 0; k < 9; ++k) r.m[k] = U[base + (long)k * TILE];
   return r;
 }
 
@@ -561,16 +549,16 @@ __global__ void k_clover(Geom g, const cx<double>* __restrict__ U, double csw, d
               for (int bb = 0; bb < 3; ++bb) A[c][3 * s1 + a][3 * s2 + bb] += f * F[3 * a + bb];
           }
     }
-  double* hp = H + (long)B * 72 * g.bs + s;
+  double* hp = H + fidx(g, B, s, 72);
   for (int c = 0; c < 2; ++c) {
-    double* h = hp + 36L * c * g.bs;
-    for (int i = 0; i < 6; ++i) h[(long)i * g.bs] = diag + A[c][i][i].re;
+    double* h = hp + 36L * c * TILE;
+    for (int i = 0; i < 6; ++i) h[(long)i * TILE] = diag + A[c][i][i].re;
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
         int k = 6 + 2 * herm_idx(i, j);
         cx<double> v = 0.5 * (A[c][i][j] + conj(A[c][j][i]));
-        h[(long)k * g.bs] = v.re;
-        h[(long)(k + 1) * g.bs] = v.im;
+        h[(long)k * TILE] = v.re;
+        h[(long)(k + 1) * TILE] = v.im;
       }
   }
 }
@@ -591,17 +579,17 @@ __global__ void k_clover_from_lex(Geom g, const cx<double>* __restrict__ lex, do
   int x[4];
   site_coords(g, B, s, x);
   long li = lex_index(g, x);
-  double* hp = H + (long)B * 72 * g.bs + s;
+  double* hp = H + fidx(g, B, s, 72);
   for (int c = 0; c < 2; ++c) {
     const cx<double>* a = lex + (li * 2 + c) * 36;
-    double* h = hp + 36L * c * g.bs;
-    for (int i = 0; i < 6; ++i) h[(long)i * g.bs] = diag + a[6 * i + i].re;
+    double* h = hp + 36L * c * TILE;
+    for (int i = 0; i < 6; ++i) h[(long)i * TILE] = diag + a[6 * i + i].re;
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
         int k = 6 + 2 * herm_idx(i, j);
         cx<double> v = 0.5 * (a[6 * i + j] + conj(a[6 * j + i]));
-        h[(long)k * g.bs] = v.re;
-        h[(long)(k + 1) * g.bs] = v.im;
+        h[(long)k * TILE] = v.re;
+        h[(long)(k + 1) * TILE] = v.im;
       }
   }
 }
@@ -617,15 +605,15 @@ __global__ void k_clover_to_lex(Geom g, const double* __restrict__ H, double dia
   int x[4];
   site_coords(g, B, s, x);
   long li = lex_index(g, x);
-  const double* hp = H + (long)B * 72 * g.bs + s;
+  const double* hp = H + fidx(g, B, s, 72);
   for (int c = 0; c < 2; ++c) {
     cx<double>* a = lex + (li * 2 + c) * 36;
-    const double* h = hp + 36L * c * g.bs;
-    for (int i = 0; i < 6; ++i) a[6 * i + i] = mk(h[(long)i * g.bs] - diag, 0.0);
+    const double* h = hp + 36L * c * TILE;
+    for (int i = 0; i < 6; ++i) a[6 * i + i] = mk(h[(long)i * TILE] - diag, 0.0);
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
         int k = 6 + 2 * herm_idx(i, j);
-        cx<double> v = mk(h[(long)k * g.bs], h[(long)(k + 1) * g.bs]);
+        cx<double> v = mk(h[(long)k * TILE], h[(long)(k + 1) * TILE]);
         a[6 * i + j] = v;
         a[6 * j + i] = conj(v);
       }
@@ -644,7 +632,7 @@ __global__ void k_links_from_lex(Geom g, const cx<double>* __restrict__ lex, cx<
   site_coords(g, B, s, x);
   long li = lex_index(g, x);
   for (int mu = 0; mu < 4; ++mu)
-    for (int k = 0; k < 9; ++k) U[((long)(B * 4 + mu) * 9 + k) * g.bs + s] = lex[(li * 4 + mu) * 9 + k];
+    for (int k = 0; k < 9; ++k) U[fidx(g, B, s, 36) + (long)(mu * 9 + k) * TILE] = lex[(li * 4 + mu) * 9 + k];
 }
 void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, hipStream_t st) {
   hipLaunchKernelGGL(k_links_from_lex, dim3((g.V + 255) / 256), dim3(256), 0, st, g, lex, U);
@@ -659,15 +647,15 @@ __global__ void k_odd_inverse(Geom g, const double* __restrict__ H, double tw, d
   if (gid >= nodd) return;
   int B = (int)(gid / g.half), io = (int)(gid - (long)B * g.half);
   int s = g.half + io;
-  const double* hp = H + (long)B * 72 * g.bs + s;
+  const double* hp = H + fidx(g, B, s, 72);
   for (int c = 0; c < 2; ++c) {
     cx<double> h[6][6], G[6][6], L[6][6], Inv[6][6];
-    const double* hc = hp + 36L * c * g.bs;
-    for (int i = 0; i < 6; ++i) h[i][i] = mk(hc[(long)i * g.bs], 0.0);
+    const double* hc = hp + 36L * c * TILE;
+    for (int i = 0; i < 6; ++i) h[i][i] = mk(hc[(long)i * TILE], 0.0);
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
         int k = 6 + 2 * herm_idx(i, j);
-        h[i][j] = mk(hc[(long)k * g.bs], hc[(long)(k + 1) * g.bs]);
+        h[i][j] = mk(hc[(long)k * TILE], hc[(long)(k + 1) * TILE]);
         h[j][i] = conj(h[i][j]);
       }
     for (int i = 0; i < 6; ++i)
@@ -703,14 +691,14 @@ __global__ void k_odd_inverse(Geom g, const double* __restrict__ H, double tw, d
         Inv[i][col] = (1.0 / L[i][i].re) * acc;
       }
     }
-    double* mp = M + (long)B * 72 * g.half + io + 36L * c * g.half;
-    for (int i = 0; i < 6; ++i) mp[(long)i * g.half] = Inv[i][i].re;
+    double* mp = M + oidx(g, B, io, 72) + 36L * c * TILE;
+    for (int i = 0; i < 6; ++i) mp[(long)i * TILE] = Inv[i][i].re;
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
         int k = 6 + 2 * herm_idx(i, j);
         cx<double> v = 0.5 * (Inv[i][j] + conj(Inv[j][i]));
-        mp[(long)k * g.half] = v.re;
-        mp[(long)(k + 1) * g.half] = v.im;
+        mp[(long)k * TILE] = v.re;
+        mp[(long)(k + 1) * TILE] = v.im;
       }
   }
 }
@@ -739,9 +727,9 @@ __global__ void __launch_bounds__(256) k_restrict_fine(Geom g, int Nv, const cx<
       acc[ii][0][0] = acc[ii][0][1] = acc[ii][1][0] = acc[ii][1][1] = 0.0;
       if (ii < ni) {
         const cx<R>* q = Q + (long)(i0 + ii) * vstride;
-        long base = (long)B * 12 * g.bs + s;
+        long base = fidx(g, B, s, 12);
         for (int c = 0; c < 12; ++c) {
-          cx<R> qv = q[base + (long)c * g.bs];
+          cx<R> qv = q[base + (long)c * TILE];
           int h = c / 6;
           acc[ii][h][0] += (double)qv.re * rv[c].re + (double)qv.im * rv[c].im;
           acc[ii][h][1] += (double)qv.re * rv[c].im - (double)qv.im * rv[c].re;
@@ -791,14 +779,14 @@ __global__ void __launch_bounds__(256) k_prolong_fine(Geom g, int Nv, const cx<R
   if (accumulate) load_spinor(x, g, B, s, acc);
   else
     for (int c = 0; c < 12; ++c) acc[c] = mk<R>(0, 0);
-  long base = (long)B * 12 * g.bs + s;
+  long base = fidx(g, B, s, 12);
   for (int i = 0; i < Nv; ++i) {
     cx<R> e0 = e[i], e1 = e[Nv + i];
     const cx<R>* q = Q + (long)i * vstride + base;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) cmac(acc[c], q[(long)c * g.bs], e0);
+    for (int c = 0; c < 6; ++c) cmac(acc[c], q[(long)c * TILE], e0);
 #pragma unroll
-    for (int c = 6; c < 12; ++c) cmac(acc[c], q[(long)c * g.bs], e1);
+    for (int c = 6; c < 12; ++c) cmac(acc[c], q[(long)c * TILE], e1);
   }
   store_spinor(x, g, B, s, acc);
 }
@@ -817,15 +805,15 @@ template void launch_prolong_fine<float>(const Geom&, int, const cx<float>*, lon
 // block orthonormalisation (classical Gram-Schmidt, twice) per aggregate half,
 // FP64 arithmetic; columns in the order v_1..v_Nv, diag(R) = norms (real > 0).
 // One workgroup per (block, half), one thread per slot (6 rows each).
-template <class RO>
-__global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<double>* __restrict__ V, long vstride,
+template <class RI, class RO>
+__global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<RI>* __restrict__ V, long vstride,
                                                  RO* __restrict__ Qout_raw, long qstride, int* __restrict__ fail) {
   cx<RO>* Qout = reinterpret_cast<cx<RO>*>(Qout_raw);
   __shared__ double red[32][4][2];
   __shared__ double dsh[32][2];
   int B = blockIdx.x >> 1, h = blockIdx.x & 1;
   int s = threadIdx.x, lane = s & 63, wv = s >> 6, nw = (g.bs + 63) >> 6;
-  long base = (long)B * 12 * g.bs + (long)(6 * h) * g.bs + s;
+  long base = fidx(g, B, s, 12) + (long)(6 * h) * TILE;
   auto reduce = [&](double a, double b, int slot) {
     int nact = min(64, g.bs - wv * 64);
     a = wave_sum_n(a, nact);
@@ -837,7 +825,10 @@ __global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<double
   };
   for (int i = 0; i < Nv; ++i) {
     cx<double> v[6];
-    for (int c = 0; c < 6; ++c) v[c] = V[(long)i * vstride + base + (long)c * g.bs];
+    for (int c = 0; c < 6; ++c) {
+      cx<RI> vi = V[(long)i * vstride + base + (long)c * TILE];
+      v[c] = mk<double>(vi.re, vi.im);
+    }
     double n0 = 0;
     for (int c = 0; c < 6; ++c) n0 += norm2(v[c]);
     reduce(n0, 0.0, 0);
@@ -849,7 +840,7 @@ __global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<double
       for (int j = 0; j < i; ++j) {
         double ar = 0, ai = 0;
         for (int c = 0; c < 6; ++c) {
-          cx<RO> q = Qout[(long)j * qstride + base + (long)c * g.bs];
+          cx<RO> q = Qout[(long)j * qstride + base + (long)c * TILE];
           ar += (double)q.re * v[c].re + (double)q.im * v[c].im;
           ai += (double)q.re * v[c].im - (double)q.im * v[c].re;
         }
@@ -869,7 +860,7 @@ __global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<double
       for (int j = 0; j < i; ++j) {
         cx<double> d = mk(dsh[j][0], dsh[j][1]);
         for (int c = 0; c < 6; ++c) {
-          cx<RO> q = Qout[(long)j * qstride + base + (long)c * g.bs];
+          cx<RO> q = Qout[(long)j * qstride + base + (long)c * TILE];
           v[c] = v[c] - d * mk<double>(q.re, q.im);
         }
       }
@@ -886,18 +877,20 @@ __global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<double
     double inv = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
     for (int c = 0; c < 6; ++c) {
       cx<double> q = inv * v[c];
-      Qout[(long)i * qstride + base + (long)c * g.bs] = mk<RO>((RO)q.re, (RO)q.im);
+      Qout[(long)i * qstride + base + (long)c * TILE] = mk<RO>((RO)q.re, (RO)q.im);
     }
   }
 }
-template <class RO>
-void launch_qr_fine(const Geom& g, int Nv, const cx<double>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
+template <class RI, class RO>
+void launch_qr_fine(const Geom& g, int Nv, const cx<RI>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_qr_fine<RO>, dim3(2 * g.nblocks), dim3(g.bs), 0, st, g, Nv, V, vstride, (RO*)Q, qstride,
+  hipLaunchKernelGGL((k_qr_fine<RI, RO>), dim3(2 * g.nblocks), dim3(g.bs), 0, st, g, Nv, V, vstride, (RO*)Q, qstride,
                      fail);
 }
-template void launch_qr_fine<double>(const Geom&, int, const cx<double>*, long, cx<double>*, long, int*, hipStream_t);
-template void launch_qr_fine<float>(const Geom&, int, const cx<double>*, long, cx<float>*, long, int*, hipStream_t);
+template void launch_qr_fine<double, double>(const Geom&, int, const cx<double>*, long, cx<double>*, long, int*,
+                                             hipStream_t);
+template void launch_qr_fine<float, float>(const Geom&, int, const cx<float>*, long, cx<float>*, long, int*,
+                                           hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Galerkin assembly of the first coarse operator, FP64.  One workgroup per
@@ -929,29 +922,29 @@ __global__ void __launch_bounds__(256) k_assemble_fine(Geom g, int Nv, const cx<
     __syncthreads();
     for (int e = t; e < Nv * 12; e += 256) {
       int i = e / 12, c = e % 12;
-      cx<RQ> v = Q[(long)i * qstride + ((long)B * 12 + c) * g.bs + sx];
+      cx<RQ> v = Q[(long)i * qstride + fidx(g, B, sx, 12) + (long)c * TILE];
       qx[e] = mk<double>(v.re, v.im);
     }
     __syncthreads();
     if (kind == 0) {
       // site term W[l] = H_{half(l)} Q_{i_l}(x) on half(l), zero elsewhere
-      const double* hp = H + (long)B * 72 * g.bs + sx;
+      const double* hp = H + fidx(g, B, sx, 72);
       for (int e = t; e < n * 12; e += 256) {
         int col = e / 12, c = e % 12;
         int hcol = col >= Nv ? 1 : 0, i = col - hcol * Nv;
         cx<double> acc = mk(0.0, 0.0);
         if (c / 6 == hcol) {
-          const double* h = hp + 36L * hcol * g.bs;
+          const double* h = hp + 36L * hcol * TILE;
           int r = c % 6;
           for (int j = 0; j < 6; ++j) {
             cx<double> hv;
-            if (j == r) hv = mk(h[(long)r * g.bs], 0.0);
+            if (j == r) hv = mk(h[(long)r * TILE], 0.0);
             else if (j > r) {
               int k = 6 + 2 * herm_idx(r, j);
-              hv = mk(h[(long)k * g.bs], h[(long)(k + 1) * g.bs]);
+              hv = mk(h[(long)k * TILE], h[(long)(k + 1) * TILE]);
             } else {
               int k = 6 + 2 * herm_idx(j, r);
-              hv = mk(h[(long)k * g.bs], -h[(long)(k + 1) * g.bs]);
+              hv = mk(h[(long)k * TILE], -h[(long)(k + 1) * TILE]);
             }
             cmac(acc, hv, qx[i * 12 + 6 * hcol + j]);
           }
@@ -994,11 +987,11 @@ __global__ void __launch_bounds__(256) k_assemble_fine(Geom g, int Nv, const cx<
           out[c] = mk(0.0, 0.0);
         }
         for (int c = 0; c < 6; ++c) {
-          cx<RQ> v = Q[(long)i * qstride + ((long)By * 12 + 6 * hcol + c) * g.bs + sy];
+          cx<RQ> v = Q[(long)i * qstride + fidx(g, By, sy, 12) + (long)(6 * hcol + c) * TILE];
           psi[6 * hcol + c] = mk<double>(v.re, v.im);
         }
-        long ub = ((long)(B * 4 + mu) * 9) * g.bs + sx;
-        for (int k = 0; k < 9; ++k) u[k] = U[ub + (long)k * g.bs];
+        long ub = fidx(g, B, sx, 36) + (long)mu * 9 * TILE;
+        for (int k = 0; k < 9; ++k) u[k] = U[ub + (long)k * TILE];
         hop_accum<0>(mu, psi, u, out);
         for (int c = 0; c < 12; ++c) W[col * 12 + c] = out[c];
       }

@@ -50,8 +50,8 @@ void launch_restrict_fine(const Geom& g, int Nv, const cx<R>* Q, long vstride, c
 template <class R>
 void launch_prolong_fine(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* ec, const int* f2c,
                          cx<R>* x, int accumulate, hipStream_t st);
-template <class RO>
-void launch_qr_fine(const Geom& g, int Nv, const cx<double>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
+template <class RI, class RO>
+void launch_qr_fine(const Geom& g, int Nv, const cx<RI>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
                     hipStream_t st);
 template <class RQ>
 void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, const cx<RQ>* Q, long qstride,
@@ -79,8 +79,8 @@ void launch_restrict_coarse(int n, int Nv, int nagg, int asz, const int* agg_sit
 template <class R>
 void launch_prolong_coarse(int n, int Nv, int nsites, const int* site_agg, const cx<R>* Q, long qstride,
                            const cx<R>* ec, cx<R>* x, int accumulate, hipStream_t st);
-template <class RO>
-void launch_qr_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<double>* V, long vstride,
+template <class RI, class RO>
+void launch_qr_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<RI>* V, long vstride,
                       cx<RO>* Q, long qstride, int* fail, hipStream_t st);
 template <class RQ>
 void launch_assemble_coarse(const CGeom& cg, int Nv, int nagg, const int ab[4], const int* agg_sites,

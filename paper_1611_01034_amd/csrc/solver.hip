@@ -105,7 +105,7 @@ void KernelTimer::flush() {
   recs.clear();
 }
 void KernelTimer::reset() {
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NKIND; ++i) {
     count[i] = 0;
     ms[i] = 0;
   }
@@ -497,7 +497,7 @@ struct MG : MGBase {
     fx.alloc(sizeof(cx<R>) * fl);
     fb.alloc(sizeof(cx<R>) * fl);
     fr.alloc(sizeof(cx<R>) * fl);
-    Vraw[0].alloc(sizeof(cx<double>) * fl * Nv[0]);
+    Vraw[0].alloc(sizeof(cx<R>) * fl * Nv[0]);
     Q[0].alloc(sizeof(cx<R>) * fl * Nv[0]);
     size_t maxnn = 0;
     for (int l = 1; l < L; ++l) {
@@ -511,7 +511,7 @@ struct MG : MGBase {
       ec[l].alloc(sizeof(cx<R>) * len);
       for (int k = 0; k < 4; ++k) wk[l][k].alloc(sizeof(cx<R>) * len);
       if (l < L - 1) {
-        Vraw[l].alloc(sizeof(cx<double>) * len * Nv[l]);
+        Vraw[l].alloc(sizeof(cx<R>) * len * Nv[l]);
         Q[l].alloc(sizeof(cx<R>) * len * Nv[l]);
         kws[l].init(p.inter_restart, len, len, true);
       } else {
@@ -528,6 +528,7 @@ struct MG : MGBase {
       if (l == L - 1) {
         cx<R>* t = wk[l][0].template as<cx<R>>();
         Aop[l] = [this, cg, l, t](const cx<R>* in, cx<R>* out) {
+          TimeScope ts(c.timer, 5);
           launch_coarse_hop_inv_odd<R, S>(cg, Dst(l), Minvc.template as<cx<R>>(), in, t, 0, c.st);
           launch_coarse_schur_even<R, S>(cg, Dst(l), tw[l], in, t, out, 0, c.st);
         };
@@ -557,7 +558,7 @@ struct MG : MGBase {
 
   // ---- level operations ----------------------------------------------------
   void fine_dirac(const cx<R>* in, cx<R>* out) {
-    TimeScope ts(c.timer, 0);
+    TimeScope ts(c.timer, 4);
     launch_dirac<R, S>(c.g, U, Hf, tw[0], in, out, c.st);
   }
   void fine_sap(const cx<R>* b, cx<R>* x, int iters, int nmr) {
@@ -713,12 +714,12 @@ struct MG : MGBase {
     long len = level_len(l);
     CoarseGeo& Gn = *geos[l + 1];
     if (l == 0) {
-      launch_qr_fine<R>(c.g, Nv[0], Vraw[0].template as<cx<double>>(), len, Q[0].template as<cx<R>>(), len,
-                        c.iflag.template as<int>(), c.st);
+      launch_qr_fine<R, R>(c.g, Nv[0], Vraw[0].template as<cx<R>>(), len, Q[0].template as<cx<R>>(), len,
+                           c.iflag.template as<int>(), c.st);
     } else {
       CoarseGeo& G = *geos[l];
-      launch_qr_coarse<R>(G.n, Nv[l], G.nagg, G.asz, G.agg_sites.template as<int>(), Vraw[l].template as<cx<double>>(),
-                          len, Q[l].template as<cx<R>>(), len, c.iflag.template as<int>(), c.st);
+      launch_qr_coarse<R, R>(G.n, Nv[l], G.nagg, G.asz, G.agg_sites.template as<int>(), Vraw[l].template as<cx<R>>(),
+                             len, Q[l].template as<cx<R>>(), len, c.iflag.template as<int>(), c.st);
     }
     check_flag("rank-deficient aggregate in the block orthonormalisation");
     assemble_next(l);
@@ -756,27 +757,46 @@ struct MG : MGBase {
   }
 
   DevBuf npart;  // partial sums + scalar for normalisation
-  void normalise(cx<double>* v, long len) {
+  void normalise(cx<R>* v, long len) {
     const int nwg = 1024;
     npart.ensure(sizeof(cx<double>) * (nwg + 1));
     cx<double>* part = npart.template as<cx<double>>();
     cx<double>* sc = part + nwg;
     int nw = (int)std::min<long>(nwg, (len + 255) / 256);
-    launch_multidot<double>(v, 0, 1, v, len, part, nw, c.st);
+    launch_multidot<R>(v, 0, 1, v, len, part, nw, c.st);
     launch_reduce(part, 1, nw, sc, 2, c.st);
-    launch_scale_by_inv<double>(v, sc, v, len, c.st);
+    launch_scale_by_inv<R>(v, sc, v, len, c.st);
   }
 
   void iterate(int l) {
     long len = level_len(l);
     for (int i = 0; i < Nv[l]; ++i) {
-      cx<double>* vi = Vraw[l].template as<cx<double>>() + (long)i * len;
-      launch_copy_cvt<double, R>(vi, setup_in(l), len, c.st);
+      cx<R>* vi = Vraw[l].template as<cx<R>>() + (long)i * len;
+      launch_copy_cvt<R, R>(vi, setup_in(l), len, c.st);
       vcycle(l, setup_in(l), setup_out(l));
-      launch_copy_cvt<R, double>(setup_out(l), vi, len, c.st);
+      launch_copy_cvt<R, R>(setup_out(l), vi, len, c.st);
       normalise(vi, len);
     }
     build_next(l);
+  }
+
+  // init vectors (FP64, lexicographic) -> level layout in precision R
+  void upload_vec(int l, const void* src, int on_device, cx<R>* dst) {
+    long len = level_len(l);
+    if (l == 0) {
+      c.f64c.ensure(sizeof(cx<double>) * len);
+      c.upload_fine(src, on_device, c.f64c.template as<cx<double>>());
+      launch_copy_cvt<double, R>(c.f64c.template as<cx<double>>(), dst, len, c.st);
+      return;
+    }
+    CoarseGeo& G = *geos[l];
+    const cx<double>* s = (const cx<double>*)src;
+    if (!on_device) {
+      c.lex.ensure(sizeof(cx<double>) * std::max(len, c.fine_len()));
+      HIP_CHECK(hipMemcpyAsync(c.lex.p, src, sizeof(cx<double>) * len, hipMemcpyHostToDevice, c.st));
+      s = c.lex.template as<cx<double>>();
+    }
+    permute<double, R>(G.n, G.nsites, G.d_order.template as<int>(), s, dst, 1, c.st);
   }
 
   void build(const void* const* vecs, int on_device, bool run_setup) override {
@@ -784,13 +804,11 @@ struct MG : MGBase {
       long len = level_len(l);
       for (int i = 0; i < Nv[l]; ++i) {
         const char* src = (const char*)vecs[l] + sizeof(cx<double>) * (size_t)len * i;
-        cx<double>* vi = Vraw[l].template as<cx<double>>() + (long)i * len;
-        upload_level(l, src, on_device, vi);
+        cx<R>* vi = Vraw[l].template as<cx<R>>() + (long)i * len;
+        upload_vec(l, src, on_device, vi);
         if (run_setup && p.init_sap_iters > 0) {
           launch_zero<R>(len, setup_zero(l), c.st);
-          launch_copy_cvt<double, R>(vi, setup_out(l), len, c.st);
-          smooth_level(l, setup_zero(l), setup_out(l), p.init_sap_iters);
-          launch_copy_cvt<R, double>(setup_out(l), vi, len, c.st);
+          smooth_level(l, setup_zero(l), vi, p.init_sap_iters);
         }
       }
       build_next(l);

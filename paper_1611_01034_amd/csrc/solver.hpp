@@ -53,8 +53,9 @@ struct KernelTimer {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
-  long count[4] = {0, 0, 0, 0};
-  double ms[4] = {0, 0, 0, 0};
+  static constexpr int NKIND = 6;
+  long count[NKIND] = {0, 0, 0, 0, 0, 0};
+  double ms[NKIND] = {0, 0, 0, 0, 0, 0};
   hipEvent_t get();
   void begin(int kind, hipEvent_t* a);
   void end(int kind, hipEvent_t a);

@@ -119,3 +119,58 @@ def mean_plaquette(U: np.ndarray) -> float:
             acc += np.trace(P, axis1=-2, axis2=-1).real.mean() / 3.0
             n += 1
     return acc / n
+
+
+# ----------------------------------------------------------------------------
+# device-side generators (torch, seeded CUDA generator): the same distributions
+# for lattices whose host-side generation would take minutes (48^3 x 96 test
+# vectors are tens of GB).  Deterministic for a given (shape, seed, device).
+
+def gaussian_device(shape, seed: int, device="cuda"):
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    shape = tuple(int(s) for s in shape)
+    re = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+    im = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+    return torch.complex(re, im)
+
+
+def gauge_field_device(dims, eps: float, seed: int, device="cuda", chunk: int = 1 << 22):
+    """Links exp(i eps H) with H = sum_a h_a lambda_a / 2, h_a ~ N(0,1), computed
+    on the device in chunks; shape [T,Z,Y,X,4,3,3] complex128."""
+    import torch
+
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims)) * 4
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    gm = torch.from_numpy(_GM).to(device)
+    out = torch.empty((n, 3, 3), dtype=torch.complex128, device=device)
+    for a in range(0, n, chunk):
+        m = min(chunk, n - a)
+        h = torch.randn((m, 8), generator=gen, device=device, dtype=torch.float64).to(torch.complex128)
+        H = torch.einsum("na,aij->nij", h, gm) * 0.5
+        U = torch.linalg.matrix_exp(1j * eps * H)
+        det = torch.linalg.det(U)
+        out[a:a + m] = U / (det ** (1.0 / 3.0))[:, None, None]
+    return out.reshape(dims + (4, 3, 3))
+
+
+def net_init_weights(C: int, nlayers: int, seed: int, scale: float = 1.0):
+    """Seeded initial weights of the gauge-covariant network (an input to both
+    the GPU kernels and the oracle): W_{d,c,c'} complex Gaussian scaled by
+    scale/sqrt(2*9*C*4), the identity offset shifted by 0.5 * identity in
+    channel and spin; gates a = 0, b = 0.  Shapes: W [9, C, C, 4, 4]."""
+    rng = np.random.default_rng(seed)
+    W, a, b = [], [], []
+    for l in range(nlayers):
+        w = rng.standard_normal((9, C, C, 4, 4)) + 1j * rng.standard_normal((9, C, C, 4, 4))
+        w *= scale / np.sqrt(2.0 * 9 * C * 4)
+        w[0] += np.einsum("cp,st->cpst", np.eye(C), np.eye(4)) * 0.5
+        W.append(w)
+        if l < nlayers - 1:
+            a.append(np.zeros(C))
+            b.append(np.zeros(C))
+    return W, a, b
