@@ -190,6 +190,34 @@ int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply);
 int ddamg_timing(ddamg_ctx* ctx, int enable);
 int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms);
 
+/* ---- learned setup (not a method of the paper: it replaces the random start
+ * of the adaptive setup; the plain setup stays the fallback) ----
+ * Network: nlayers gauge-covariant parallel-transport layers with nchan
+ * complex channels (4, 8, 12, 16 or 24); layer l computes
+ *   z_c(x) = sum_{d=0..8} sum_{c'} W_l[d][c][c'] (T_d x_{c'})(x)
+ * with T_0 = 1, T_{1+mu} x(x) = U_mu(x) x(x+mu), T_{5+mu} x(x) = U_mu(x-mu)^dag x(x-mu)
+ * (mu = T,Z,Y,X) and W a 4x4 spin matrix; all layers but the last are gated,
+ * y_c = z_c sigmoid(a_c |z_c|^2 + b_c).  Arithmetic in FP32.
+ * Parameters (FP64 host vector): W_0 .. W_{L-1}, each [9][C][C][4][4] complex
+ * with real/imag interleaved, then a_0, b_0, a_1, b_1, ... ([C] each).
+ * Fields: nchan spinor fields (spinor layout above, contiguous). */
+int ddamg_net_create(ddamg_ctx* ctx, int nlayers, int nchan);
+long ddamg_net_num_params(ddamg_ctx* ctx);
+int ddamg_net_set_params(ddamg_ctx* ctx, const double* params, long n);
+int ddamg_net_get_params(ddamg_ctx* ctx, double* params, long n);
+/* out = network(noise) on the context's gauge field */
+int ddamg_net_forward(ddamg_ctx* ctx, const void* noise, void* out, int on_device);
+/* subspace loss of network(noise) against orthonormal targets (the block
+ * orthonormalised test vectors of a plain setup):
+ *   L = sum_{aggregate halves} |(I - Pi_Y) Q|_F^2 / sum |Q|_F^2,
+ * and its gradient dL/dRe + i dL/dIm per parameter (grads may be NULL). */
+int ddamg_net_loss_grad(ddamg_ctx* ctx, const void* noise, const void* target, int on_device, double* loss,
+                        double* grads);
+/* one Adam step (beta 0.9/0.999, eps 1e-8) on that loss; returns the loss
+ * before the update. */
+int ddamg_net_train_step(ddamg_ctx* ctx, const void* noise, const void* target, int on_device, double lr,
+                         double* loss);
+
 #ifdef __cplusplus
 }
 #endif

@@ -613,3 +613,240 @@ int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// learned setup: gauge-covariant network (forward, loss, backward, Adam)
+namespace {
+
+void net_need(Ctx& c) {
+  need_gauge(c);
+  if (c.net.L == 0) throw Error(BAD_STATE, "no network created");
+}
+
+void net_buffers(Ctx& c) {
+  NetState& n = c.net;
+  if (n.V == c.g.V) return;
+  long f = (long)n.C * c.fine_len();  // complex entries of one C-channel field
+  n.act.alloc(sizeof(cx<float>) * f * (n.L + 1));
+  n.zb.alloc(sizeof(cx<float>) * f * n.L);
+  n.sb.alloc(sizeof(float) * (long)n.C * c.g.V * std::max(1, n.L - 1));
+  n.g1.alloc(sizeof(cx<float>) * f);
+  n.g2.alloc(sizeof(cx<float>) * f);
+  n.gpart.alloc(sizeof(double) * 2 * (long)n.C * ((c.g.V + 255) / 256));
+  n.wpart.alloc(sizeof(cx<float>) * 256L * n.nWc);
+  n.lscr.alloc(sizeof(cx<double>) * 2L * c.g.nblocks * 3 * n.C * n.C);
+  n.lpart.alloc(sizeof(double) * 2L * c.g.nblocks);
+  n.V = c.g.V;
+}
+
+// C fields in the host layout (FP64, contiguous) -> C-channel block-layout FP32 field
+void net_upload(Ctx& c, const void* src, int on_device, cx<float>* dst) {
+  long fl = c.fine_len();
+  for (int ch = 0; ch < c.net.C; ++ch) {
+    const char* s = (const char*)src + sizeof(cx<double>) * (size_t)fl * ch;
+    c.upload_fine(s, on_device, c.f64a.as<cx<double>>());
+    launch_copy_cvt<double, float>(c.f64a.as<cx<double>>(), dst + (long)ch * fl, fl, c.st);
+  }
+}
+
+void net_forward(Ctx& c) {
+  NetState& n = c.net;
+  long f = (long)n.C * c.fine_len();
+  cx<float>* act = n.act.as<cx<float>>();
+  cx<float>* zb = n.zb.as<cx<float>>();
+  for (int l = 0; l < n.L; ++l) {
+    launch_net_mix(c.g, n.C, c.U32.as<cx<float>>(), act + (long)l * f, n.W(l), zb + (long)l * f, false, c.st);
+    if (l < n.L - 1)
+      launch_net_gate(c.g, n.C, zb + (long)l * f, n.ab(l), n.ab(l) + n.C, act + (long)(l + 1) * f,
+                      n.sb.as<float>() + (long)l * n.C * c.g.V, c.st);
+  }
+}
+
+// loss of the last layer's output against targets (in g2); gradient into g1
+double net_loss(Ctx& c) {
+  NetState& n = c.net;
+  long f = (long)n.C * c.fine_len();
+  double inv_norm = 1.0 / ((double)n.C * 2.0 * c.g.nblocks);
+  launch_net_loss(c.g, n.C, n.zb.as<cx<float>>() + (long)(n.L - 1) * f, n.g2.as<cx<float>>(), inv_norm,
+                  n.lscr.as<cx<double>>(), n.g1.as<cx<float>>(), n.lpart.as<double>(), c.st);
+  std::vector<double> lp(2L * c.g.nblocks);
+  HIP_CHECK(hipMemcpyAsync(lp.data(), n.lpart.p, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, c.st));
+  c.sync();
+  double L = 0;
+  for (double v : lp) L += v;
+  return L;
+}
+
+void net_backward(Ctx& c) {
+  NetState& n = c.net;
+  long f = (long)n.C * c.fine_len();
+  cx<float>* act = n.act.as<cx<float>>();
+  cx<float>* zb = n.zb.as<cx<float>>();
+  cx<float>* G = n.g1.as<cx<float>>();   // gradient w.r.t. this layer's output
+  cx<float>* Gz = n.g2.as<cx<float>>();
+  int nwgw = (int)std::min<long>(256, std::max<long>(1, c.g.V / 8 / 4));
+  for (int l = n.L - 1; l >= 0; --l) {
+    cx<float>* gz = G;
+    if (l < n.L - 1) {
+      launch_net_gate_bwd(c.g, n.C, G, zb + (long)l * f, n.sb.as<float>() + (long)l * n.C * c.g.V, n.ab(l), Gz,
+                          n.gpart.as<double>(), n.Gab(l), n.Gab(l) + n.C, c.st);
+      gz = Gz;
+    }
+    launch_net_wgrad(c.g, n.C, c.U32.as<cx<float>>(), act + (long)l * f, gz, n.wpart.as<cx<float>>(), nwgw, n.GW(l),
+                     c.st);
+    if (l > 0) {
+      cx<float>* dst = (gz == G) ? Gz : G;
+      launch_net_mix(c.g, n.C, c.U32.as<cx<float>>(), gz, n.W(l), dst, true, c.st);
+      G = dst;
+      Gz = (dst == n.g1.as<cx<float>>()) ? n.g2.as<cx<float>>() : n.g1.as<cx<float>>();
+    }
+  }
+}
+
+void net_params_to_host(const NetState& n, const DevBuf& buf, double* out, hipStream_t st) {
+  std::vector<float> h(n.nreal);
+  HIP_CHECK(hipMemcpyAsync(h.data(), buf.p, sizeof(float) * n.nreal, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (long i = 0; i < n.nreal; ++i) out[i] = h[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+int ddamg_net_create(ddamg_ctx* ctx, int nlayers, int nchan) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (nlayers < 1 || nlayers > 16) throw Error(INVALID_ARG, "nlayers must be in 1..16");
+    if (!(nchan == 4 || nchan == 8 || nchan == 12 || nchan == 16 || nchan == 24))
+      throw Error(INVALID_ARG, "nchan must be 4, 8, 12, 16 or 24");
+    if (c.g.V % 64) throw Error(INVALID_ARG, "the network needs a lattice volume divisible by 64");
+    NetState& n = c.net;
+    n.L = nlayers;
+    n.C = nchan;
+    n.nWc = 9L * nchan * nchan * 16;
+    n.nreal = 2L * nlayers * n.nWc + 2L * (nlayers - 1) * nchan;
+    n.params.alloc(sizeof(float) * n.nreal);
+    n.grads.alloc(sizeof(float) * n.nreal);
+    n.m.alloc(sizeof(float) * n.nreal);
+    n.v.alloc(sizeof(float) * n.nreal);
+    HIP_CHECK(hipMemsetAsync(n.params.p, 0, sizeof(float) * n.nreal, c.st));
+    HIP_CHECK(hipMemsetAsync(n.grads.p, 0, sizeof(float) * n.nreal, c.st));
+    HIP_CHECK(hipMemsetAsync(n.m.p, 0, sizeof(float) * n.nreal, c.st));
+    HIP_CHECK(hipMemsetAsync(n.v.p, 0, sizeof(float) * n.nreal, c.st));
+    n.V = 0;
+    n.step = 0;
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+long ddamg_net_num_params(ddamg_ctx* ctx) { return ctx ? ctx->c.net.nreal : -1; }
+
+int ddamg_net_set_params(ddamg_ctx* ctx, const double* params, long n) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (c.net.L == 0) throw Error(BAD_STATE, "no network created");
+    if (!params || n != c.net.nreal) throw Error(INVALID_ARG, "parameter count mismatch");
+    std::vector<float> h(n);
+    for (long i = 0; i < n; ++i) {
+      if (!std::isfinite(params[i])) throw Error(NUMERICAL, "non-finite network parameter");
+      h[i] = (float)params[i];
+    }
+    HIP_CHECK(hipMemcpyAsync(c.net.params.p, h.data(), sizeof(float) * n, hipMemcpyHostToDevice, c.st));
+    HIP_CHECK(hipMemsetAsync(c.net.m.p, 0, sizeof(float) * n, c.st));
+    HIP_CHECK(hipMemsetAsync(c.net.v.p, 0, sizeof(float) * n, c.st));
+    c.net.step = 0;
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_net_get_params(ddamg_ctx* ctx, double* params, long n) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (c.net.L == 0) throw Error(BAD_STATE, "no network created");
+    if (!params || n != c.net.nreal) throw Error(INVALID_ARG, "parameter count mismatch");
+    net_params_to_host(c.net, c.net.params, params, c.st);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_net_forward(ddamg_ctx* ctx, const void* noise, void* out, int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    net_need(c);
+    if (!noise || !out) throw Error(INVALID_ARG, "NULL field");
+    c.ensure_32();
+    net_buffers(c);
+    NetState& n = c.net;
+    long fl = c.fine_len();
+    long f = (long)n.C * fl;
+    net_upload(c, noise, on_device, n.act.as<cx<float>>());
+    net_forward(c);
+    const cx<float>* y = n.zb.as<cx<float>>() + (long)(n.L - 1) * f;
+    for (int ch = 0; ch < n.C; ++ch) {
+      launch_copy_cvt<float, double>(y + (long)ch * fl, c.f64b.as<cx<double>>(), fl, c.st);
+      char* dst = (char*)out + sizeof(cx<double>) * (size_t)fl * ch;
+      c.download_fine(c.f64b.as<cx<double>>(), dst, on_device);
+    }
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+// forward + loss + backward; grads (optional, host FP64, parameter layout)
+int ddamg_net_loss_grad(ddamg_ctx* ctx, const void* noise, const void* target, int on_device, double* loss,
+                        double* grads) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    net_need(c);
+    if (!noise || !target) throw Error(INVALID_ARG, "NULL field");
+    c.ensure_32();
+    net_buffers(c);
+    NetState& n = c.net;
+    net_upload(c, noise, on_device, n.act.as<cx<float>>());
+    net_upload(c, target, on_device, n.g2.as<cx<float>>());
+    net_forward(c);
+    double L = net_loss(c);
+    net_backward(c);
+    if (loss) *loss = L;
+    if (grads) net_params_to_host(n, n.grads, grads, c.st);
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_net_train_step(ddamg_ctx* ctx, const void* noise, const void* target, int on_device, double lr,
+                         double* loss) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    net_need(c);
+    if (!noise || !target) throw Error(INVALID_ARG, "NULL field");
+    if (!(lr > 0) || !std::isfinite(lr)) throw Error(INVALID_ARG, "lr must be > 0");
+    c.ensure_32();
+    net_buffers(c);
+    NetState& n = c.net;
+    net_upload(c, noise, on_device, n.act.as<cx<float>>());
+    net_upload(c, target, on_device, n.g2.as<cx<float>>());
+    net_forward(c);
+    double L = net_loss(c);
+    net_backward(c);
+    n.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    float c1 = 1.f - std::pow(b1, (float)n.step), c2 = 1.f - std::pow(b2, (float)n.step);
+    launch_adam(n.nreal, n.params.as<float>(), n.grads.as<float>(), n.m.as<float>(), n.v.as<float>(), (float)lr, b1,
+                b2, 1e-8f, c1, c2, c.st);
+    c.sync();
+    if (loss) *loss = L;
+    return DDAMG_OK;
+  });
+}
+
+}  // extern "C"

@@ -102,6 +102,20 @@ template <class R, class S>
 void launch_coarse_schur_even(const CGeom& cg, const void* D, double tw, const cx<R>* v, const cx<R>* t, cx<R>* out,
                               int mode, hipStream_t st);
 
+// ------------------------------------------------------------- learned setup
+void launch_net_mix(const Geom& g, int C, const cx<float>* U, const cx<float>* in, const cx<float>* W, cx<float>* out,
+                    bool adj, hipStream_t st);
+void launch_net_gate(const Geom& g, int C, const cx<float>* z, const float* a, const float* b, cx<float>* y, float* sv,
+                     hipStream_t st);
+void launch_net_gate_bwd(const Geom& g, int C, const cx<float>* Gy, const cx<float>* z, const float* sv,
+                         const float* a, cx<float>* Gz, double* partial, float* Ga, float* Gb, hipStream_t st);
+void launch_net_wgrad(const Geom& g, int C, const cx<float>* U, const cx<float>* x, const cx<float>* Gz,
+                      cx<float>* partial, int nwg, cx<float>* GW, hipStream_t st);
+void launch_net_loss(const Geom& g, int C, const cx<float>* Y, const cx<float>* Q, double inv_norm, cx<double>* scr,
+                     cx<float>* GY, double* lpart, hipStream_t st);
+void launch_adam(long n, float* p, const float* gr, float* m, float* v, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st);
+
 // ---------------------------------------------------------------------- BLAS
 // partial sums of <V_i, w> (i < k) into partial[i][nwg]; then reduced into out
 template <class R>

@@ -134,6 +134,21 @@ struct MGBase {
   long vcycles = 0;
 };
 
+// learned-setup network: parameters (real view, FP32), Adam moments, activations
+struct NetState {
+  int L = 0, C = 0;
+  long nWc = 0;       // complex weights per layer: 9*C*C*16
+  long nreal = 0;     // real parameters in total
+  DevBuf params, grads, m, v;
+  DevBuf act, zb, sb, g1, g2, wpart, gpart, lscr, lpart, host_stage;
+  long V = 0;         // lattice the buffers are sized for
+  long step = 0;
+  cx<float>* W(int l) const { return params.as<cx<float>>() + (long)l * nWc; }
+  float* ab(int l) const { return params.as<float>() + 2 * (long)L * nWc + 2L * l * C; }
+  cx<float>* GW(int l) const { return grads.as<cx<float>>() + (long)l * nWc; }
+  float* Gab(int l) const { return grads.as<float>() + 2 * (long)L * nWc + 2L * l * C; }
+};
+
 struct Ctx {
   hipStream_t st = nullptr;
   Geom g{};
@@ -151,6 +166,7 @@ struct Ctx {
   ddamg_params p{};
   std::unique_ptr<MGBase> mg;
   KrylovWS<double> outer;
+  NetState net;
   KernelTimer timer;
   std::string err;
 

@@ -18,6 +18,12 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ddamg.h")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+# torch ships its own HIP runtime; load it first so that the library binds to
+# the same runtime (one HIP context per process, shared streams and pointers)
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, NOT_CONVERGED, INVALID_ARG, BAD_STATE, HIP_ERROR, OUT_OF_MEMORY, NUMERICAL = 0, 1, -1, -2, -3, -4, -5
@@ -97,11 +103,39 @@ _SIGS = {
     "ddamg_bench_dirac": (_i, [_vp, _i, _i]),
     "ddamg_timing": (_i, [_vp, _i]),
     "ddamg_timing_query": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
+    "ddamg_net_create": (_i, [_vp, _i, _i]),
+    "ddamg_net_num_params": (ctypes.c_long, [_vp]),
+    "ddamg_net_set_params": (_i, [_vp, ctypes.POINTER(_d), ctypes.c_long]),
+    "ddamg_net_get_params": (_i, [_vp, ctypes.POINTER(_d), ctypes.c_long]),
+    "ddamg_net_forward": (_i, [_vp, _vp, _vp, _i]),
+    "ddamg_net_loss_grad": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "ddamg_net_train_step": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(_d)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
     _f.argtypes = _args
+
+
+def pack_net(W, a, b):
+    """Flat FP64 parameter vector of the network: every layer's W [9,C,C,4,4]
+    complex (real/imag interleaved), then (a_l, b_l) of the gated layers."""
+    parts = [np.asarray(w, dtype=np.complex128).reshape(-1).view(np.float64) for w in W]
+    for al, bl in zip(a, b):
+        parts += [np.asarray(al, dtype=np.float64), np.asarray(bl, dtype=np.float64)]
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def unpack_net(v, C, L):
+    nW = 9 * C * C * 16
+    W = [v[2 * l * nW: 2 * (l + 1) * nW].view(np.complex128).reshape(9, C, C, 4, 4) for l in range(L)]
+    off = 2 * L * nW
+    a, b = [], []
+    for l in range(L - 1):
+        a.append(v[off: off + C])
+        b.append(v[off + C: off + 2 * C])
+        off += 2 * C
+    return W, a, b
 
 
 def exported_symbols():
@@ -179,9 +213,9 @@ class DDAMG:
         self.params = None
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.ddamg_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -329,6 +363,48 @@ class DDAMG:
         out = np.empty_like(v)
         self._check(_lib.ddamg_vcycle(self._h, _ptr(v)[0], _ptr(out)[0]))
         return out
+
+    # ---- learned setup ---------------------------------------------------------
+    def net_create(self, nlayers, nchan):
+        self._check(_lib.ddamg_net_create(self._h, int(nlayers), int(nchan)))
+        self.net_shape = (int(nlayers), int(nchan))
+
+    def net_set_params(self, vec):
+        vec = np.ascontiguousarray(vec, dtype=np.float64)
+        self._check(_lib.ddamg_net_set_params(self._h, vec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              vec.size))
+
+    def net_get_params(self):
+        n = _lib.ddamg_net_num_params(self._h)
+        out = np.empty(n, dtype=np.float64)
+        self._check(_lib.ddamg_net_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n))
+        return out
+
+    def net_forward(self, noise):
+        noise = _c128(noise)
+        out = np.empty_like(noise) if not _is_torch(noise) else noise.new_empty(noise.shape)
+        pn, dev = _ptr(noise)
+        self._check(_lib.ddamg_net_forward(self._h, pn, _ptr(out)[0], dev))
+        return out
+
+    def net_loss_grad(self, noise, target, want_grad=True):
+        noise, target = _c128(noise), _c128(target)
+        pn, dev = _ptr(noise)
+        loss = ctypes.c_double()
+        g = None
+        gp = None
+        if want_grad:
+            g = np.empty(_lib.ddamg_net_num_params(self._h), dtype=np.float64)
+            gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._check(_lib.ddamg_net_loss_grad(self._h, pn, _ptr(target)[0], dev, ctypes.byref(loss), gp))
+        return loss.value, g
+
+    def net_train_step(self, noise, target, lr):
+        noise, target = _c128(noise), _c128(target)
+        pn, dev = _ptr(noise)
+        loss = ctypes.c_double()
+        self._check(_lib.ddamg_net_train_step(self._h, pn, _ptr(target)[0], dev, float(lr), ctypes.byref(loss)))
+        return loss.value
 
     # ---- measurement ---------------------------------------------------------
     def bench_dirac(self, napply, precision="fp64"):
