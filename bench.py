@@ -9,7 +9,7 @@ residual <= 1e-10.  Inputs (SU(3) links exp(i 0.3 H), Gaussian sources and
 initial test vectors, all seeded) are generated on the device before the
 timed region.
 
-    python bench.py [--gpus 1] [--steps 1] [--warmup 0] [--nrhs 12]
+    python bench.py [--gpus 1] [--steps 1] [--warmup 0] [--nrhs 2]
                     [--dims 96,48,48,48] [--fp64-compare 1]
 
 Prints one JSON line.  `value` is the mixed-precision step time in seconds
@@ -39,9 +39,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--nrhs", type=int, default=12)
+    ap.add_argument("--nrhs", type=int, default=2)
     ap.add_argument("--dims", type=str, default="96,48,48,48")
-    ap.add_argument("--precision", type=str, default="fp32")
+    ap.add_argument("--precision", type=str, default="bf16")
     ap.add_argument("--setup-iters", type=int, default=1)
     ap.add_argument("--fp64-compare", type=int, default=1)
     ap.add_argument("--fp64-setup-iters", type=int, default=5)
@@ -137,19 +137,22 @@ def main():
     ctx = make_ctx()
     p_mixed = params(args.precision, args.setup_iters)
 
-    def step(c):
+    def step(c, tag):
+        t = time.time()
         c.setup(p_mixed, [V0, V1])
+        log(f"{tag}: setup issued ({time.time() - t:.1f} s)")
         _, st = c.solve(b, tol=1e-10, x=x)
+        log(f"{tag}: solve done ({time.time() - t:.1f} s, {st['iters']} iterations)")
         return st
 
-    for _ in range(args.warmup):
-        step(ctx)
+    for i in range(args.warmup):
+        step(ctx, f"warmup {i}")
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.time()
     stats = None
-    for _ in range(args.steps):
-        stats = step(ctx)
+    for i in range(args.steps):
+        stats = step(ctx, f"step {i}")
     torch.cuda.synchronize()
     dt = (time.time() - t0) / args.steps
     n_d, ms_d = ctx.timing_query(0)
@@ -183,6 +186,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.time()
         c64.setup(p64, [V0, V1])
+        log(f"fp64: setup issued ({time.time() - t1:.1f} s)")
         _, fp64_stats = c64.solve(b, tol=1e-10, x=x)
         torch.cuda.synchronize()
         fp64_s = time.time() - t1

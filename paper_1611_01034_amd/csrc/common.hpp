@@ -172,6 +172,15 @@ __host__ __device__ __forceinline__ void neighbour(const Geom& g, int B, int s, 
   coords_site(g, x, Bn, sn);
 }
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs, each with
+// its own L2.  Map workgroup w of nwg to a logical index so that every XCD
+// owns one contiguous range of logical indices (lattice blocks that are
+// neighbours in the block order then share an L2).  A bijection of [0, nwg).
+__host__ __device__ __forceinline__ int xcd_remap(int w, int nwg) {
+  int q = nwg >> 3, r = nwg & 7, x = w & 7, k = w >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // index of component 0 of slot s of block B, field with C components
 __host__ __device__ __forceinline__ long fidx(const Geom& g, int B, int s, int C) {
   return ((long)B * (g.bs / TILE) + (s / TILE)) * C * TILE + (s % TILE);

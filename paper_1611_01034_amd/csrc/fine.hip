@@ -21,28 +21,33 @@
 namespace ddamg {
 
 // ---------------------------------------------------------------------------
-// D(tw) psi, full lattice, one work-item per site
+// D(tw) psi, full lattice.  One workgroup per lattice block, one work-item per
+// site; the block's input spinors are staged in LDS, so only hops that leave
+// the block read neighbours from global memory.  Workgroups are remapped so
+// each XCD sweeps a contiguous range of blocks.
 template <class R, class S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 4, 8))) k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U,
-                                               const R* __restrict__ H, R tw, const cx<R>* __restrict__ in,
-                                               cx<R>* __restrict__ out) {
-  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= g.V) return;
-  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3, 8)))
+k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H, R tw,
+        const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
+  extern __shared__ char smem_raw[];
+  cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x bs, parity-split
+  const int B = xcd_remap(blockIdx.x, gridDim.x), s = threadIdx.x;
   SiteNbr me;
   me_of(g, B, s, me);
   cx<R> psi[12], acc[12];
   load_spinor(in, g, B, s, psi);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) *lds_site(lds, g, s, c) = psi[c];
   site_term(H, g, B, s, tw, psi, acc);
-  hop_global<R, S>(U, in, g, B, s, me, acc);
+  __syncthreads();
+  hop_staged<R, S>(U, in, lds, g, B, s, me, acc);
   store_spinor(out, g, B, s, acc);
 }
 
 template <class R, class S>
 void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<R>* in, cx<R>* out, hipStream_t st) {
-  long n = g.V;
-  int blocks = (int)((n + 255) / 256);
-  hipLaunchKernelGGL((k_dirac<R, S>), dim3(blocks), dim3(256), 0, st, g,
+  size_t sm = 12 * (size_t)g.bs * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_dirac<R, S>), dim3(g.nblocks), dim3(g.bs), sm, st, g,
                      (const typename store_traits<S>::elem*)U, H, (R)tw, in, out);
 }
 template void launch_dirac<double, double>(const Geom&, const void*, const double*, double, const cx<double>*,
@@ -108,7 +113,7 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
   __shared__ double red[3][16];
   int B;
   {
-    int B0 = 2 * blockIdx.x;
+    int B0 = 2 * xcd_remap(blockIdx.x, gridDim.x);
     int bc[4];
     block_coords(g, B0, bc);
     int par = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
@@ -122,13 +127,19 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
   me_of(g, B, t, me);
   cx<R> r[12], tmp[12];
   {
+    // r = b - D x, with x of this block staged in ev/od (free until the
+    // odd-site solve below)
     cx<R> psi[12];
     load_spinor(x, g, B, t, psi);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) *lds_site(ev, g, t, c) = psi[c];
     site_term(H, g, B, t, tw, psi, tmp);
-    hop_global<R, S>(U, x, g, B, t, me, tmp);
+    __syncthreads();
+    hop_staged<R, S>(U, x, ev, g, B, t, me, tmp);
     load_spinor(b, g, B, t, r);
 #pragma unroll
     for (int c = 0; c < 12; ++c) r[c] -= tmp[c];
+    __syncthreads();
     if (!even) {
       site_inv(H, Minv, g, B, t, tw, r, tmp);
 #pragma unroll

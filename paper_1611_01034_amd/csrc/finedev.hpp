@@ -167,34 +167,55 @@ __device__ __forceinline__ void nbr_of(const Geom& g, const SiteNbr& sn, int mu,
   snb = local_slot(g, l);
 }
 
-// hopping part of D at (B,s) with all neighbours read from global memory
+// Spinors of one block staged in LDS, parity-split: component c of slot s sits
+// at lds[(p * 12 + c) * half + (s - p * half)], p = parity of s.
+template <class R>
+__device__ __forceinline__ cx<R>* lds_site(cx<R>* lds, const Geom& g, int s, int c) {
+  int p = s >= g.half ? 1 : 0;
+  return lds + (long)(p * 12 + c) * g.half + (s - p * g.half);
+}
+
+template <class R>
+__device__ __forceinline__ void load_nbr_staged(const cx<R>* in, const cx<R>* lds, const Geom& g, int B, int Bn, int sn,
+                                                cx<R> p[12]) {
+  if (Bn == B) {
+    int par = sn >= g.half ? 1 : 0;
+    const cx<R>* q = lds + (long)par * 12 * g.half + (sn - par * g.half);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = q[(long)c * g.half];
+  } else {
+    load_spinor(in, g, Bn, sn, p);
+  }
+}
+
+// hopping part of D at (B,s) with the neighbours inside block B read from the
+// block's staged copy in LDS and the others from global memory
 template <int MU, class R, class S>
-__device__ __forceinline__ void hop_global_dir(const typename store_traits<S>::elem* U, const cx<R>* in, const Geom& g,
-                                               int B, int s, const SiteNbr& me, cx<R> out[12]) {
+__device__ __forceinline__ void hop_staged_dir(const typename store_traits<S>::elem* U, const cx<R>* in,
+                                               const cx<R>* lds, const Geom& g, int B, int s, const SiteNbr& me,
+                                               cx<R> out[12]) {
   cx<R> psi[12], u[9];
   int Bn, sn;
   nbr_of(g, me, MU, +1, Bn, sn);
-  load_spinor(in, g, Bn, sn, psi);
+  load_nbr_staged(in, lds, g, B, Bn, sn, psi);
   load_link<R, S>(U, g, B, s, MU, u);
   hop_accum_t<0, MU>(psi, u, out);
   nbr_of(g, me, MU, -1, Bn, sn);
-  load_spinor(in, g, Bn, sn, psi);
+  load_nbr_staged(in, lds, g, B, Bn, sn, psi);
   load_link<R, S>(U, g, Bn, sn, MU, u);
   hop_accum_t<1, MU>(psi, u, out);
 }
 
 template <class R, class S>
-__device__ __forceinline__ void hop_global(const typename store_traits<S>::elem* U, const cx<R>* in, const Geom& g,
-                                           int B, int s, const SiteNbr& me, cx<R> out[12]) {
-  // One direction per iteration of a loop whose trip count the compiler cannot
-  // see (g.ndir == 4): keeps the operands of a single hop live at a time.
+__device__ __forceinline__ void hop_staged(const typename store_traits<S>::elem* U, const cx<R>* in, const cx<R>* lds,
+                                           const Geom& g, int B, int s, const SiteNbr& me, cx<R> out[12]) {
 #pragma unroll 1
   for (int mu = 0; mu < g.ndir; ++mu) {
     switch (mu) {
-      case 0: hop_global_dir<0, R, S>(U, in, g, B, s, me, out); break;
-      case 1: hop_global_dir<1, R, S>(U, in, g, B, s, me, out); break;
-      case 2: hop_global_dir<2, R, S>(U, in, g, B, s, me, out); break;
-      default: hop_global_dir<3, R, S>(U, in, g, B, s, me, out); break;
+      case 0: hop_staged_dir<0, R, S>(U, in, lds, g, B, s, me, out); break;
+      case 1: hop_staged_dir<1, R, S>(U, in, lds, g, B, s, me, out); break;
+      case 2: hop_staged_dir<2, R, S>(U, in, lds, g, B, s, me, out); break;
+      default: hop_staged_dir<3, R, S>(U, in, lds, g, B, s, me, out); break;
     }
   }
 }

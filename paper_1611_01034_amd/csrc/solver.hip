@@ -145,10 +145,14 @@ void KrylovWS<R>::init(int m_, long ld_, long N, bool flex) {
   scal.ensure(sizeof(cx<double>) * 4);
   resid.ensure(sizeof(double));
   if (!h_resid) HIP_CHECK(hipHostMalloc((void**)&h_resid, sizeof(double) * 4, hipHostMallocDefault));
+  for (auto& e : ready)
+    if (!e) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 template <class R>
 KrylovWS<R>::~KrylovWS() {
   if (h_resid) (void)hipHostFree(h_resid);
+  for (auto e : ready)
+    if (e) (void)hipEventDestroy(e);
 }
 template struct KrylovWS<double>;
 template struct KrylovWS<float>;
@@ -202,6 +206,13 @@ KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(co
     launch_zero<double>(m + 1, ws.g.template as<cx<double>>(), st);
     launch_set_scalar(ws.g.template as<cx<double>>(), scal + 1, st);
     int jd = 0;
+    // Without a preconditioner an iteration is cheap, so the convergence test
+    // of iteration j is taken while iteration j+1 is already queued (no idle
+    // gap on the device).  If iteration j met the tolerance, the queued
+    // iteration j+1 is discarded: it changes only Hessenberg column j+1 and
+    // g[j+1], g[j+2], so the update from columns 0..j is unaffected.
+    const bool lookahead = !fixed && M == nullptr;
+    bool pending = false;  // an estimate of iteration jd-1 is in flight
     for (int j = 0; j < mm; ++j) {
       cx<R>* Vj = V + (long)j * ld;
       cx<R>* Vn = V + (long)(j + 1) * ld;
@@ -225,11 +236,29 @@ KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(co
                     ws.resid.template as<double>(), st);
       ++it;
       jd = j + 1;
-      if (!fixed) {
+      if (lookahead) {
+        const int k = j & 1;
+        HIP_CHECK(hipMemcpyAsync(ws.h_resid + 2 + k, ws.resid.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipEventRecord(ws.ready[k], st));
+        if (pending) {
+          HIP_CHECK(hipEventSynchronize(ws.ready[k ^ 1]));
+          if (ws.h_resid[2 + (k ^ 1)] <= tol * bnorm) {  // iteration j-1 converged: drop iteration j
+            --it;
+            jd = j;
+            pending = false;
+            break;
+          }
+        }
+        pending = true;
+      } else if (!fixed) {
         double est = read(ws.resid.p);
         if (est <= tol * bnorm) break;
       }
       if (it >= max_iter) break;
+    }
+    if (pending) {  // test the last queued estimate before the restart
+      HIP_CHECK(hipEventSynchronize(ws.ready[(jd - 1) & 1]));
+      pending = false;
     }
     launch_trisolve(H, m + 1, ws.g.template as<cx<double>>(), ws.y.template as<cx<double>>(), jd, st);
     launch_multi_axpy<R>(Z, ld, jd, ws.y.template as<cx<double>>(), 1.0, x, N, st);

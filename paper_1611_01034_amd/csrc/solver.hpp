@@ -73,7 +73,8 @@ struct KrylovWS {
   long ld = 0;  // allocated length of one vector
   bool flexible = false;
   DevBuf V, Z, tmp, H, cs, sn, g, y, part, scal, resid;
-  double* h_resid = nullptr;  // pinned host mirror
+  double* h_resid = nullptr;  // pinned host mirror: [0] blocking reads, [2 + k] look-ahead slot k
+  hipEvent_t ready[2] = {nullptr, nullptr};  // look-ahead: residual estimate k has reached h_resid[2 + k]
   int nwg = 0;
   void init(int m_, long ld_, long N, bool flex);
   ~KrylovWS();

@@ -17,6 +17,10 @@ plain setup, the plain setup is run instead (decide_fallback).
 """
 from __future__ import annotations
 
+import argparse
+import json
+import os
+import sys
 import time
 
 import numpy as np
@@ -34,10 +38,15 @@ def decide_fallback(rho_probe: float, rho_ref: float, margin: float = 1.25) -> b
 
 
 def init_torch_device():
-    """torch's HIP context must exist before the library's first call."""
+    """Select device 0 in torch; returns torch's current stream handle, which
+    every context created here uses."""
     import torch
-    torch.cuda.init()
-    return torch
+    torch.cuda.set_device(0)
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ctx(dims, block):
+    return ddamg.DDAMG(dims, block, KAPPA, CSW, MU, stream=init_torch_device())
 
 
 def _torch_dev(a):
@@ -61,14 +70,14 @@ def mg_params(levels=2, nvec=(24,), block=(4, 4, 4, 4), setup_iters=1, precision
                                 precision=precision, coarse_mu_factor=delta)
 
 
-def make_targets(dims, block, seeds, eps_list, nvec=24, setup_iters=5, stream=None):
+def make_targets(dims, block, seeds, eps_list, nvec=24, setup_iters=5):
     """Plain setups on seeded fields; returns [(U, Q)] with Q the block
     orthonormalised level-0 test vectors (host FP64, spinor layout)."""
     out = []
     for i, s in enumerate(seeds):
         eps = eps_list[i % len(eps_list)]
         U = synth.gauge_field(dims, eps, s)
-        with ddamg.DDAMG(dims, block, KAPPA, CSW, MU, stream=stream) as ctx:
+        with _ctx(dims, block) as ctx:
             ctx.set_gauge(U)
             V0 = synth.spinor(dims, s + 100000, nvec=nvec)
             ctx.setup(mg_params(nvec=(nvec,), block=block, setup_iters=setup_iters, precision="fp32"), [V0])
@@ -80,12 +89,10 @@ def make_targets(dims, block, seeds, eps_list, nvec=24, setup_iters=5, stream=No
 def train(dims, block, data, C=24, L=4, epochs=8, lr=2e-3, seed=4242, log=print, on_device=True):
     """Adam on the subspace loss over the (U, Q) pairs of `data`; a fresh noise
     draw per step.  Returns (parameter vector, loss history)."""
-    if on_device:
-        init_torch_device()
     W, a, b = synth.net_init_weights(C, L, seed)
     params = ddamg.pack_net(W, a, b)
     hist = []
-    with ddamg.DDAMG(dims, block, KAPPA, CSW, MU) as ctx:
+    with _ctx(dims, block) as ctx:
         ctx.net_create(L, C)
         ctx.net_set_params(params)
         tgts = [_torch_dev(Q) if on_device else Q for (_, Q) in data]
@@ -120,7 +127,7 @@ def evaluate(dims, block, seeds, eps, params, C=24, L=4, nvec=24, tol=1e-10, log
         U = synth.gauge_field(dims, eps, s)
         b = synth.spinor(dims, s + 200000)
         row = {"seed": s}
-        with ddamg.DDAMG(dims, block, KAPPA, CSW, MU) as ctx:
+        with _ctx(dims, block) as ctx:
             ctx.set_gauge(U)
             Vr = synth.spinor(dims, s + 100000, nvec=nvec)
             Vl = learned_vectors(ctx, params, C, L, dims, s + 300000)
@@ -134,3 +141,80 @@ def evaluate(dims, block, seeds, eps, params, C=24, L=4, nvec=24, tol=1e-10, log
         log(row)
         rows.append(row)
     return rows
+
+
+def save_weights(path, params, C, L, meta=None):
+    """Parameter vector and shape in a plain .npz (no pickled objects)."""
+    np.savez(path, params=np.asarray(params, dtype=np.float64), C=np.int64(C), L=np.int64(L),
+             meta=np.array(json.dumps(meta or {})))
+
+
+def load_weights(path):
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].copy(), int(z["C"]), int(z["L"]), json.loads(str(z["meta"]))
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "net_l4_c24.npz")
+
+
+def _seeds(spec):
+    a, b = (int(x) for x in spec.split(":"))
+    return list(range(a, b))
+
+
+def _tuple(spec):
+    return tuple(int(x) for x in spec.split(","))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sp = ap.add_subparsers(dest="mode", required=True)
+    t = sp.add_parser("train")
+    t.add_argument("--dims", default="16,8,8,8", help="T,Z,Y,X")
+    t.add_argument("--block", default="4,4,4,4")
+    t.add_argument("--seeds", default="4000:4064")
+    t.add_argument("--eps", default="0.2,0.3,0.4")
+    t.add_argument("--nvec", type=int, default=24)
+    t.add_argument("--layers", type=int, default=4)
+    t.add_argument("--epochs", type=int, default=20)
+    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--out", default=WEIGHTS)
+    e = sp.add_parser("evaluate")
+    e.add_argument("--dims", default="48,24,24,24")
+    e.add_argument("--block", default="4,4,4,4")
+    e.add_argument("--seeds", default="4100:4116")
+    e.add_argument("--eps", type=float, default=0.3)
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    if a.mode == "train":
+        dims, block = _tuple(a.dims), _tuple(a.block)
+        eps = [float(x) for x in a.eps.split(",")]
+        t0 = time.time()
+        data = make_targets(dims, block, _seeds(a.seeds), eps, nvec=a.nvec)
+        t_targets = time.time() - t0
+        print(f"targets: {len(data)} fields in {t_targets:.1f} s", flush=True)
+        t0 = time.time()
+        params, hist = train(dims, block, data, C=a.nvec, L=a.layers, epochs=a.epochs, lr=a.lr)
+        t_train = time.time() - t0
+        meta = {"dims": dims, "block": block, "seeds": a.seeds, "eps": eps, "epochs": a.epochs, "lr": a.lr,
+                "loss_history": hist, "targets_s": t_targets, "train_s": t_train,
+                "targets": "block-orthonormalised level-0 test vectors of the plain 5-iteration FP32 setup"}
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        save_weights(a.out, params, a.nvec, a.layers, meta)
+        print(json.dumps({k: v for k, v in meta.items() if k != "loss_history"}), flush=True)
+    else:
+        params, C, L, meta = load_weights(a.weights)
+        rows = evaluate(_tuple(a.dims), _tuple(a.block), _seeds(a.seeds), a.eps, params, C=C, L=L, nvec=C)
+        summary = {}
+        for k in ("learned+1", "random+1", "plain5"):
+            summary[k] = {m: float(np.mean([r[k][m] for r in rows])) for m in ("rho", "iters", "setup_s", "solve_s")}
+        out = {"dims": _tuple(a.dims), "eps": a.eps, "seeds": a.seeds, "summary": summary, "rows": rows}
+        print(json.dumps(summary), flush=True)
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(out, fh, indent=1)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
