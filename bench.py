@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--fp64-compare", type=int, default=1)
     ap.add_argument("--fp64-setup-iters", type=int, default=5)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--rhs-batch", type=int, default=2)
+    ap.add_argument("--learned", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=16)
     return ap.parse_args()
 
 
@@ -121,25 +124,40 @@ def main():
     U = synth.gauge_field_device(dims, 0.3, 5001)
     b = synth.gaussian_device((args.nrhs,) + dims + (4, 3), 5101)
     x = torch.empty_like(b)
-    V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
     V1 = synth.gaussian_device((nv[1],) + cd + (2 * nv[0],), 5502)
+    if args.learned:
+        from paper_1611_01034_amd import learned_setup
+        wts, C, L, _ = learned_setup.load_weights(learned_setup.WEIGHTS)
+        if C != nv[0]:
+            raise SystemExit("network channels must equal the level-0 test vector count")
+        noise = synth.gaussian_device((C,) + dims + (4, 3), 5501, dtype="complex64")
+        V0 = None
+    else:
+        V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
     torch.cuda.synchronize()
 
-    def make_ctx():
+    def make_ctx(net=False):
         c = ddamg.DDAMG(dims, block, KAPPA, CSW, MU, stream=stream.cuda_stream)
         c.set_gauge(U)
+        if net:
+            c.net_create(L, C)
+            c.net_set_params(wts)
         return c
 
-    def params(prec, setup_iters):
+    def params(prec, setup_iters, rhs_batch, batch):
         return ddamg.default_params(levels=levels, block=[block, (2, 2, 2, 2)], nvec=nv, setup_iters=setup_iters,
-                                    coarse_setup_iters=3, precision=prec, coarse_mu_factor=5.0)
+                                    coarse_setup_iters=3, precision=prec, coarse_mu_factor=5.0, batch=batch,
+                                    rhs_batch=rhs_batch)
 
-    ctx = make_ctx()
-    p_mixed = params(args.precision, args.setup_iters)
+    ctx = make_ctx(net=bool(args.learned))
+    p_mixed = params(args.precision, args.setup_iters, min(args.rhs_batch, args.nrhs), args.batch)
 
     def step(c, tag):
         t = time.time()
-        c.setup(p_mixed, [V0, V1])
+        if args.learned:
+            c.setup_learned(p_mixed, noise, V1)
+        else:
+            c.setup(p_mixed, [V0, V1])
         log(f"{tag}: setup issued ({time.time() - t:.1f} s)")
         _, st = c.solve(b, tol=1e-10, x=x)
         log(f"{tag}: solve done ({time.time() - t:.1f} s, {st['iters']} iterations)")
@@ -181,8 +199,13 @@ def main():
     fp64_s = None
     fp64_stats = None
     if args.fp64_compare:
+        if V0 is None:
+            del noise
+            torch.cuda.empty_cache()
+            V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
         c64 = make_ctx()
-        p64 = params("fp64", args.fp64_setup_iters)
+        # FP64 fine fields are twice the size: 4 test vectors per setup batch
+        p64 = params("fp64", args.fp64_setup_iters, 1, min(args.batch, 4))
         torch.cuda.synchronize()
         t1 = time.time()
         c64.setup(p64, [V0, V1])
@@ -213,7 +236,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(str(d) for d in reversed(dims))} twisted-mass Wilson-clover, "
                                f"kappa {KAPPA}, c_sw {CSW}, mu {MU}, delta 5, 3 levels (4^4, 2^4 aggregates, "
-                               f"Nv 24/32), {args.nrhs} rhs, setup {args.setup_iters} iteration(s), "
+                               f"Nv 24/32), {args.nrhs} rhs ({min(args.rhs_batch, args.nrhs)} in lock step), "
+                               f"{'learned' if args.learned else 'random'} initial test vectors + "
+                               f"{args.setup_iters} setup iteration(s) on batches of {args.batch} test vectors, "
                                f"preconditioner {args.precision}, outer FGMRES FP64, tol 1e-10",
                    "global_batch": args.nrhs, "parallelism": "none"},
         "roofline": {"bound": "hbm", "kernel": "D(mu) FP64 full-lattice apply",

@@ -90,6 +90,14 @@ typedef struct ddamg_params {
   double coarse_tol;           /* (default 0.1) */
   int precision;               /* DDAMG_FP64 / FP32 / FP16 / BF16 */
   int fixed_iters;             /* 1: inner solves run exactly their max iteration counts */
+  int batch;                   /* test vectors the setup advances together through one lock-step
+                                  V-cycle (1 = one at a time; default 16, at most 16).  With
+                                  FP16/BF16 storage the coarse operators of a batch run on the
+                                  matrix cores. */
+  int rhs_batch;               /* right-hand sides ddamg_solve advances together: one lock-step
+                                  outer FGMRES whose V-cycles and coarse solves serve all of them
+                                  (default 1, at most 16).  Each holds its own FP64 Krylov basis of
+                                  2 * restart + 1 fine fields. */
 } ddamg_params;
 
 typedef struct ddamg_stats {
@@ -141,6 +149,19 @@ int ddamg_setup(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_v
  * setup iteration): P from their block orthonormalisation, D_c by Galerkin
  * assembly.  Same shapes as ddamg_setup. */
 int ddamg_set_test_vectors(ddamg_ctx* ctx, const ddamg_params* p, const void* const* vectors, int on_device);
+/* Adaptive setup started from the learned network's vectors instead of random
+ * ones (the network of ddamg_net_create / ddamg_net_set_params, C channels;
+ * p->nvec[0] must equal C).  noise: the network input, C fields of the fine
+ * lattice, lexicographic TZYX [C][V][4][3], complex128 (noise_precision =
+ * DDAMG_FP64) or complex64 (DDAMG_FP32), caller-owned, host or device
+ * (on_device).  The network runs in FP32 with two C-channel buffers that are
+ * freed on return; its output takes the place of init_vectors[0] of
+ * ddamg_setup, after which the setup proceeds exactly as there (p->init_sap_iters
+ * smoothing, p->setup_iters refinement iterations).  coarse_init: level-1
+ * initial vectors for three levels (as init_vectors[1] of ddamg_setup), else
+ * ignored. */
+int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise, int noise_precision,
+                        int on_device, const void* coarse_init);
 
 /* Solve D(mu) x_r = b_r for nrhs right-hand sides (spinor layout, nrhs
  * contiguous fields) with FGMRES preconditioned by Eq. (1), stopping at a
@@ -175,12 +196,28 @@ int ddamg_coarse_sap(ddamg_ctx* ctx, int level, const void* b, void* x, int iter
 int ddamg_coarse_solve(ddamg_ctx* ctx, int level, const void* b, void* x);
 /* out = V-cycle (Eq. 1) applied to in on the fine level, x0 = 0. */
 int ddamg_vcycle(ddamg_ctx* ctx, const void* in, void* out);
+/* The coarse operator of level l >= 1 (Sec. 1, D_c = P^dag D P with the
+ * Gamma5,c-hermitian backward couplings and the twist of the level) on nrhs
+ * fields at once, 1 <= nrhs <= 16.  in, out: host complex128 [nrhs][len_l],
+ * caller-owned, same layout as ddamg_apply_coarse.  With FP16/BF16 storage
+ * and 2 N_v a multiple of 16 the products run on the matrix cores with the
+ * inputs rounded to the storage format (FP32 accumulation, twist in FP32);
+ * otherwise the single-field kernel runs once per field. */
+int ddamg_apply_coarse_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out);
+/* Coarse solves of nrhs right-hand sides in lock step (one operator launch
+ * per step for all of them; each keeps its own Krylov space and stopping
+ * test).  Same solver and layout as ddamg_coarse_solve; 1 <= nrhs <= 16. */
+int ddamg_coarse_solve_multi(ddamg_ctx* ctx, int level, int nrhs, const void* b, void* x);
 
 /* ---- measurement ---- */
 /* Run napply applications of D(mu) on device-resident fields in the
  * library's own layout (inputs already in HBM), on the context stream;
  * returns immediately after enqueueing. */
 int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply);
+/* napply applications of the level-l coarse operator to nrhs device-resident
+ * fields at once (which = 0: full stencil; 1: odd-even reduced operator of the
+ * coarsest level), precision of the last setup; enqueued on the context stream. */
+int ddamg_bench_coarse(ddamg_ctx* ctx, int level, int nrhs, int napply, int which);
 /* Per-kernel timing with HIP events on the context stream.  kind: 0 = FP64
  * D(mu) (outer operator), 1 = fine SAP colour sweep, 2 = coarse operator
  * apply (intermediate levels, residuals included), 3 = restriction and

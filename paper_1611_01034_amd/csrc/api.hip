@@ -113,6 +113,8 @@ void check_params(const ddamg_params* p) {
     throw Error(INVALID_ARG, "coarse_mu_factor (delta) must be >= 1");
   if (!(p->inter_tol > 0) || !(p->coarse_tol > 0)) throw Error(INVALID_ARG, "inner tolerances must be > 0");
   if (p->precision < 0 || p->precision > 3) throw Error(INVALID_ARG, "unknown precision");
+  if (p->batch < 1 || p->batch > 16) throw Error(INVALID_ARG, "batch must be in [1, 16]");
+  if (p->rhs_batch < 1 || p->rhs_batch > 16) throw Error(INVALID_ARG, "rhs_batch must be in [1, 16]");
 }
 
 }  // namespace
@@ -151,6 +153,8 @@ void ddamg_default_params(ddamg_params* p) {
   p->coarse_tol = 0.1;
   p->precision = DDAMG_FP64;
   p->fixed_iters = 0;
+  p->batch = 16;
+  p->rhs_batch = 1;
 }
 
 int ddamg_create(const int dims[4], const int block[4], double kappa, double csw, double mu, void* stream,
@@ -350,7 +354,42 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
     int total_it = 0;
     bool all_conv = true;
     KrylovResult kr;
-    for (int r = 0; r < nrhs; ++r) {
+    const int Kb = std::min(nrhs, c.p.rhs_batch);
+    if (Kb > 1) {
+      // right-hand sides in groups of Kb through one lock-step outer FGMRES
+      c.outer.V.release();
+      c.outer.Z.release();
+      c.outer.tmp.release();
+      KrylovWSm<double> ws;
+      ws.init(c.p.restart, Kb, N, N, true);
+      DevBuf bK, xK;
+      bK.alloc(sizeof(cx<double>) * N * Kb);
+      xK.alloc(sizeof(cx<double>) * N * Kb);
+      OpM<double> AK = [&c, N](const cx<double>* in, cx<double>* out, int K) {
+        for (int k = 0; k < K; ++k) c.dirac64(in + k * N, out + k * N, c.mu);
+      };
+      OpM<double> MK = [&c](const cx<double>* in, cx<double>* out, int K) { c.mg->precond_multi(in, out, K); };
+      double worst = 0;
+      for (int r0 = 0; r0 < nrhs; r0 += Kb) {
+        const int k = std::min(Kb, nrhs - r0);
+        for (int q = 0; q < k; ++q) {
+          const char* bs = (const char*)b + sizeof(cx<double>) * (size_t)N * (r0 + q);
+          c.upload_fine(bs, on_device, bK.as<cx<double>>() + (long)q * N);
+          check_finite(c, (const double*)(bK.as<cx<double>>() + (long)q * N), 2 * N);
+        }
+        KrylovResultM km = fgmres_multi<double>(c, ws, k, N, AK, &MK, bK.as<cx<double>>(), xK.as<cx<double>>(), tol,
+                                                c.p.max_iter, false, true);
+        for (int q = 0; q < k; ++q) {
+          char* xs = (char*)x + sizeof(cx<double>) * (size_t)N * (r0 + q);
+          c.download_fine(xK.as<cx<double>>() + (long)q * N, xs, on_device);
+          total_it += km.iters[q];
+          all_conv = all_conv && km.converged[q];
+          worst = std::max(worst, km.resid[q]);
+        }
+      }
+      kr.resid = worst;
+    }
+    for (int r = Kb > 1 ? nrhs : 0; r < nrhs; ++r) {
       const char* bs = (const char*)b + sizeof(cx<double>) * (size_t)N * r;
       char* xs = (char*)x + sizeof(cx<double>) * (size_t)N * r;
       c.upload_fine(bs, on_device, c.f64a.as<cx<double>>());
@@ -537,6 +576,36 @@ int ddamg_coarse_solve(ddamg_ctx* ctx, int level, const void* b, void* x) {
     return DDAMG_OK;
   });
 }
+int ddamg_apply_coarse_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 0);
+    if (nrhs < 1 || nrhs > 16 || !in || !out) throw Error(INVALID_ARG, "nrhs must be in [1, 16]");
+    c.mg->apply_coarse_multi_host(level, nrhs, (const cx<double>*)in, (cx<double>*)out);
+    return DDAMG_OK;
+  });
+}
+int ddamg_coarse_solve_multi(ddamg_ctx* ctx, int level, int nrhs, const void* b, void* x) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 0);
+    if (nrhs < 1 || nrhs > 16 || !b || !x) throw Error(INVALID_ARG, "nrhs must be in [1, 16]");
+    c.mg->coarse_solve_multi_host(level, nrhs, (const cx<double>*)b, (cx<double>*)x);
+    return DDAMG_OK;
+  });
+}
+int ddamg_bench_coarse(ddamg_ctx* ctx, int level, int nrhs, int napply, int which) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 0);
+    if (nrhs < 1 || nrhs > 16 || napply < 0 || which < 0 || which > 1) throw Error(INVALID_ARG, "bad arguments");
+    c.mg->bench_coarse_multi(level, nrhs, napply, which);
+    return DDAMG_OK;
+  });
+}
 int ddamg_vcycle(ddamg_ctx* ctx, const void* in, void* out) {
   if (!ctx) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {
@@ -662,6 +731,18 @@ void net_forward(Ctx& c) {
   }
 }
 
+// forward pass with two C-channel buffers (inference: no activations kept);
+// `in` holds the input and is overwritten; returns the buffer with the output
+cx<float>* net_infer(Ctx& c, cx<float>* in, cx<float>* tmp) {
+  NetState& n = c.net;
+  for (int l = 0; l < n.L; ++l) {
+    launch_net_mix(c.g, n.C, c.U32.as<cx<float>>(), in, n.W(l), tmp, false, c.st);
+    if (l < n.L - 1) launch_net_gate_inplace(c.g, n.C, n.ab(l), n.ab(l) + n.C, tmp, c.st);
+    std::swap(in, tmp);
+  }
+  return in;
+}
+
 // loss of the last layer's output against targets (in g2); gradient into g1
 double net_loss(Ctx& c) {
   NetState& n = c.net;
@@ -713,6 +794,57 @@ void net_params_to_host(const NetState& n, const DevBuf& buf, double* out, hipSt
 }  // namespace
 
 extern "C" {
+
+int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise, int noise_precision,
+                        int on_device, const void* coarse_init) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    check_params(p);
+    if (c.net.L == 0) throw Error(BAD_STATE, "no network: call ddamg_net_create and ddamg_net_set_params");
+    if (p->nvec[0] != c.net.C) throw Error(INVALID_ARG, "nvec[0] must equal the network's channel count");
+    if (!noise || (p->levels == 3 && !coarse_init)) throw Error(INVALID_ARG, "NULL input");
+    if (noise_precision != DDAMG_FP64 && noise_precision != DDAMG_FP32)
+      throw Error(INVALID_ARG, "noise must be complex128 (DDAMG_FP64) or complex64 (DDAMG_FP32)");
+    c.ensure_32();
+    const long fl = c.fine_len(), f = (long)c.net.C * fl;
+    DevBuf A, B;
+    A.alloc(sizeof(cx<float>) * f);
+    B.alloc(sizeof(cx<float>) * f);
+    c.lex.ensure(sizeof(cx<double>) * fl);
+    for (int ch = 0; ch < c.net.C; ++ch) {
+      cx<float>* dst = A.as<cx<float>>() + (long)ch * fl;
+      if (noise_precision == DDAMG_FP64) {
+        c.upload_fine((const char*)noise + sizeof(cx<double>) * (size_t)fl * ch, on_device, c.f64a.as<cx<double>>());
+        launch_copy_cvt<double, float>(c.f64a.as<cx<double>>(), dst, fl, c.st);
+      } else {
+        // complex64 lexicographic -> FP64 lexicographic staging -> block layout FP32
+        const cx<float>* src = (const cx<float>*)noise + (long)ch * fl;
+        if (!on_device) {
+          HIP_CHECK(hipMemcpyAsync(c.f64b.p, src, sizeof(cx<float>) * fl, hipMemcpyHostToDevice, c.st));
+          src = c.f64b.as<cx<float>>();
+        }
+        launch_copy_cvt<float, double>(src, c.lex.as<cx<double>>(), fl, c.st);
+        launch_from_lex<float>(c.g, c.lex.as<cx<double>>(), dst, 12, c.st);
+      }
+    }
+    cx<float>* out = net_infer(c, A.as<cx<float>>(), B.as<cx<float>>());
+    c.have_setup = false;
+    c.mg.reset();
+    c.p = *p;
+    c.mg = make_mg(c);
+    c.mg->load_fine_init(out);
+    A.release();
+    B.release();
+    const void* vecs[3] = {nullptr, coarse_init, nullptr};
+    c.mg->build(vecs, on_device, true);
+    c.have_setup = true;
+    return DDAMG_OK;
+  });
+}
+
+
 
 int ddamg_net_create(ddamg_ctx* ctx, int nlayers, int nchan) {
   if (!ctx) return DDAMG_INVALID_ARG;

@@ -245,4 +245,280 @@ template void launch_copy_cvt<float, double>(const cx<float>*, cx<double>*, long
 template void launch_copy_cvt<double, double>(const cx<double>*, cx<double>*, long, hipStream_t);
 template void launch_copy_cvt<float, float>(const cx<float>*, cx<float>*, long, hipStream_t);
 
+
+
+// ---------------------------------------------------------------------------
+// Column-batched forms: K independent Krylov processes advance in lock step.
+// Column r = blockIdx.y; every vector argument carries a column stride (cs*),
+// every scalar array a per-column stride; columns with act[r] == 0 are skipped.
+namespace {
+__device__ __forceinline__ bool col_off(const int* act) { return act && !act[blockIdx.y]; }
+}  // namespace
+
+template <class R>
+__global__ void __launch_bounds__(256) k_multidot_b(const cx<R>* __restrict__ V, long ldv, long csV, int k,
+                                                    const cx<R>* __restrict__ w, long csw, long N,
+                                                    cx<double>* __restrict__ partial, long pcs, const int* act) {
+  if (col_off(act)) return;
+  const long r = blockIdx.y;
+  V += r * csV;
+  w += r * csw;
+  partial += r * pcs;
+  __shared__ double red[KCHUNK][4][2];
+  int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  long stride = (long)gridDim.x * blockDim.x;
+  for (int i0 = 0; i0 < k; i0 += KCHUNK) {
+    double acc[KCHUNK][2];
+#pragma unroll
+    for (int ii = 0; ii < KCHUNK; ++ii) acc[ii][0] = acc[ii][1] = 0.0;
+    for (long e = (long)blockIdx.x * blockDim.x + t; e < N; e += stride) {
+      cx<R> wv_ = w[e];
+#pragma unroll
+      for (int ii = 0; ii < KCHUNK; ++ii) {
+        if (i0 + ii < k) {
+          cx<R> v = V[(long)(i0 + ii) * ldv + e];
+          acc[ii][0] += (double)v.re * wv_.re + (double)v.im * wv_.im;
+          acc[ii][1] += (double)v.re * wv_.im - (double)v.im * wv_.re;
+        }
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < KCHUNK; ++ii)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        double v = wave_sum_n(acc[ii][p], 64);
+        if (lane == 0) red[ii][wv][p] = v;
+      }
+    __syncthreads();
+    if (t < KCHUNK && i0 + t < k) {
+      double re = red[t][0][0] + red[t][1][0] + red[t][2][0] + red[t][3][0];
+      double im = red[t][0][1] + red[t][1][1] + red[t][2][1] + red[t][3][1];
+      partial[(long)(i0 + t) * gridDim.x + blockIdx.x] = mk(re, im);
+    }
+    __syncthreads();
+  }
+}
+template <class R>
+void launch_multidot_b(const cx<R>* V, long ldv, long csV, int k, const cx<R>* w, long csw, long N, cx<double>* partial,
+                       long pcs, int nwg, int K, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_multidot_b<R>, dim3(nwg, K), dim3(256), 0, st, V, ldv, csV, k, w, csw, N, partial, pcs, act);
+}
+
+__global__ void __launch_bounds__(256) k_reduce_b(const cx<double>* __restrict__ partial, long pcs, int nwg,
+                                                  cx<double>* __restrict__ out, long ocs, int mode, const int* act) {
+  if (col_off(act)) return;
+  partial += blockIdx.y * pcs;
+  out += blockIdx.y * ocs;
+  __shared__ double red[4][2];
+  int i = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double re = 0, im = 0;
+  for (int e = t; e < nwg; e += 256) {
+    cx<double> v = partial[(long)i * nwg + e];
+    re += v.re;
+    im += v.im;
+  }
+  re = wave_sum_n(re, 64);
+  im = wave_sum_n(im, 64);
+  if (lane == 0) {
+    red[wv][0] = re;
+    red[wv][1] = im;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double r = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    double m = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+    if (mode == 0) out[i] = mk(r, m);
+    else if (mode == 1) out[i] = out[i] + mk(r, m);
+    else out[i] = mk(sqrt(r > 0 ? r : 0.0), 0.0);
+  }
+}
+void launch_reduce_b(const cx<double>* partial, long pcs, int k, int nwg, cx<double>* out, long ocs, int mode, int K,
+                     const int* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_b, dim3(k, K), dim3(256), 0, st, partial, pcs, nwg, out, ocs, mode, act);
+}
+
+// w_r += sign * sum_{i<k_r} coef_r[i] V_r[i]   (k_r = kcol ? kcol[r] : k)
+template <class R>
+__global__ void __launch_bounds__(256) k_multi_axpy_b(const cx<R>* __restrict__ V, long ldv, long csV, int k,
+                                                      const int* kcol, const cx<double>* __restrict__ coef, long ccs,
+                                                      double sign, cx<R>* __restrict__ w, long csw, long N,
+                                                      const int* act) {
+  if (col_off(act)) return;
+  const long r = blockIdx.y;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const int kk = kcol ? kcol[r] : k;
+  V += r * csV;
+  coef += r * ccs;
+  w += r * csw;
+  cx<double> acc = mk(0.0, 0.0);
+  for (int i = 0; i < kk; ++i) {
+    cx<R> v = V[(long)i * ldv + e];
+    cmac(acc, coef[i], mk<double>(v.re, v.im));
+  }
+  cx<R> x = w[e];
+  w[e] = mk<R>((R)(x.re + sign * acc.re), (R)(x.im + sign * acc.im));
+}
+template <class R>
+void launch_multi_axpy_b(const cx<R>* V, long ldv, long csV, int k, const int* kcol, const cx<double>* coef, long ccs,
+                         double sign, cx<R>* w, long csw, long N, int K, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_axpy_b<R>, dim3((N + 255) / 256, K), dim3(256), 0, st, V, ldv, csV, k, kcol, coef, ccs,
+                     sign, w, csw, N, act);
+}
+
+// out_r = in_r / s_r (real part);  an inactive column is zeroed when zero_off
+template <class R>
+__global__ void k_scale_by_inv_b(const cx<R>* __restrict__ in, long csi, const cx<double>* __restrict__ s, long scs,
+                                 cx<R>* __restrict__ out, long cso, long N, const int* act, int zero_off) {
+  const long r = blockIdx.y;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  if (act && !act[r]) {
+    if (zero_off) out[r * cso + e] = mk<R>(0, 0);
+    return;
+  }
+  double d = s[r * scs].re;
+  double f = d > 0 ? 1.0 / d : 0.0;
+  cx<R> v = in[r * csi + e];
+  out[r * cso + e] = mk<R>((R)(f * v.re), (R)(f * v.im));
+}
+template <class R>
+void launch_scale_by_inv_b(const cx<R>* in, long csi, const cx<double>* s, long scs, cx<R>* out, long cso, long N,
+                           int K, const int* act, int zero_off, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_by_inv_b<R>, dim3((N + 255) / 256, K), dim3(256), 0, st, in, csi, s, scs, out, cso, N, act,
+                     zero_off);
+}
+
+template <class RA, class RB>
+__global__ void k_copy_cvt_b(const cx<RA>* __restrict__ in, long csi, cx<RB>* __restrict__ out, long cso, long N) {
+  const long r = blockIdx.y;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  cx<RA> v = in[r * csi + e];
+  out[r * cso + e] = mk<RB>((RB)v.re, (RB)v.im);
+}
+template <class RA, class RB>
+void launch_copy_cvt_b(const cx<RA>* in, long csi, cx<RB>* out, long cso, long N, int K, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_cvt_b<RA, RB>), dim3((N + 255) / 256, K), dim3(256), 0, st, in, csi, out, cso, N);
+}
+
+// out_r = a_r - b_r
+template <class R>
+__global__ void k_sub_b(long N, const cx<R>* __restrict__ a, long csa, const cx<R>* __restrict__ b, long csb,
+                        cx<R>* __restrict__ out, long cso) {
+  const long r = blockIdx.y;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  out[r * cso + e] = a[r * csa + e] - b[r * csb + e];
+}
+template <class R>
+void launch_sub_b(long N, const cx<R>* a, long csa, const cx<R>* b, long csb, cx<R>* out, long cso, int K,
+                  hipStream_t st) {
+  if (N > 0) hipLaunchKernelGGL(k_sub_b<R>, dim3((N + 255) / 256, K), dim3(256), 0, st, N, a, csa, b, csb, out, cso);
+}
+
+template <class R>
+__global__ void k_zero_b(long N, cx<R>* __restrict__ x, long cs) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < N) x[blockIdx.y * cs + e] = mk<R>(0, 0);
+}
+template <class R>
+void launch_zero_b(long N, cx<R>* x, long cs, int K, hipStream_t st) {
+  if (N > 0) hipLaunchKernelGGL(k_zero_b<R>, dim3((N + 255) / 256, K), dim3(256), 0, st, N, x, cs);
+}
+
+// Givens step j of every active column: thread r handles column r.  Scalar
+// arrays per column: H (ldh*m, column-major, leading dimension ldh), cs, sn (m),
+// g (ldh), resid (1).
+__global__ void k_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>* sn, cx<double>* g, int j,
+                           double* resid, int K, const int* act) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= K || (act && !act[r])) return;
+  cx<double>* h = H + (long)r * ldh * m + (long)j * ldh;
+  double* c_ = cs + (long)r * m;
+  cx<double>* s_ = sn + (long)r * m;
+  cx<double>* g_ = g + (long)r * ldh;
+  for (int i = 0; i < j; ++i) {
+    cx<double> a = h[i], b = h[i + 1];
+    h[i] = c_[i] * a + s_[i] * b;
+    h[i + 1] = c_[i] * b - conj(s_[i]) * a;
+  }
+  cx<double> a = h[j], b = h[j + 1];
+  double den = sqrt(norm2(a) + norm2(b));
+  double c;
+  cx<double> s;
+  if (den == 0.0) {
+    c = 1.0;
+    s = mk(0.0, 0.0);
+  } else if (norm2(a) == 0.0) {
+    c = 0.0;
+    s = mk(1.0, 0.0);
+  } else {
+    double aa = sqrt(norm2(a));
+    c = aa / den;
+    s = (1.0 / (aa * den)) * (a * conj(b));
+  }
+  c_[j] = c;
+  s_[j] = s;
+  h[j] = c * a + s * b;
+  h[j + 1] = mk(0.0, 0.0);
+  cx<double> gj = g_[j];
+  g_[j + 1] = -(conj(s) * gj);
+  g_[j] = c * gj;
+  resid[r] = sqrt(norm2(g_[j + 1]));
+}
+void launch_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>* sn, cx<double>* g, int j, double* resid,
+                     int K, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_givens_b, dim3(1), dim3(64), 0, st, H, ldh, m, cs, sn, g, j, resid, K, act);
+}
+
+// back substitution of column r's jd[r] x jd[r] system; y_r[i] = 0 for i >= jd[r]
+__global__ void k_trisolve_b(const cx<double>* H, int ldh, int m, const cx<double>* g, cx<double>* y,
+                             const int* jd, int K) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= K) return;
+  const cx<double>* Hr = H + (long)r * ldh * m;
+  const cx<double>* gr = g + (long)r * ldh;
+  cx<double>* yr = y + (long)r * ldh;
+  const int j = jd[r];
+  for (int i = m; i >= j; --i) yr[i] = mk(0.0, 0.0);
+  for (int i = j - 1; i >= 0; --i) {
+    cx<double> s = gr[i];
+    for (int k = i + 1; k < j; ++k) s = s - Hr[(long)k * ldh + i] * yr[k];
+    cx<double> d = Hr[(long)i * ldh + i];
+    double dn = norm2(d);
+    yr[i] = dn > 0 ? (1.0 / dn) * (s * conj(d)) : mk(0.0, 0.0);
+  }
+}
+void launch_trisolve_b(const cx<double>* H, int ldh, int m, const cx<double>* g, cx<double>* y, const int* jd, int K,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_trisolve_b, dim3(1), dim3(64), 0, st, H, ldh, m, g, y, jd, K);
+}
+
+// g_r = 0 except g_r[0] = s_r  (start of a cycle)
+__global__ void k_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int K, const int* act) {
+  const int r = blockIdx.x;
+  if (r >= K || (act && !act[r])) return;
+  for (int i = threadIdx.x; i < ldh; i += blockDim.x) g[(long)r * ldh + i] = i == 0 ? s[r * scs] : mk(0.0, 0.0);
+}
+void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int K, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_g_b, dim3(K), dim3(64), 0, st, g, ldh, s, scs, K, act);
+}
+
+#define INST_BB(R)                                                                                                  \
+  template void launch_multidot_b<R>(const cx<R>*, long, long, int, const cx<R>*, long, long, cx<double>*, long,   \
+                                     int, int, const int*, hipStream_t);                                            \
+  template void launch_multi_axpy_b<R>(const cx<R>*, long, long, int, const int*, const cx<double>*, long, double,  \
+                                       cx<R>*, long, long, int, const int*, hipStream_t);                           \
+  template void launch_scale_by_inv_b<R>(const cx<R>*, long, const cx<double>*, long, cx<R>*, long, long, int,      \
+                                         const int*, int, hipStream_t);                                             \
+  template void launch_sub_b<R>(long, const cx<R>*, long, const cx<R>*, long, cx<R>*, long, int, hipStream_t);     \
+  template void launch_zero_b<R>(long, cx<R>*, long, int, hipStream_t);
+INST_BB(double)
+INST_BB(float)
+template void launch_copy_cvt_b<double, float>(const cx<double>*, long, cx<float>*, long, long, int, hipStream_t);
+template void launch_copy_cvt_b<float, double>(const cx<float>*, long, cx<double>*, long, long, int, hipStream_t);
+template void launch_copy_cvt_b<double, double>(const cx<double>*, long, cx<double>*, long, long, int, hipStream_t);
+template void launch_copy_cvt_b<float, float>(const cx<float>*, long, cx<float>*, long, long, int, hipStream_t);
+
 }  // namespace ddamg

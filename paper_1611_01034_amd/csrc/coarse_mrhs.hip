@@ -1,0 +1,341 @@
+// Coarse operator on several right-hand sides at once, on the matrix cores.
+//
+// For K right-hand sides (K <= 16) stored one after the other (stride ldv
+// complex), every coarse site needs
+//   Y_r(c) = S(c) X_r(c) + sum_mu F_mu(c) X_r(c+mu)
+//          + sum_mu Gamma5 F_mu(c-mu)^dag Gamma5 X_r(c-mu) + i tw Gamma5 X_r(c)
+// (Sec. 1: D_c = P^dag D_W P, Gamma5,c-hermiticity, twist i mu Gamma5,c).
+// Each of the 9 blocks times the K inputs is one real matrix product on the
+// matrix cores: with A the n x n complex block and X the n x K inputs,
+//   rows    i       : output component i,
+//   columns (r, c)  : c = 0 real part, c = 1 imaginary part of right-hand side r,
+//   inner   (l, c') : real / imaginary part of input component l,
+//   A_real[i][(l,0)] = Re A_il,  A_real[i][(l,1)] = Im A_il,
+//   B[(l,0)][(r,0)] = Re x_lr,  B[(l,1)][(r,0)] = -Im x_lr,
+//   B[(l,0)][(r,1)] = Im x_lr,  B[(l,1)][(r,1)] =  Re x_lr,
+// so that (A_real B)[i][(r,0)] = Re (A x_r)_i and [i][(r,1)] = Im (A x_r)_i.
+// The interleaved (re, im) storage of the blocks is A_real row by row, so the
+// stored 16-bit entries feed the matrix cores unconverted.  Inputs are rounded
+// to the storage format for the product; accumulation is FP32; the twist is
+// added in FP32 from the unrounded input.
+//
+// v_mfma_f32_16x16x32_{f16,bf16} (wave64) fragments: lane L holds A[L%16][8(L/16) + e]
+// and B[8(L/16) + e][L%16] for e < 8; the result D[4(L/16) + e][L%16] for e < 4.
+//
+// One wavefront per coarse site; n = 2 N_v must be a multiple of 16 (n <= 64).
+#include "kernels.hpp"
+
+namespace ddamg {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+
+template <class S> struct mm16;
+template <> struct mm16<f16> {
+  using frag = v8h;
+  using e16 = f16;
+  static __device__ __forceinline__ v4f mma(frag a, frag b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct mm16<bf16> {
+  using frag = v8b;
+  using e16 = bf16;
+  static __device__ __forceinline__ v4f mma(frag a, frag b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// B fragment of input x (n components, right-hand side stride ldv) for the
+// lane's column j = 16u + L%16 and complex inputs lc..lc+3; sgn scales x.
+template <class S>
+__device__ __forceinline__ typename mm16<S>::frag b_frag(const cx<float>* x, long ldv, int K, int j, int lc, float sgn) {
+  using E = typename mm16<S>::e16;
+  typename mm16<S>::frag f;
+  const int r = j >> 1, c = j & 1;
+  if (r < K) {
+    const float4* p = reinterpret_cast<const float4*>(x + (long)r * ldv + lc);
+    float4 a = p[0], b = p[1];
+    float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float re = sgn * v[2 * q], im = sgn * v[2 * q + 1];
+      f[2 * q] = (E)(c == 0 ? re : im);
+      f[2 * q + 1] = (E)(c == 0 ? -im : re);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = (E)0.0f;
+  }
+  return f;
+}
+
+// A fragment of a block stored column-major (entry (i,l) at l*n + i): row i,
+// complex columns lc..lc+3
+template <class S>
+__device__ __forceinline__ typename mm16<S>::frag a_frag_col(const typename store_traits<S>::elem* blk, int n, int i,
+                                                            int lc) {
+  typename mm16<S>::frag f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    auto e = blk[(long)(lc + q) * n + i];
+    f[2 * q] = e.re;
+    f[2 * q + 1] = e.im;
+  }
+  return f;
+}
+
+// A fragment of g_i conj(F[l][i]) (F column-major: (l,i) at i*n + l), i.e. the
+// backward block Gamma5 F^dag Gamma5 without the g_l factor (applied to x)
+template <class S>
+__device__ __forceinline__ typename mm16<S>::frag a_frag_bwd(const typename store_traits<S>::elem* blk, int n, int i,
+                                                            int lc, bool neg_row) {
+  using E = typename mm16<S>::e16;
+  typename mm16<S>::frag f;
+  const typename store_traits<S>::elem* p = blk + (long)i * n + lc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    auto e = p[q];
+    E re = e.re, im = e.im;
+    f[2 * q] = neg_row ? (E)(-(float)re) : re;
+    f[2 * q + 1] = neg_row ? im : (E)(-(float)im);
+  }
+  return f;
+}
+
+// acc[t][u] += sum over the selected blocks, rows 16t.., columns 16u..
+//   self: S(site) xs(site);  hops: hs * (forward + backward hops of xh)
+template <class S, int NT>
+__device__ __forceinline__ void stencil_mfma(const CGeom& cg, const typename store_traits<S>::elem* D, int site,
+                                             const cx<float>* xs, const cx<float>* xh, float hs, int K, long ldv,
+                                             int lane, v4f acc[4][NT]) {
+  const int n = cg.n, RT = n >> 4, h = n >> 1;
+  const long nn = (long)n * n;
+  const int row = lane & 15, grp = lane >> 4;
+#pragma unroll 1
+  for (int b = xs ? 0 : 1; b < (xh ? 9 : 1); ++b) {
+    const typename store_traits<S>::elem* blk;
+    const cx<float>* x;
+    float sgn = 1.0f;
+    bool bwd = b >= 5;
+    if (b == 0) {
+      blk = D + (long)site * 5 * nn;
+      x = xs + (long)site * n;
+    } else if (!bwd) {
+      int mu = b - 1;
+      blk = D + ((long)site * 5 + 1 + mu) * nn;
+      x = xh + (long)cg.nbr[site * 8 + mu] * n;
+      sgn = hs;
+    } else {
+      int mu = b - 5;
+      int cb = cg.nbr[site * 8 + 4 + mu];
+      blk = D + ((long)cb * 5 + 1 + mu) * nn;
+      x = xh + (long)cb * n;
+      sgn = hs;
+    }
+#pragma unroll 1
+    for (int s = 0; s < RT; ++s) {
+      const int lc = 16 * s + 4 * grp;
+      // g_l of the backward block goes on the input (lc..lc+3 lie in one half)
+      const float gs = bwd ? (lc < h ? -sgn : sgn) : sgn;
+      typename mm16<S>::frag bf[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) bf[u] = b_frag<S>(x, ldv, K, 16 * u + row, lc, gs);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < RT) {
+          const int i = 16 * t + row;
+          typename mm16<S>::frag af = bwd ? a_frag_bwd<S>(blk, n, i, lc, i < h) : a_frag_col<S>(blk, n, i, lc);
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[t][u] = mm16<S>::mma(af, bf[u], acc[t][u]);
+        }
+      }
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void zero_acc(v4f acc[4][NT]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[t][u] = v4f{0.f, 0.f, 0.f, 0.f};
+}
+
+// Write the result of the site: y = acc (+ i tw Gamma5 xt) or y = base - (...)
+// (xt: input of the twist term, or null).
+template <int NT>
+__device__ __forceinline__ void store_mfma(const CGeom& cg, int site, v4f acc[4][NT], float tw, const cx<float>* xt,
+                                           const cx<float>* base, float base_sign, int K, long ldv, int lane,
+                                           cx<float>* y) {
+  const int n = cg.n, RT = n >> 4, h = n >> 1;
+  const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int j = 16 * u + col, r = j >> 1, c = j & 1;
+    if (r >= K) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= RT) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * t + 4 * grp + e;
+        const long o = (long)r * ldv + (long)site * n + i;
+        float v = acc[t][u][e];
+        if (xt) {
+          cx<float> xv = xt[o];
+          float g = i < h ? -tw : tw;
+          v += c == 0 ? -g * xv.im : g * xv.re;
+        }
+        if (base) {
+          const float* bp = reinterpret_cast<const float*>(base + o);
+          v = bp[c] + base_sign * v;
+        }
+        reinterpret_cast<float*>(y + o)[c] = v;
+      }
+    }
+  }
+}
+
+// y_r = D x_r (b == null) or y_r = b_r - D x_r, all sites
+template <class S, int NT>
+__global__ void __launch_bounds__(256) k_coarse_apply_mrhs(CGeom cg, const typename store_traits<S>::elem* __restrict__ D,
+                                                           float tw, int K, long ldv, const cx<float>* __restrict__ x,
+                                                           const cx<float>* __restrict__ b, cx<float>* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int site = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (site >= cg.nsites) return;
+  v4f acc[4][NT];
+  zero_acc<NT>(acc);
+  stencil_mfma<S, NT>(cg, D, site, x, x, 1.0f, K, ldv, lane, acc);
+  store_mfma<NT>(cg, site, acc, tw, x, b, -1.0f, K, ldv, lane, y);
+}
+
+// even sites of the odd-even reduced system: mode 0: y = (S + i tw G5) v - H t;
+// mode 1: y = v - H t   (H: the hops, t lives on the odd sites)
+template <class S, int NT>
+__global__ void __launch_bounds__(256) k_coarse_schur_even_mrhs(CGeom cg,
+                                                                const typename store_traits<S>::elem* __restrict__ D,
+                                                                float tw, int K, long ldv,
+                                                                const cx<float>* __restrict__ v,
+                                                                const cx<float>* __restrict__ t,
+                                                                cx<float>* __restrict__ y, int mode) {
+  const int lane = threadIdx.x & 63;
+  const int site = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (site >= cg.neven) return;
+  v4f acc[4][NT];
+  zero_acc<NT>(acc);
+  stencil_mfma<S, NT>(cg, D, site, mode == 0 ? v : nullptr, t, -1.0f, K, ldv, lane, acc);
+  if (mode == 0) store_mfma<NT>(cg, site, acc, tw, v, nullptr, 1.0f, K, ldv, lane, y);
+  else store_mfma<NT>(cg, site, acc, 0.0f, nullptr, v, 1.0f, K, ldv, lane, y);
+}
+
+// odd sites: y = Minv (base - H x) (base may be null: y = Minv (-(-H x)) = Minv H x
+// with the sign convention of the single right-hand-side kernel: y = Minv H x)
+// Minv: [odd site][n][n] FP32 column-major.  The hop result goes through LDS
+// ([n][K] per wavefront) to the FP32 matrix-vector products with Minv.
+template <class S, int NT>
+__global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
+                                                                 const typename store_traits<S>::elem* __restrict__ D,
+                                                                 const cx<float>* __restrict__ Minv, int K, long ldv,
+                                                                 const cx<float>* __restrict__ x,
+                                                                 const cx<float>* __restrict__ base,
+                                                                 cx<float>* __restrict__ y) {
+  __shared__ cx<float> us[4][64 * 16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int io = blockIdx.x * 4 + wv;
+  const int site = cg.neven + io;
+  const bool valid = site < cg.nsites;
+  const int n = cg.n, RT = n >> 4;
+  if (valid) {
+    v4f acc[4][NT];
+    zero_acc<NT>(acc);
+    stencil_mfma<S, NT>(cg, D, site, nullptr, x, 1.0f, K, ldv, lane, acc);
+    // u = H x or base - H x, into LDS as us[i * 16 + r]
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int j = 16 * u + col, r = j >> 1, c = j & 1;
+      if (r >= K) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= RT) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = 16 * t + 4 * grp + e;
+          float v = acc[t][u][e];
+          if (base) v = reinterpret_cast<const float*>(base + (long)r * ldv + (long)site * n + i)[c] - v;
+          reinterpret_cast<float*>(&us[wv][i * 16 + r])[c] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (valid && lane < n) {
+    const cx<float>* M = Minv + (long)io * n * n;
+    cx<float> out[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[r] = mk<float>(0, 0);
+    for (int l = 0; l < n; ++l) {
+      cx<float> m = M[(long)l * n + lane];
+      const cx<float>* ul = &us[wv][l * 16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < K) cmac(out[r], m, ul[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      if (r < K) y[(long)r * ldv + (long)site * n + lane] = out[r];
+  }
+}
+
+static inline int nt_of(int K) { return K <= 8 ? 1 : 2; }
+
+template <class S>
+void launch_coarse_apply_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* x,
+                              const cx<float>* b, cx<float>* y, hipStream_t st) {
+  dim3 grid((cg.nsites + 3) / 4);
+  auto Dp = (const typename store_traits<S>::elem*)D;
+  if (nt_of(K) == 1)
+    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 1>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
+  else
+    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 2>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
+}
+
+template <class S>
+void launch_coarse_schur_even_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* v,
+                                   const cx<float>* t, cx<float>* y, int mode, hipStream_t st) {
+  dim3 grid((cg.neven + 3) / 4);
+  auto Dp = (const typename store_traits<S>::elem*)D;
+  if (nt_of(K) == 1)
+    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 1>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, v, t, y,
+                       mode);
+  else
+    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 2>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, v, t, y,
+                       mode);
+}
+
+template <class S>
+void launch_coarse_hop_inv_odd_mrhs(const CGeom& cg, const void* D, const cx<float>* Minv, int K, long ldv,
+                                    const cx<float>* x, const cx<float>* base, cx<float>* y, hipStream_t st) {
+  int nodd = cg.nsites - cg.neven;
+  dim3 grid((nodd + 3) / 4);
+  auto Dp = (const typename store_traits<S>::elem*)D;
+  if (nt_of(K) == 1)
+    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 1>), grid, dim3(256), 0, st, cg, Dp, Minv, K, ldv, x, base, y);
+  else
+    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 2>), grid, dim3(256), 0, st, cg, Dp, Minv, K, ldv, x, base, y);
+}
+
+#define INST_MRHS(S)                                                                                              \
+  template void launch_coarse_apply_mrhs<S>(const CGeom&, const void*, double, int, long, const cx<float>*,      \
+                                            const cx<float>*, cx<float>*, hipStream_t);                          \
+  template void launch_coarse_schur_even_mrhs<S>(const CGeom&, const void*, double, int, long, const cx<float>*, \
+                                                 const cx<float>*, cx<float>*, int, hipStream_t);                \
+  template void launch_coarse_hop_inv_odd_mrhs<S>(const CGeom&, const void*, const cx<float>*, int, long,        \
+                                                  const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
+INST_MRHS(f16)
+INST_MRHS(bf16)
+
+}  // namespace ddamg

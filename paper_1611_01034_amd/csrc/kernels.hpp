@@ -107,6 +107,7 @@ void launch_net_mix(const Geom& g, int C, const cx<float>* U, const cx<float>* i
                     bool adj, hipStream_t st);
 void launch_net_gate(const Geom& g, int C, const cx<float>* z, const float* a, const float* b, cx<float>* y, float* sv,
                      hipStream_t st);
+void launch_net_gate_inplace(const Geom& g, int C, const float* a, const float* b, cx<float>* z, hipStream_t st);
 void launch_net_gate_bwd(const Geom& g, int C, const cx<float>* Gy, const cx<float>* z, const float* sv,
                          const float* a, cx<float>* Gz, double* partial, float* Ga, float* Gb, hipStream_t st);
 void launch_net_wgrad(const Geom& g, int C, const cx<float>* U, const cx<float>* x, const cx<float>* Gz,
@@ -139,5 +140,44 @@ void launch_givens(cx<double>* H, int ldh, double* cs, cx<double>* sn, cx<double
                    hipStream_t st);
 void launch_trisolve(const cx<double>* H, int ldh, const cx<double>* g, cx<double>* y, int j, hipStream_t st);
 void launch_set_scalar(cx<double>* dst, const cx<double>* src_norm2_sqrt, hipStream_t st);
+
+// column-batched Krylov kernels (K columns, column r = blockIdx.y; act: per-column
+// mask or null; cs*: column strides of vectors and scalar arrays)
+template <class R>
+void launch_multidot_b(const cx<R>* V, long ldv, long csV, int k, const cx<R>* w, long csw, long N, cx<double>* partial,
+                       long pcs, int nwg, int K, const int* act, hipStream_t st);
+void launch_reduce_b(const cx<double>* partial, long pcs, int k, int nwg, cx<double>* out, long ocs, int mode, int K,
+                     const int* act, hipStream_t st);
+template <class R>
+void launch_multi_axpy_b(const cx<R>* V, long ldv, long csV, int k, const int* kcol, const cx<double>* coef, long ccs,
+                         double sign, cx<R>* w, long csw, long N, int K, const int* act, hipStream_t st);
+template <class R>
+void launch_scale_by_inv_b(const cx<R>* in, long csi, const cx<double>* s, long scs, cx<R>* out, long cso, long N,
+                           int K, const int* act, int zero_off, hipStream_t st);
+template <class RA, class RB>
+void launch_copy_cvt_b(const cx<RA>* in, long csi, cx<RB>* out, long cso, long N, int K, hipStream_t st);
+template <class R>
+void launch_sub_b(long N, const cx<R>* a, long csa, const cx<R>* b, long csb, cx<R>* out, long cso, int K,
+                  hipStream_t st);
+template <class R>
+void launch_zero_b(long N, cx<R>* x, long cs, int K, hipStream_t st);
+void launch_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>* sn, cx<double>* g, int j, double* resid,
+                     int K, const int* act, hipStream_t st);
+void launch_trisolve_b(const cx<double>* H, int ldh, int m, const cx<double>* g, cx<double>* y, const int* jd, int K,
+                       hipStream_t st);
+void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int K, const int* act, hipStream_t st);
+
+// coarse operator on K <= 16 right-hand sides at once (matrix cores; 16-bit
+// operator storage S; n = 2 N_v a multiple of 16).  Vectors FP32, right-hand
+// side r at offset r * ldv.
+template <class S>
+void launch_coarse_apply_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* x,
+                              const cx<float>* b, cx<float>* y, hipStream_t st);
+template <class S>
+void launch_coarse_schur_even_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* v,
+                                   const cx<float>* t, cx<float>* y, int mode, hipStream_t st);
+template <class S>
+void launch_coarse_hop_inv_odd_mrhs(const CGeom& cg, const void* D, const cx<float>* Minv, int K, long ldv,
+                                    const cx<float>* x, const cx<float>* base, cx<float>* y, hipStream_t st);
 
 }  // namespace ddamg

@@ -151,6 +151,28 @@ __global__ void k_net_gate(Geom g, int C, const cx<float>* __restrict__ z, const
   sv[(long)c * g.V + gid] = sg;
 }
 
+// the gate in place, inference only (no record of the sigmoid for a backward pass)
+__global__ void k_net_gate_inplace(Geom g, const float* a, const float* b, cx<float>* z) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = blockIdx.y;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  const long base = (long)c * g.V * 12 + fidx(g, B, s, 12);
+  cx<float> v[12];
+  float n = 0.f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    v[k] = z[base + (long)k * TILE];
+    n += norm2(v[k]);
+  }
+  float sg = 1.f / (1.f + expf(-(a[c] * n + b[c])));
+#pragma unroll
+  for (int k = 0; k < 12; ++k) z[base + (long)k * TILE] = sg * v[k];
+}
+void launch_net_gate_inplace(const Geom& g, int C, const float* a, const float* b, cx<float>* z, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_gate_inplace, dim3((unsigned)((g.V + 255) / 256), C), dim3(256), 0, st, g, a, b, z);
+}
+
 // gate backward: G_z = s G_y + 2 t a s(1-s) z, t = Re <z, G_y>; per-workgroup
 // partial sums of t s(1-s) |z|^2 (-> G_a) and t s(1-s) (-> G_b), FP64
 __global__ void __launch_bounds__(256) k_net_gate_bwd(Geom g, int C, const cx<float>* __restrict__ Gy,

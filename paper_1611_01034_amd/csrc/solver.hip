@@ -274,6 +274,184 @@ KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(co
   res.converged = beta <= tol * bnorm;
   return res;
 }
+// ---------------------------------------------------------------------------
+// K (F)GMRES processes in lock step: one launch per step serves every column
+// (the batched operator reads its matrix once for all columns).  Each column
+// keeps its own Hessenberg matrix, rotations and stopping test; a column that
+// meets its tolerance drops out of the reductions and its next basis vector is
+// zeroed, so nested solves see a zero right-hand side for it.  The iterates are
+// those of K separate solves in exact arithmetic.
+template <class R>
+void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex) {
+  m = m_;
+  K = K_;
+  ld = ld_;
+  flexible = flex;
+  V.ensure(sizeof(cx<R>) * (size_t)(m + 1) * K * ld);
+  if (flex) Z.ensure(sizeof(cx<R>) * (size_t)m * K * ld);
+  r.ensure(sizeof(cx<R>) * (size_t)K * ld);
+  H.ensure(sizeof(cx<double>) * (size_t)(m + 1) * m * K);
+  cs.ensure(sizeof(double) * m * K);
+  sn.ensure(sizeof(cx<double>) * m * K);
+  g.ensure(sizeof(cx<double>) * (m + 1) * K);
+  y.ensure(sizeof(cx<double>) * (m + 1) * K);
+  nwg = (int)std::min<long>(256, std::max<long>(1, (N + 255) / 256));
+  part.ensure(sizeof(cx<double>) * (size_t)nwg * (m + 1) * K);
+  scal.ensure(sizeof(cx<double>) * 4 * K);
+  resid.ensure(sizeof(double) * K);
+  act.ensure(sizeof(int) * K);
+  jd.ensure(sizeof(int) * K);
+  if (!h_resid) {
+    HIP_CHECK(hipHostMalloc((void**)&h_resid, sizeof(double) * 64, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void**)&h_scal, sizeof(cx<double>) * 4 * 64, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void**)&h_act, sizeof(int) * 64, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void**)&h_jd, sizeof(int) * 64, hipHostMallocDefault));
+  }
+}
+template <class R>
+KrylovWSm<R>::~KrylovWSm() {
+  if (h_resid) (void)hipHostFree(h_resid);
+  if (h_scal) (void)hipHostFree(h_scal);
+  if (h_act) (void)hipHostFree(h_act);
+  if (h_jd) (void)hipHostFree(h_jd);
+}
+template struct KrylovWSm<double>;
+template struct KrylovWSm<float>;
+
+template <class R>
+KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>& A, const OpM<R>* M, const cx<R>* b,
+                           cx<R>* x, double tol, int max_iter, bool fixed, bool x_is_zero) {
+  if (K < 1 || K > ws.K || K > 64) throw Error(INVALID_ARG, "lock-step solve: bad column count");
+  hipStream_t st = c.st;
+  const int m = ws.m, ldh = m + 1;
+  const long ld = ws.ld, hcs = (long)ldh * m;
+  const int nwg = (int)std::min<long>(ws.nwg, std::max<long>(1, (N + 255) / 256));
+  const long pcs = (long)nwg * ldh;
+  cx<R>* V = ws.V.template as<cx<R>>();
+  cx<R>* Z = M ? ws.Z.template as<cx<R>>() : V;
+  cx<R>* r = ws.r.template as<cx<R>>();
+  cx<double>* H = ws.H.template as<cx<double>>();
+  cx<double>* scal = ws.scal.template as<cx<double>>();
+  cx<double>* part = ws.part.template as<cx<double>>();
+  cx<double>* g = ws.g.template as<cx<double>>();
+  cx<double>* y = ws.y.template as<cx<double>>();
+  int* act = ws.act.template as<int>();
+  int* jd = ws.jd.template as<int>();
+  // ||v_r|| of every column into scal[r*4 + slot]
+  auto norms = [&](const cx<R>* v, int slot, const int* a) {
+    launch_multidot_b<R>(v, 0, ld, 1, v, ld, N, part, pcs, nwg, K, a, st);
+    launch_reduce_b(part, pcs, 1, nwg, scal + slot, 4, 2, K, a, st);
+  };
+  auto read_scal = [&]() {
+    HIP_CHECK(hipMemcpyAsync(ws.h_scal, scal, sizeof(cx<double>) * 4 * K, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  };
+  auto push_act = [&]() {
+    HIP_CHECK(hipMemcpyAsync(act, ws.h_act, sizeof(int) * K, hipMemcpyHostToDevice, st));
+  };
+  KrylovResultM res;
+  res.iters.assign(K, 0);
+  res.resid.assign(K, 0.0);
+  res.converged.assign(K, 0);
+  norms(b, 0, nullptr);
+  if (x_is_zero) {
+    launch_zero_b<R>(N, x, ld, K, st);
+    launch_copy_cvt_b<R, R>(b, ld, r, ld, N, K, st);
+  } else {
+    A(x, r, K);
+    launch_sub_b<R>(N, b, ld, r, ld, r, ld, K, st);
+  }
+  norms(r, 1, nullptr);
+  read_scal();
+  std::vector<double> bn(K), beta(K);
+  for (int k = 0; k < K; ++k) {
+    bn[k] = ws.h_scal[4 * k].re;
+    beta[k] = ws.h_scal[4 * k + 1].re;
+  }
+  auto update_active = [&]() {
+    int n_act = 0;
+    for (int k = 0; k < K; ++k) {
+      bool done = bn[k] == 0.0 || (!fixed && beta[k] <= tol * bn[k]) || beta[k] == 0.0;
+      ws.h_act[k] = done ? 0 : 1;
+      n_act += ws.h_act[k];
+    }
+    return n_act;
+  };
+  int steps = 0;
+  while (update_active() > 0 && steps < max_iter) {
+    push_act();
+    const int mm = fixed ? std::min(m, max_iter - steps) : m;
+    // V_0 = r / beta (inactive columns zeroed), g = beta e_0
+    launch_scale_by_inv_b<R>(r, ld, scal + 1, 4, V, ld, N, K, act, 1, st);
+    launch_init_g_b(g, ldh, scal + 1, 4, K, act, st);
+    for (int k = 0; k < K; ++k) ws.h_jd[k] = 0;
+    for (int j = 0; j < mm; ++j) {
+      cx<R>* Vj = V + (long)j * K * ld;
+      cx<R>* Vn = V + (long)(j + 1) * K * ld;
+      cx<R>* z = Vj;
+      if (M) {
+        z = Z + (long)j * K * ld;
+        (*M)(Vj, z, K);
+      }
+      A(z, Vn, K);
+      cx<double>* hcol = H + (long)j * ldh;
+      launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
+      launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 0, K, act, st);
+      launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, hcol, hcs, -1.0, Vn, ld, N, K, act, st);
+      launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
+      launch_reduce_b(part, pcs, j + 1, nwg, y, ldh, 0, K, act, st);
+      launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 1, K, act, st);
+      launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, y, ldh, -1.0, Vn, ld, N, K, act, st);
+      launch_multidot_b<R>(Vn, 0, ld, 1, Vn, ld, N, part, pcs, nwg, K, act, st);
+      launch_reduce_b(part, pcs, 1, nwg, hcol + j + 1, hcs, 2, K, act, st);
+      launch_scale_by_inv_b<R>(Vn, ld, hcol + j + 1, hcs, Vn, ld, N, K, act, 1, st);
+      launch_givens_b(H, ldh, m, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), g, j,
+                      ws.resid.template as<double>(), K, act, st);
+      ++steps;
+      int still = 0;
+      for (int k = 0; k < K; ++k)
+        if (ws.h_act[k]) {
+          ws.h_jd[k] = j + 1;
+          ++res.iters[k];
+        }
+      if (!fixed) {
+        HIP_CHECK(hipMemcpyAsync(ws.h_resid, ws.resid.p, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        bool changed = false;
+        for (int k = 0; k < K; ++k)
+          if (ws.h_act[k] && ws.h_resid[k] <= tol * bn[k]) {
+            ws.h_act[k] = 0;
+            changed = true;
+          }
+        for (int k = 0; k < K; ++k) still += ws.h_act[k];
+        if (changed) push_act();
+        if (still == 0) break;
+      }
+      if (steps >= max_iter) break;
+    }
+    HIP_CHECK(hipMemcpyAsync(jd, ws.h_jd, sizeof(int) * K, hipMemcpyHostToDevice, st));
+    launch_trisolve_b(H, ldh, m, g, y, jd, K, st);
+    launch_multi_axpy_b<R>(Z, (long)K * ld, ld, m, jd, y, ldh, 1.0, x, ld, N, K, nullptr, st);
+    A(x, r, K);
+    launch_sub_b<R>(N, b, ld, r, ld, r, ld, K, st);
+    norms(r, 1, nullptr);
+    read_scal();
+    for (int k = 0; k < K; ++k) beta[k] = ws.h_scal[4 * k + 1].re;
+    if (fixed && steps >= max_iter) break;
+  }
+  res.steps = steps;
+  for (int k = 0; k < K; ++k) {
+    res.resid[k] = bn[k] > 0 ? beta[k] / bn[k] : 0.0;
+    res.converged[k] = bn[k] == 0.0 || beta[k] <= tol * bn[k];
+  }
+  return res;
+}
+template KrylovResultM fgmres_multi<double>(Ctx&, KrylovWSm<double>&, int, long, const OpM<double>&,
+                                            const OpM<double>*, const cx<double>*, cx<double>*, double, int, bool,
+                                            bool);
+template KrylovResultM fgmres_multi<float>(Ctx&, KrylovWSm<float>&, int, long, const OpM<float>&, const OpM<float>*,
+                                           const cx<float>*, cx<float>*, double, int, bool, bool);
+
 template KrylovResult fgmres<double>(Ctx&, KrylovWS<double>&, long,
                                      const std::function<void(const cx<double>*, cx<double>*)>&,
                                      const std::function<void(const cx<double>*, cx<double>*)>*, const cx<double>*,
@@ -463,6 +641,11 @@ struct MG : MGBase {
   DevBuf rc[4], ec[4], wk[4][4];  // coarse vectors per level
   KrylovWS<R> kws[4];
   std::function<void(const cx<R>*, cx<R>*)> Aop[4], Mop[4];
+  // lock-step (K-column) forms: buffers sized for Km columns
+  int Km = 0;
+  DevBuf rcm[4], ecm[4], wkm[4][2], fxm;
+  KrylovWSm<R> kwsm[4];
+  OpM<R> AopM[4], MopM[4];
 
   MG(Ctx& c_, const ddamg_params& p_) : c(c_), p(p_), L(p_.levels) {
     const Geom& g = c.g;
@@ -681,6 +864,151 @@ struct MG : MGBase {
     }
   }
 
+  // ---- lock-step forms on K columns (column k of a level-l K-vector at k * len(l))
+  static constexpr bool kMfma = std::is_same<S, f16>::value || std::is_same<S, bf16>::value;
+  bool mfma_level(int l) const { return kMfma && geos[l]->n % 16 == 0 && geos[l]->n <= 64; }
+
+  void ensure_multi(int K) {
+    if (K <= Km) return;
+    for (int l = 1; l < L; ++l) {
+      CoarseGeo& G = *geos[l];
+      long len = (long)G.nsites * G.n;
+      rcm[l].ensure(sizeof(cx<R>) * len * K);
+      ecm[l].ensure(sizeof(cx<R>) * len * K);
+      for (int k = 0; k < 2; ++k) wkm[l][k].ensure(sizeof(cx<R>) * len * K);
+      if (l < L - 1) kwsm[l].init(p.inter_restart, K, len, len, true);
+      else kwsm[l].init(p.coarse_restart, K, len, (long)G.neven * G.n, false);
+      CGeom cg = G.cg();
+      if (l == L - 1) {
+        cx<R>* t = wkm[l][0].template as<cx<R>>();
+        AopM[l] = [this, cg, l, t, len](const cx<R>* in, cx<R>* out, int K_) {
+          TimeScope ts(c.timer, 5);
+          if constexpr (kMfma) {
+            if (mfma_level(l)) {
+              launch_coarse_hop_inv_odd_mrhs<S>(cg, Dst(l), Minvc.template as<cx<R>>(), K_, len, in, nullptr, t,
+                                                c.st);
+              launch_coarse_schur_even_mrhs<S>(cg, Dst(l), tw[l], K_, len, in, t, out, 0, c.st);
+              return;
+            }
+          }
+          for (int k = 0; k < K_; ++k) {
+            launch_coarse_hop_inv_odd<R, S>(cg, Dst(l), Minvc.template as<cx<R>>(), in + k * len, t + k * len, 0,
+                                            c.st);
+            launch_coarse_schur_even<R, S>(cg, Dst(l), tw[l], in + k * len, t + k * len, out + k * len, 0, c.st);
+          }
+        };
+      } else {
+        AopM[l] = [this, cg, l, len](const cx<R>* in, cx<R>* out, int K_) {
+          TimeScope ts(c.timer, 2);
+          if constexpr (kMfma) {
+            if (mfma_level(l)) {
+              launch_coarse_apply_mrhs<S>(cg, Dst(l), tw[l], K_, len, in, nullptr, out, c.st);
+              return;
+            }
+          }
+          for (int k = 0; k < K_; ++k) launch_coarse_apply<R, S>(cg, Dst(l), tw[l], in + k * len, out + k * len, c.st);
+        };
+        MopM[l] = [this, l](const cx<R>* in, cx<R>* out, int K_) { vcycle_m(l, in, out, K_); };
+      }
+    }
+    Km = K;
+  }
+
+  void coarse_solve_m(int l, const cx<R>* b, cx<R>* x, int K) {
+    CoarseGeo& G = *geos[l];
+    CGeom cg = G.cg();
+    const long len = (long)G.nsites * G.n;
+    KrylovResultM kr;
+    if (l == L - 1) {
+      cx<R>* t = wkm[l][0].template as<cx<R>>();
+      cx<R>* rhs = wkm[l][1].template as<cx<R>>();
+      for (int k = 0; k < K; ++k)
+        hipLaunchKernelGGL(k_minv_odd<R>, dim3((G.nsites - G.neven + 3) / 4), dim3(256), 0, c.st, cg,
+                           Minvc.template as<cx<R>>(), b + k * len, t + k * len);
+      bool done = false;
+      if constexpr (kMfma) {
+        if (mfma_level(l)) {
+          launch_coarse_schur_even_mrhs<S>(cg, Dst(l), tw[l], K, len, b, t, rhs, 1, c.st);
+          done = true;
+        }
+      }
+      if (!done)
+        for (int k = 0; k < K; ++k)
+          launch_coarse_schur_even<R, S>(cg, Dst(l), tw[l], b + k * len, t + k * len, rhs + k * len, 1, c.st);
+      kr = fgmres_multi<R>(c, kwsm[l], K, (long)G.neven * G.n, AopM[l], nullptr, rhs, x, p.coarse_tol,
+                           p.coarse_max_iter, p.fixed_iters != 0, true);
+      done = false;
+      if constexpr (kMfma) {
+        if (mfma_level(l)) {
+          launch_coarse_hop_inv_odd_mrhs<S>(cg, Dst(l), Minvc.template as<cx<R>>(), K, len, x, b, x, c.st);
+          done = true;
+        }
+      }
+      if (!done)
+        for (int k = 0; k < K; ++k)
+          launch_coarse_hop_inv_odd_base<R, S>(cg, Dst(l), Minvc.template as<cx<R>>(), x + k * len, b + k * len,
+                                               x + k * len, c.st);
+    } else {
+      kr = fgmres_multi<R>(c, kwsm[l], K, len, AopM[l], &MopM[l], b, x, p.inter_tol, p.inter_max_iter,
+                           p.fixed_iters != 0, true);
+    }
+    for (int k = 0; k < K; ++k) coarse_iters[l] += kr.iters[k];
+  }
+
+  // x = cycle(v) on level l for K columns, x0 = 0
+  void vcycle_m(int l, const cx<R>* v, cx<R>* x, int K) {
+    const long len = level_len(l), lenc = level_len(l + 1);
+    cx<R>* rc_ = rcm[l + 1].template as<cx<R>>();
+    cx<R>* ec_ = ecm[l + 1].template as<cx<R>>();
+    if (l == 0) {
+      vcycles += K;
+      for (int k = 0; k < K; ++k) {
+        const cx<R>* rin = v + k * len;
+        if (p.sap_pre > 0) {
+          launch_zero<R>(len, x + k * len, c.st);
+          fine_sap(v + k * len, x + k * len, p.sap_pre, p.mr_steps);
+          fine_dirac(x + k * len, fr.template as<cx<R>>());
+          launch_sub<R>(len, v + k * len, fr.template as<cx<R>>(), fr.template as<cx<R>>(), c.st);
+          rin = fr.template as<cx<R>>();
+        }
+        restrict_(0, rin, rc_ + k * lenc);
+      }
+      coarse_solve_m(1, rc_, ec_, K);
+      for (int k = 0; k < K; ++k) {
+        prolong_(0, ec_ + k * lenc, x + k * len, p.sap_pre > 0);
+        fine_sap(v + k * len, x + k * len, p.sap_post, p.mr_steps);
+      }
+    } else {
+      for (int k = 0; k < K; ++k) restrict_(l, v + k * len, rc_ + k * lenc);
+      coarse_solve_m(l + 1, rc_, ec_, K);
+      for (int k = 0; k < K; ++k) {
+        prolong_(l, ec_ + k * lenc, x + k * len, 0);
+        coarse_sap(l, v + k * len, x + k * len, p.coarse_sap_post);
+      }
+    }
+  }
+
+  void load_fine_init(const cx<float>* v) override {
+    const long len = c.fine_len();
+    for (int i = 0; i < Nv[0]; ++i)
+      launch_copy_cvt<float, R>(v + (long)i * len, Vraw[0].template as<cx<R>>() + (long)i * len, len, c.st);
+    c.sync();
+    fine_loaded = true;
+  }
+  DevBuf fbm;
+  void precond_multi(const cx<double>* v, cx<double>* z, int K) override {
+    ensure_multi(K);
+    const long n = c.fine_len();
+    if constexpr (std::is_same<R, double>::value) {
+      vcycle_m(0, v, z, K);
+    } else {
+      fbm.ensure(sizeof(cx<R>) * n * K);
+      fxm.ensure(sizeof(cx<R>) * n * K);
+      launch_copy_cvt_b<double, R>(v, n, fbm.template as<cx<R>>(), n, n, K, c.st);
+      vcycle_m(0, fbm.template as<cx<R>>(), fxm.template as<cx<R>>(), K);
+      launch_copy_cvt_b<R, double>(fxm.template as<cx<R>>(), n, z, n, n, K, c.st);
+    }
+  }
   void precond(const cx<double>* v, cx<double>* z) override {
     if constexpr (std::is_same<R, double>::value) {
       vcycle(0, v, z);
@@ -799,6 +1127,30 @@ struct MG : MGBase {
 
   void iterate(int l) {
     long len = level_len(l);
+    if (p.batch > 1) {
+      // chunks of up to p.batch test vectors through one lock-step V-cycle
+      const int K = std::min(p.batch, Nv[l]);
+      ensure_multi(K);
+      cx<R>* out;
+      if (l == 0) {
+        fxm.ensure(sizeof(cx<R>) * len * K);
+        out = fxm.template as<cx<R>>();
+      } else {
+        out = ecm[l].template as<cx<R>>();
+      }
+      for (int i0 = 0; i0 < Nv[l]; i0 += K) {
+        const int k = std::min(K, Nv[l] - i0);
+        cx<R>* v0 = Vraw[l].template as<cx<R>>() + (long)i0 * len;
+        // level >= 1: the cycle's input must not alias its work vectors; Vraw does not
+        vcycle_m(l, v0, out, k);
+        for (int q = 0; q < k; ++q) {
+          launch_copy_cvt<R, R>(out + (long)q * len, v0 + (long)q * len, len, c.st);
+          normalise(v0 + (long)q * len, len);
+        }
+      }
+      build_next(l);
+      return;
+    }
     for (int i = 0; i < Nv[l]; ++i) {
       cx<R>* vi = Vraw[l].template as<cx<R>>() + (long)i * len;
       launch_copy_cvt<R, R>(vi, setup_in(l), len, c.st);
@@ -832,9 +1184,13 @@ struct MG : MGBase {
     for (int l = 0; l < L - 1; ++l) {
       long len = level_len(l);
       for (int i = 0; i < Nv[l]; ++i) {
-        const char* src = (const char*)vecs[l] + sizeof(cx<double>) * (size_t)len * i;
         cx<R>* vi = Vraw[l].template as<cx<R>>() + (long)i * len;
-        upload_vec(l, src, on_device, vi);
+        if (l == 0 && fine_loaded) {
+          // already in place (load_fine_init)
+        } else {
+          const char* src = (const char*)vecs[l] + sizeof(cx<double>) * (size_t)len * i;
+          upload_vec(l, src, on_device, vi);
+        }
         if (run_setup && p.init_sap_iters > 0) {
           launch_zero<R>(len, setup_zero(l), c.st);
           smooth_level(l, setup_zero(l), vi, p.init_sap_iters);
@@ -842,15 +1198,20 @@ struct MG : MGBase {
       }
       build_next(l);
     }
-    if (!run_setup) return;
-    for (int it = 0; it < p.setup_iters; ++it) {
-      iterate(0);
-      if (L == 3) {
-        assemble_next(1);
-        for (int t = 0; t < p.coarse_setup_iters; ++t) iterate(1);
+    if (run_setup) {
+      for (int it = 0; it < p.setup_iters; ++it) {
+        iterate(0);
+        if (L == 3) {
+          assemble_next(1);
+          for (int t = 0; t < p.coarse_setup_iters; ++t) iterate(1);
+        }
       }
     }
     c.sync();
+    // the raw test vectors and the setup's fine K-column buffer are not needed
+    // by the solver: give the memory back (the largest items of the setup)
+    for (int l = 0; l < L - 1; ++l) Vraw[l].release();
+    fxm.release();
   }
 
   // ---- parity helpers (host FP64 in/out) --------------------------------------
@@ -928,6 +1289,64 @@ struct MG : MGBase {
     coarse_sap(l, bb, xx, iters);
     launch_copy_cvt<R, double>(xx, a.as<cx<double>>(), len, c.st);
     download_level(l, a.as<cx<double>>(), x);
+  }
+  void apply_coarse_m(int l, const cx<R>* in, cx<R>* out, int K) {
+    CoarseGeo& G = *geos[l];
+    const long len = level_len(l);
+    if constexpr (kMfma) {
+      if (mfma_level(l)) {
+        launch_coarse_apply_mrhs<S>(G.cg(), Dst(l), tw[l], K, len, in, nullptr, out, c.st);
+        return;
+      }
+    }
+    for (int k = 0; k < K; ++k) launch_coarse_apply<R, S>(G.cg(), Dst(l), tw[l], in + k * len, out + k * len, c.st);
+  }
+  void apply_coarse_multi_host(int l, int K, const cx<double>* in, cx<double>* out) override {
+    ensure_multi(K);
+    const long len = level_len(l);
+    DevBuf a;
+    a.alloc(sizeof(cx<double>) * len);
+    cx<R>* x = rcm[l].template as<cx<R>>();
+    cx<R>* y = ecm[l].template as<cx<R>>();
+    for (int k = 0; k < K; ++k) {
+      upload_level(l, in + k * len, 0, a.as<cx<double>>());
+      launch_copy_cvt<double, R>(a.as<cx<double>>(), x + k * len, len, c.st);
+    }
+    apply_coarse_m(l, x, y, K);
+    for (int k = 0; k < K; ++k) {
+      launch_copy_cvt<R, double>(y + k * len, a.as<cx<double>>(), len, c.st);
+      download_level(l, a.as<cx<double>>(), out + k * len);
+    }
+  }
+  void coarse_solve_multi_host(int l, int K, const cx<double>* b, cx<double>* x) override {
+    ensure_multi(K);
+    const long len = level_len(l);
+    DevBuf a;
+    a.alloc(sizeof(cx<double>) * len);
+    cx<R>* bb = rcm[l].template as<cx<R>>();
+    cx<R>* xx = ecm[l].template as<cx<R>>();
+    for (int k = 0; k < K; ++k) {
+      upload_level(l, b + k * len, 0, a.as<cx<double>>());
+      launch_copy_cvt<double, R>(a.as<cx<double>>(), bb + k * len, len, c.st);
+    }
+    coarse_solve_m(l, bb, xx, K);
+    for (int k = 0; k < K; ++k) {
+      launch_copy_cvt<R, double>(xx + k * len, a.as<cx<double>>(), len, c.st);
+      download_level(l, a.as<cx<double>>(), x + k * len);
+    }
+  }
+  void bench_coarse_multi(int l, int K, int napply, int which) override {
+    ensure_multi(K);
+    const long len = level_len(l);
+    cx<R>* x = rcm[l].template as<cx<R>>();
+    cx<R>* y = ecm[l].template as<cx<R>>();
+    // any finite input serves for timing: fill with a constant
+    launch_zero<R>(len * K, y, c.st);
+    launch_axpby<R>(len * K, 0.0, y, 0.0, x, c.st);
+    for (int i = 0; i < napply; ++i) {
+      if (which == 1 && l == L - 1) AopM[l](x, y, K);
+      else apply_coarse_m(l, x, y, K);
+    }
   }
   void coarse_solve_host(int l, const cx<double>* b, cx<double>* x) override {
     long len = level_len(l);

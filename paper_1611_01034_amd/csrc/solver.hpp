@@ -80,6 +80,39 @@ struct KrylovWS {
   ~KrylovWS();
 };
 
+// Workspace of K Krylov processes in lock step.  Every K-column vector is K
+// vectors of stride ld (column r at offset r * ld); the basis is
+// [m+1][K][ld] (V) and [m][K][ld] (Z); scalars per column.
+template <class R>
+struct KrylovWSm {
+  int m = 0, K = 0;
+  long ld = 0;
+  bool flexible = false;
+  DevBuf V, Z, r, H, cs, sn, g, y, part, scal, resid, act, jd;
+  double* h_resid = nullptr;   // pinned: K residual estimates
+  cx<double>* h_scal = nullptr;  // pinned: K x 4 scalars
+  int* h_act = nullptr;        // pinned: K flags
+  int* h_jd = nullptr;         // pinned: K counts
+  int nwg = 0;
+  void init(int m_, int K_, long ld_, long N, bool flex);
+  ~KrylovWSm();
+};
+
+struct KrylovResultM {
+  std::vector<int> iters;      // per column
+  std::vector<double> resid;   // relative true residual at exit
+  std::vector<char> converged;
+  int steps = 0;               // lock-step iterations
+};
+
+// operator / preconditioner on K columns of stride ld
+template <class R>
+using OpM = std::function<void(const cx<R>*, cx<R>*, int)>;
+
+template <class R>
+KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>& A, const OpM<R>* M, const cx<R>* b,
+                           cx<R>* x, double tol, int max_iter, bool fixed, bool x_is_zero);
+
 using OpR64 = std::function<void(const cx<double>*, cx<double>*)>;
 using OpR32 = std::function<void(const cx<float>*, cx<float>*)>;
 
@@ -121,6 +154,8 @@ struct MGBase {
   virtual ~MGBase() = default;
   virtual void build(const void* const* vecs, int on_device, bool run_setup) = 0;
   virtual void precond(const cx<double>* v, cx<double>* z) = 0;  // fine block layout FP64
+  // the same on K fine FP64 fields (stride = fine length), in lock step
+  virtual void precond_multi(const cx<double>* v, cx<double>* z, int K) = 0;
   virtual void set_mu(double mu) = 0;
   virtual int nlev() const = 0;
   virtual const CoarseGeo& geo(int l) const = 0;  // l >= 1
@@ -131,8 +166,18 @@ struct MGBase {
   virtual void apply_coarse_host(int l, const cx<double>* in, cx<double>* out) = 0;
   virtual void coarse_sap_host(int l, const cx<double>* b, cx<double>* x, int iters) = 0;
   virtual void coarse_solve_host(int l, const cx<double>* b, cx<double>* x) = 0;
+  // K columns of a level-l field, host FP64 [K][len] in the level layout
+  virtual void apply_coarse_multi_host(int l, int K, const cx<double>* in, cx<double>* out) = 0;
+  virtual void coarse_solve_multi_host(int l, int K, const cx<double>* b, cx<double>* x) = 0;
+  // napply launches of the K-column coarse operator of level l on device-resident
+  // work vectors (which = 0: full stencil, 1: odd-even reduced operator, coarsest level)
+  virtual void bench_coarse_multi(int l, int K, int napply, int which) = 0;
   long coarse_iters[4] = {0, 0, 0, 0};
   long vcycles = 0;
+  // level-0 initial vectors from the device (block layout, FP32, stride = fine
+  // length), copied into the hierarchy; build() then skips vecs[0]
+  virtual void load_fine_init(const cx<float>* v) = 0;
+  bool fine_loaded = false;
 };
 
 // learned-setup network: parameters (real view, FP32), Adam moments, activations

@@ -56,6 +56,8 @@ class Params(ctypes.Structure):
         ("coarse_tol", ctypes.c_double),
         ("precision", ctypes.c_int),
         ("fixed_iters", ctypes.c_int),
+        ("batch", ctypes.c_int),
+        ("rhs_batch", ctypes.c_int),
     ]
 
 
@@ -100,6 +102,10 @@ _SIGS = {
     "ddamg_coarse_sap": (_i, [_vp, _i, _vp, _vp, _i]),
     "ddamg_coarse_solve": (_i, [_vp, _i, _vp, _vp]),
     "ddamg_vcycle": (_i, [_vp, _vp, _vp]),
+    "ddamg_setup_learned": (_i, [_vp, ctypes.POINTER(Params), _vp, _i, _i, _vp]),
+    "ddamg_apply_coarse_multi": (_i, [_vp, _i, _i, _vp, _vp]),
+    "ddamg_coarse_solve_multi": (_i, [_vp, _i, _i, _vp, _vp]),
+    "ddamg_bench_coarse": (_i, [_vp, _i, _i, _i, _i]),
     "ddamg_bench_dirac": (_i, [_vp, _i, _i]),
     "ddamg_timing": (_i, [_vp, _i]),
     "ddamg_timing_query": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
@@ -268,6 +274,30 @@ class DDAMG:
         self._check(_lib.ddamg_setup(self._h, ctypes.byref(params), ptrs, dev))
         self.params = params
 
+    def setup_learned(self, params: Params, noise, coarse_init=None):
+        """Adaptive setup from the network's output on `noise` (C fields,
+        complex64 or complex128, numpy or torch); the network must be set."""
+        if _is_torch(noise):
+            import torch
+            if noise.dtype not in (torch.complex64, torch.complex128):
+                raise TypeError("noise must be complex64 or complex128")
+            prec = FP32 if noise.dtype == torch.complex64 else FP64
+            noise = noise.contiguous()
+        else:
+            noise = np.asarray(noise)
+            prec = FP32 if noise.dtype == np.complex64 else FP64
+            noise = np.ascontiguousarray(noise, dtype=np.complex64 if prec == FP32 else np.complex128)
+        pn, dev = _ptr(noise)
+        pc = ctypes.c_void_p(None)
+        keep = None
+        if coarse_init is not None:
+            keep = _c128(coarse_init)
+            pc, dev_c = _ptr(keep)
+            if dev_c != dev:
+                raise ValueError("noise and coarse_init must both be on the host or both on the device")
+        self._check(_lib.ddamg_setup_learned(self._h, ctypes.byref(params), pn, prec, dev, pc))
+        self.params = params
+
     def set_test_vectors(self, params: Params, vectors):
         arrs, ptrs, dev = self._vec_ptrs(vectors)
         self._check(_lib.ddamg_set_test_vectors(self._h, ctypes.byref(params), ptrs, dev))
@@ -357,6 +387,22 @@ class DDAMG:
         x = np.empty_like(b)
         self._check(_lib.ddamg_coarse_solve(self._h, int(level), _ptr(b)[0], _ptr(x)[0]))
         return x
+
+    def apply_coarse_multi(self, level, ys):
+        """ys: [nrhs, ...] fields of level `level` (same layout as apply_coarse)."""
+        ys = _c128(ys)
+        out = np.empty_like(ys)
+        self._check(_lib.ddamg_apply_coarse_multi(self._h, int(level), int(ys.shape[0]), _ptr(ys)[0], _ptr(out)[0]))
+        return out
+
+    def coarse_solve_multi(self, level, bs):
+        bs = _c128(bs)
+        x = np.empty_like(bs)
+        self._check(_lib.ddamg_coarse_solve_multi(self._h, int(level), int(bs.shape[0]), _ptr(bs)[0], _ptr(x)[0]))
+        return x
+
+    def bench_coarse(self, level, nrhs, napply, which=0):
+        self._check(_lib.ddamg_bench_coarse(self._h, int(level), int(nrhs), int(napply), int(which)))
 
     def vcycle(self, v):
         v = _c128(v)

@@ -70,11 +70,14 @@ def mg_params(levels=2, nvec=(24,), block=(4, 4, 4, 4), setup_iters=1, precision
                                 precision=precision, coarse_mu_factor=delta)
 
 
-def make_targets(dims, block, seeds, eps_list, nvec=24, setup_iters=5):
+def make_targets(dims, block, seeds, eps_list, nvec=24, setup_iters=5, log=print):
     """Plain setups on seeded fields; returns [(U, Q)] with Q the block
     orthonormalised level-0 test vectors (host FP64, spinor layout)."""
     out = []
+    t0 = time.time()
     for i, s in enumerate(seeds):
+        if i % 8 == 0:
+            log(f"targets: field {i}/{len(seeds)} ({time.time() - t0:.1f} s)")
         eps = eps_list[i % len(eps_list)]
         U = synth.gauge_field(dims, eps, s)
         with _ctx(dims, block) as ctx:
@@ -119,6 +122,14 @@ def learned_vectors(ctx: ddamg.DDAMG, params, C, L, dims, seed):
     return ctx.net_forward(synth.spinor(dims, seed, nvec=C))
 
 
+def VARIANTS(Vl, Vr):
+    """(name, initial vectors, setup iterations) of the comparison: learned or
+    random start with 0 or 1 refinement iterations, and the plain 5-iteration
+    setup from the random start."""
+    return (("learned+0", Vl, 0), ("random+0", Vr, 0), ("learned+1", Vl, 1), ("random+1", Vr, 1),
+            ("plain5", Vr, 5))
+
+
 def evaluate(dims, block, seeds, eps, params, C=24, L=4, nvec=24, tol=1e-10, log=print):
     """For each held-out field: learned + 1 refinement, random + 1 refinement,
     plain 5-iteration setup.  Returns a list of per-field dicts."""
@@ -131,7 +142,7 @@ def evaluate(dims, block, seeds, eps, params, C=24, L=4, nvec=24, tol=1e-10, log
             ctx.set_gauge(U)
             Vr = synth.spinor(dims, s + 100000, nvec=nvec)
             Vl = learned_vectors(ctx, params, C, L, dims, s + 300000)
-            for name, vecs, it in (("learned+1", Vl, 1), ("random+1", Vr, 1), ("plain5", Vr, 5)):
+            for name, vecs, it in VARIANTS(Vl, Vr):
                 t0 = time.time()
                 ctx.setup(mg_params(nvec=(nvec,), block=block, setup_iters=it), [vecs])
                 ts = time.time() - t0
@@ -144,14 +155,15 @@ def evaluate(dims, block, seeds, eps, params, C=24, L=4, nvec=24, tol=1e-10, log
 
 
 def save_weights(path, params, C, L, meta=None):
-    """Parameter vector and shape in a plain .npz (no pickled objects)."""
-    np.savez(path, params=np.asarray(params, dtype=np.float64), C=np.int64(C), L=np.int64(L),
+    """Parameter vector (FP32, the precision the network computes in) and
+    shape in a plain .npz (no pickled objects)."""
+    np.savez(path, params=np.asarray(params, dtype=np.float32), C=np.int64(C), L=np.int64(L),
              meta=np.array(json.dumps(meta or {})))
 
 
 def load_weights(path):
     with np.load(path, allow_pickle=False) as z:
-        return z["params"].copy(), int(z["C"]), int(z["L"]), json.loads(str(z["meta"]))
+        return z["params"].astype(np.float64), int(z["C"]), int(z["L"]), json.loads(str(z["meta"]))
 
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "net_l4_c24.npz")
@@ -207,7 +219,7 @@ def main(argv=None):
         params, C, L, meta = load_weights(a.weights)
         rows = evaluate(_tuple(a.dims), _tuple(a.block), _seeds(a.seeds), a.eps, params, C=C, L=L, nvec=C)
         summary = {}
-        for k in ("learned+1", "random+1", "plain5"):
+        for k in [v[0] for v in VARIANTS(None, None)]:
             summary[k] = {m: float(np.mean([r[k][m] for r in rows])) for m in ("rho", "iters", "setup_s", "solve_s")}
         out = {"dims": _tuple(a.dims), "eps": a.eps, "seeds": a.seeds, "summary": summary, "rows": rows}
         print(json.dumps(summary), flush=True)

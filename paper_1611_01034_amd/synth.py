@@ -126,14 +126,17 @@ def mean_plaquette(U: np.ndarray) -> float:
 # for lattices whose host-side generation would take minutes (48^3 x 96 test
 # vectors are tens of GB).  Deterministic for a given (shape, seed, device).
 
-def gaussian_device(shape, seed: int, device="cuda"):
+def gaussian_device(shape, seed: int, device="cuda", dtype="complex128"):
+    """Complex Gaussian field (N(0,1) real and imaginary parts) drawn on the
+    device with a seeded torch generator; dtype complex128 or complex64."""
     import torch
 
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
     shape = tuple(int(s) for s in shape)
-    re = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
-    im = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+    rt = torch.float64 if dtype == "complex128" else torch.float32
+    re = torch.randn(shape, generator=gen, device=device, dtype=rt)
+    im = torch.randn(shape, generator=gen, device=device, dtype=rt)
     return torch.complex(re, im)
 
 
