@@ -88,6 +88,19 @@ def cpu_baseline(nrhs, V_target):
                       f"x{V_target // V} and by {nrhs} right-hand sides"}
 
 
+DIRAC_SOURCES = ["dirac.hip", "finedev.hpp", "common.hpp"]
+
+
+def dirac_sources_sha256():
+    """Hash of the sources the D(mu) kernel is built from (same recipe as
+    paper_1611_01034_amd.profsum.sources_sha256)."""
+    h = hashlib.sha256()
+    for f in DIRAC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_01034_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic_for(kernel_src_hash):
     p = os.path.join(ROOT, "profiles", "dirac_fp64_48x48x48x96_traffic.json")
     if not os.path.exists(p):
@@ -190,8 +203,7 @@ def main():
     avg_ms = ms_d / max(n_d, 1)
     bytes_launch = DIRAC_FP64_BYTES_PER_SITE * V
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if n_d else None
-    src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_1611_01034_amd", "csrc", "fine.hip"), "rb").read()
-                              ).hexdigest()
+    src_hash = dirac_sources_sha256()
     ctx.close()
     del ctx
     torch.cuda.empty_cache()

@@ -1,0 +1,47 @@
+// The fine operator D(+-mu) = D_W +- i Gamma5 mu (Sec. 1) on the whole
+// lattice: Wilson hops with spin projection, the clover site term and the
+// twist, in FP64 or FP32 arithmetic with FP64/FP32/FP16/BF16 link storage.
+#include "finedev.hpp"
+
+namespace ddamg {
+
+// ---------------------------------------------------------------------------
+// D(tw) psi, full lattice.  One workgroup per lattice block, one work-item per
+// site; the block's input spinors are staged in LDS, so only hops that leave
+// the block read neighbours from global memory.  Workgroups are remapped so
+// each XCD sweeps a contiguous range of blocks.
+template <class R, class S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3, 8)))
+k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H, R tw,
+        const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
+  extern __shared__ char smem_raw[];
+  cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x bs, parity-split
+  const int B = xcd_remap(blockIdx.x, gridDim.x), s = threadIdx.x;
+  SiteNbr me;
+  me_of(g, B, s, me);
+  cx<R> psi[12], acc[12];
+  load_spinor(in, g, B, s, psi);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) *lds_site(lds, g, s, c) = psi[c];
+  site_term(H, g, B, s, tw, psi, acc);
+  __syncthreads();
+  hop_staged<R, S>(U, in, lds, g, B, s, me, acc);
+  store_spinor(out, g, B, s, acc);
+}
+
+template <class R, class S>
+void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<R>* in, cx<R>* out, hipStream_t st) {
+  size_t sm = 12 * (size_t)g.bs * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_dirac<R, S>), dim3(g.nblocks), dim3(g.bs), sm, st, g,
+                     (const typename store_traits<S>::elem*)U, H, (R)tw, in, out);
+}
+template void launch_dirac<double, double>(const Geom&, const void*, const double*, double, const cx<double>*,
+                                           cx<double>*, hipStream_t);
+template void launch_dirac<float, float>(const Geom&, const void*, const float*, double, const cx<float>*,
+                                         cx<float>*, hipStream_t);
+template void launch_dirac<float, f16>(const Geom&, const void*, const float*, double, const cx<float>*,
+                                          cx<float>*, hipStream_t);
+template void launch_dirac<float, bf16>(const Geom&, const void*, const float*, double,
+                                                  const cx<float>*, cx<float>*, hipStream_t);
+
+}  // namespace ddamg

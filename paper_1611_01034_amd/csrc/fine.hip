@@ -20,44 +20,7 @@
 
 namespace ddamg {
 
-// ---------------------------------------------------------------------------
-// D(tw) psi, full lattice.  One workgroup per lattice block, one work-item per
-// site; the block's input spinors are staged in LDS, so only hops that leave
-// the block read neighbours from global memory.  Workgroups are remapped so
-// each XCD sweeps a contiguous range of blocks.
-template <class R, class S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3, 8)))
-k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H, R tw,
-        const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
-  extern __shared__ char smem_raw[];
-  cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x bs, parity-split
-  const int B = xcd_remap(blockIdx.x, gridDim.x), s = threadIdx.x;
-  SiteNbr me;
-  me_of(g, B, s, me);
-  cx<R> psi[12], acc[12];
-  load_spinor(in, g, B, s, psi);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) *lds_site(lds, g, s, c) = psi[c];
-  site_term(H, g, B, s, tw, psi, acc);
-  __syncthreads();
-  hop_staged<R, S>(U, in, lds, g, B, s, me, acc);
-  store_spinor(out, g, B, s, acc);
-}
 
-template <class R, class S>
-void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<R>* in, cx<R>* out, hipStream_t st) {
-  size_t sm = 12 * (size_t)g.bs * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_dirac<R, S>), dim3(g.nblocks), dim3(g.bs), sm, st, g,
-                     (const typename store_traits<S>::elem*)U, H, (R)tw, in, out);
-}
-template void launch_dirac<double, double>(const Geom&, const void*, const double*, double, const cx<double>*,
-                                           cx<double>*, hipStream_t);
-template void launch_dirac<float, float>(const Geom&, const void*, const float*, double, const cx<float>*,
-                                         cx<float>*, hipStream_t);
-template void launch_dirac<float, f16>(const Geom&, const void*, const float*, double, const cx<float>*,
-                                          cx<float>*, hipStream_t);
-template void launch_dirac<float, bf16>(const Geom&, const void*, const float*, double,
-                                                  const cx<float>*, cx<float>*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // workgroup reduction helpers (deterministic: fixed shuffle and wave order)
@@ -105,7 +68,8 @@ __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::el
 template <class R, class S>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 1 : 3, 8)))
 k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H,
-      const R* __restrict__ Minv, R tw, const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr) {
+      const R* __restrict__ Minv, R tw, const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr, int K,
+      long ld) {
   extern __shared__ char smem_raw[];
   cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x half, even slots
   cx<R>* od = ev + 12 * g.half;                     // 12 x half, odd slots
@@ -113,7 +77,14 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
   __shared__ double red[3][16];
   int B;
   {
-    int B0 = 2 * xcd_remap(blockIdx.x, gridDim.x);
+    // K right-hand sides interleaved: consecutive workgroups (same XCD) take
+    // the same lattice block for different fields, so its links, clover and
+    // odd-site inverses are shared through L2
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int pair = w / K, rr = w - pair * K;
+    b += (long)rr * ld;
+    x += (long)rr * ld;
+    int B0 = 2 * pair;
     int bc[4];
     block_coords(g, B0, bc);
     int par = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
@@ -226,10 +197,23 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
 template <class R, class S>
 void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
                 cx<R>* x, int n_mr, hipStream_t st) {
-  size_t sm = 3 * 12 * (size_t)g.half * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_sap<R, S>), dim3(g.nblocks / 2), dim3(g.bs), sm, st, g, colour,
-                     (const typename store_traits<S>::elem*)U, H, Minv, (R)tw, b, x, n_mr);
+  launch_sap_multi<R, S>(g, colour, U, H, Minv, tw, b, x, n_mr, 1, 0, st);
 }
+template <class R, class S>
+void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+                      cx<R>* x, int n_mr, int K, long ld, hipStream_t st) {
+  size_t sm = 3 * 12 * (size_t)g.half * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_sap<R, S>), dim3((g.nblocks / 2) * K), dim3(g.bs), sm, st, g, colour,
+                     (const typename store_traits<S>::elem*)U, H, Minv, (R)tw, b, x, n_mr, K, ld);
+}
+template void launch_sap_multi<double, double>(const Geom&, int, const void*, const double*, const double*, double,
+                                               const cx<double>*, cx<double>*, int, int, long, hipStream_t);
+template void launch_sap_multi<float, float>(const Geom&, int, const void*, const float*, const float*, double,
+                                             const cx<float>*, cx<float>*, int, int, long, hipStream_t);
+template void launch_sap_multi<float, f16>(const Geom&, int, const void*, const float*, const float*, double,
+                                           const cx<float>*, cx<float>*, int, int, long, hipStream_t);
+template void launch_sap_multi<float, bf16>(const Geom&, int, const void*, const float*, const float*, double,
+                                            const cx<float>*, cx<float>*, int, int, long, hipStream_t);
 template void launch_sap<double, double>(const Geom&, int, const void*, const double*, const double*, double,
                                          const cx<double>*, cx<double>*, int, hipStream_t);
 template void launch_sap<float, float>(const Geom&, int, const void*, const float*, const float*, double,

@@ -34,6 +34,9 @@ void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<
 template <class R, class S>
 void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
                 cx<R>* x, int n_mr, hipStream_t st);
+template <class R, class S>
+void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+                      cx<R>* x, int n_mr, int K, long ld, hipStream_t st);
 template <class R>
 void launch_from_lex(const Geom& g, const cx<double>* lex, cx<R>* out, int ncomp, hipStream_t st);
 template <class R>

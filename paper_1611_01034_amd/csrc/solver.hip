@@ -780,6 +780,14 @@ struct MG : MGBase {
         launch_sap<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, c.st);
       }
   }
+  // SAP on K fine fields (stride = fine length), one launch per colour
+  void fine_sap_m(const cx<R>* b, cx<R>* x, int K, int iters, int nmr) {
+    for (int it = 0; it < iters; ++it)
+      for (int col = 0; col < 2; ++col) {
+        TimeScope ts(c.timer, 1);
+        launch_sap_multi<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, K, c.fine_len(), c.st);
+      }
+  }
   void coarse_sap(int l, const cx<R>* b, cx<R>* x, int iters) {
     CoarseGeo& G = *geos[l];
     CGeom cg = G.cg();
@@ -962,11 +970,13 @@ struct MG : MGBase {
     cx<R>* ec_ = ecm[l + 1].template as<cx<R>>();
     if (l == 0) {
       vcycles += K;
+      if (p.sap_pre > 0) {
+        launch_zero<R>(len * K, x, c.st);
+        fine_sap_m(v, x, K, p.sap_pre, p.mr_steps);
+      }
       for (int k = 0; k < K; ++k) {
         const cx<R>* rin = v + k * len;
         if (p.sap_pre > 0) {
-          launch_zero<R>(len, x + k * len, c.st);
-          fine_sap(v + k * len, x + k * len, p.sap_pre, p.mr_steps);
           fine_dirac(x + k * len, fr.template as<cx<R>>());
           launch_sub<R>(len, v + k * len, fr.template as<cx<R>>(), fr.template as<cx<R>>(), c.st);
           rin = fr.template as<cx<R>>();
@@ -974,10 +984,8 @@ struct MG : MGBase {
         restrict_(0, rin, rc_ + k * lenc);
       }
       coarse_solve_m(1, rc_, ec_, K);
-      for (int k = 0; k < K; ++k) {
-        prolong_(0, ec_ + k * lenc, x + k * len, p.sap_pre > 0);
-        fine_sap(v + k * len, x + k * len, p.sap_post, p.mr_steps);
-      }
+      for (int k = 0; k < K; ++k) prolong_(0, ec_ + k * lenc, x + k * len, p.sap_pre > 0);
+      fine_sap_m(v, x, K, p.sap_post, p.mr_steps);
     } else {
       for (int k = 0; k < K; ++k) restrict_(l, v + k * len, rc_ + k * lenc);
       coarse_solve_m(l + 1, rc_, ec_, K);

@@ -5,7 +5,7 @@ per-dispatch counters), and the calibrated HBM traffic of one kernel.
     python -m paper_1611_01034_amd.profsum pmc DIR OUT --cmd "..."
     python -m paper_1611_01034_amd.profsum traffic --fetch F.json --write W.json
         --kernel REGEX --copy REGEX --copy-bytes N --site-bytes B --sites V
-        --source FILE --out OUT.json
+        --source FILE[,FILE...] --out OUT.json
 
 `stats` reads *kernel_stats.csv, `pmc` reads *counter_collection.csv found
 under DIR (recursively); each writes a text table and a JSON twin (OUT with
@@ -21,6 +21,16 @@ import os
 import re
 import sys
 from collections import defaultdict
+
+
+def sources_sha256(paths):
+    """SHA-256 over the concatenated contents of the given source files (the
+    kernel and the headers it is built from)."""
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def _find(d, suffix):
@@ -106,13 +116,13 @@ def traffic(a):
     fetch_b = f_k * sf
     write_b = w_k * sw
     alg = a.site_bytes * a.sites
-    src = hashlib.sha256(open(a.source, "rb").read()).hexdigest()
+    src = sources_sha256(a.source.split(","))
     res = {"kernel": a.kernel, "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
            "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes_each_way": a.copy_bytes,
            "scale_fetch": sf, "scale_write": sw, "fetch_bytes": fetch_b, "write_bytes": write_b,
            "bytes_per_launch": fetch_b + write_b, "algorithmic_bytes_per_launch": alg,
            "traffic_over_algorithmic": (fetch_b + write_b) / alg,
-           "source": os.path.relpath(a.source), "source_sha256": src,
+           "source": [os.path.relpath(x) for x in a.source.split(",")], "source_sha256": src,
            "commands": {"fetch": json.load(open(a.fetch))["command"], "write": json.load(open(a.write))["command"]}}
     with open(a.out, "w") as fh:
         json.dump(res, fh, indent=1)
