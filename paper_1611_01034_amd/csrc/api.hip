@@ -735,8 +735,18 @@ void net_forward(Ctx& c) {
 // `in` holds the input and is overwritten; returns the buffer with the output
 cx<float>* net_infer(Ctx& c, cx<float>* in, cx<float>* tmp) {
   NetState& n = c.net;
+  // matrix cores when the channel count and the lattice allow (FP32 products)
+  const bool mf = n.C % 8 == 0 && c.g.V % 64 == 0;
+  const long per = 9L * n.C * n.C * 16 * 2;
+  if (mf) {
+    n.packed.ensure(sizeof(float) * per * n.L);
+    for (int l = 0; l < n.L; ++l) launch_net_pack(n.C, n.W(l), n.packed.as<float>() + l * per, c.st);
+  }
   for (int l = 0; l < n.L; ++l) {
-    launch_net_mix(c.g, n.C, c.U32.as<cx<float>>(), in, n.W(l), tmp, false, c.st);
+    if (mf)
+      launch_net_mix_mfma(c.g, n.C, c.U32.as<cx<float>>(), in, n.packed.as<float>() + l * per, tmp, c.st);
+    else
+      launch_net_mix(c.g, n.C, c.U32.as<cx<float>>(), in, n.W(l), tmp, false, c.st);
     if (l < n.L - 1) launch_net_gate_inplace(c.g, n.C, n.ab(l), n.ab(l) + n.C, tmp, c.st);
     std::swap(in, tmp);
   }
@@ -917,10 +927,8 @@ int ddamg_net_forward(ddamg_ctx* ctx, const void* noise, void* out, int on_devic
     net_buffers(c);
     NetState& n = c.net;
     long fl = c.fine_len();
-    long f = (long)n.C * fl;
     net_upload(c, noise, on_device, n.act.as<cx<float>>());
-    net_forward(c);
-    const cx<float>* y = n.zb.as<cx<float>>() + (long)(n.L - 1) * f;
+    const cx<float>* y = net_infer(c, n.act.as<cx<float>>(), n.zb.as<cx<float>>());
     for (int ch = 0; ch < n.C; ++ch) {
       launch_copy_cvt<float, double>(y + (long)ch * fl, c.f64b.as<cx<double>>(), fl, c.st);
       char* dst = (char*)out + sizeof(cx<double>) * (size_t)fl * ch;

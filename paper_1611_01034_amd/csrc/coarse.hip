@@ -109,13 +109,16 @@ template <class R, class S>
 __global__ void __launch_bounds__(1024) k_coarse_sap(CGeom cg, const typename store_traits<S>::elem* __restrict__ D,
                                                      R tw, int bsz, const int* __restrict__ blk_sites,
                                                      const int* __restrict__ blk_nbr, const cx<R>* __restrict__ r,
-                                                     cx<R>* __restrict__ x, int n_mr) {
+                                                     cx<R>* __restrict__ x, int n_mr, int K, long ld) {
   extern __shared__ char smem_raw[];
   cx<R>* rho = reinterpret_cast<cx<R>*>(smem_raw);  // [bsz][64]
   __shared__ double red[3][16];
   const int n = cg.n;
   const long nn = (long)n * n;
-  int blk = blockIdx.x;
+  // K fields interleaved: consecutive workgroups take one block for different fields
+  const int blk = blockIdx.x / K, rr = blockIdx.x - blk * K;
+  r += (long)rr * ld;
+  x += (long)rr * ld;
   int j = threadIdx.x >> 6, k = threadIdx.x & 63;
   int site = blk_sites[blk * bsz + j];
   const int* lnb = blk_nbr + ((long)blk * bsz + j) * 8;
@@ -182,9 +185,14 @@ __global__ void __launch_bounds__(1024) k_coarse_sap(CGeom cg, const typename st
 template <class R, class S>
 void launch_coarse_sap(const CGeom& cg, const void* D, double tw, int nblk_colour, int bsz, const int* blk_sites,
                        const int* blk_nbr, const cx<R>* r, cx<R>* x, int n_mr, hipStream_t st) {
+  launch_coarse_sap_multi<R, S>(cg, D, tw, nblk_colour, bsz, blk_sites, blk_nbr, r, x, n_mr, 1, 0, st);
+}
+template <class R, class S>
+void launch_coarse_sap_multi(const CGeom& cg, const void* D, double tw, int nblk_colour, int bsz, const int* blk_sites,
+                             const int* blk_nbr, const cx<R>* r, cx<R>* x, int n_mr, int K, long ld, hipStream_t st) {
   size_t sm = (size_t)bsz * 64 * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_coarse_sap<R, S>), dim3(nblk_colour), dim3(64 * bsz), sm, st, cg,
-                     (const typename store_traits<S>::elem*)D, (R)tw, bsz, blk_sites, blk_nbr, r, x, n_mr);
+  hipLaunchKernelGGL((k_coarse_sap<R, S>), dim3(nblk_colour * K), dim3(64 * bsz), sm, st, cg,
+                     (const typename store_traits<S>::elem*)D, (R)tw, bsz, blk_sites, blk_nbr, r, x, n_mr, K, ld);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,6 +662,8 @@ void launch_coarse_schur_even(const CGeom& cg, const void* D, double tw, const c
                                              cx<R>*, hipStream_t);                                                \
   template void launch_coarse_sap<R, S>(const CGeom&, const void*, double, int, int, const int*, const int*,      \
                                         const cx<R>*, cx<R>*, int, hipStream_t);                                  \
+  template void launch_coarse_sap_multi<R, S>(const CGeom&, const void*, double, int, int, const int*,            \
+                                              const int*, const cx<R>*, cx<R>*, int, int, long, hipStream_t);     \
   template void launch_coarse_hop_inv_odd<R, S>(const CGeom&, const void*, const cx<R>*, const cx<R>*, cx<R>*,    \
                                                 int, hipStream_t);                                                \
   template void launch_coarse_hop_inv_odd_base<R, S>(const CGeom&, const void*, const cx<R>*, const cx<R>*,       \

@@ -22,7 +22,10 @@
 // v_mfma_f32_16x16x32_{f16,bf16} (wave64) fragments: lane L holds A[L%16][8(L/16) + e]
 // and B[8(L/16) + e][L%16] for e < 8; the result D[4(L/16) + e][L%16] for e < 4.
 //
-// One wavefront per coarse site; n = 2 N_v must be a multiple of 16 (n <= 64).
+// One workgroup per coarse site with n/16 wavefronts, wavefront t computing
+// output rows 16t..16t+15 (n = 2 N_v a multiple of 16, n <= 64): short
+// dependency chains and n/16 times the wavefronts of a one-per-site mapping,
+// which is what keeps these small, latency-bound grids busy.
 #include "kernels.hpp"
 
 namespace ddamg {
@@ -104,12 +107,12 @@ __device__ __forceinline__ typename mm16<S>::frag a_frag_bwd(const typename stor
   return f;
 }
 
-// acc[t][u] += sum over the selected blocks, rows 16t.., columns 16u..
+// acc[u] += sum over the selected blocks, output rows 16t..16t+15, columns 16u..
 //   self: S(site) xs(site);  hops: hs * (forward + backward hops of xh)
 template <class S, int NT>
 __device__ __forceinline__ void stencil_mfma(const CGeom& cg, const typename store_traits<S>::elem* D, int site,
-                                             const cx<float>* xs, const cx<float>* xh, float hs, int K, long ldv,
-                                             int lane, v4f acc[4][NT]) {
+                                             int t, const cx<float>* xs, const cx<float>* xh, float hs, int K,
+                                             long ldv, int lane, v4f acc[NT]) {
   const int n = cg.n, RT = n >> 4, h = n >> 1;
   const long nn = (long)n * n;
   const int row = lane & 15, grp = lane >> 4;
@@ -142,58 +145,47 @@ __device__ __forceinline__ void stencil_mfma(const CGeom& cg, const typename sto
       typename mm16<S>::frag bf[NT];
 #pragma unroll
       for (int u = 0; u < NT; ++u) bf[u] = b_frag<S>(x, ldv, K, 16 * u + row, lc, gs);
+      const int i = 16 * t + row;
+      typename mm16<S>::frag af = bwd ? a_frag_bwd<S>(blk, n, i, lc, i < h) : a_frag_col<S>(blk, n, i, lc);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < RT) {
-          const int i = 16 * t + row;
-          typename mm16<S>::frag af = bwd ? a_frag_bwd<S>(blk, n, i, lc, i < h) : a_frag_col<S>(blk, n, i, lc);
-#pragma unroll
-          for (int u = 0; u < NT; ++u) acc[t][u] = mm16<S>::mma(af, bf[u], acc[t][u]);
-        }
-      }
+      for (int u = 0; u < NT; ++u) acc[u] = mm16<S>::mma(af, bf[u], acc[u]);
     }
   }
 }
 
 template <int NT>
-__device__ __forceinline__ void zero_acc(v4f acc[4][NT]) {
+__device__ __forceinline__ void zero_acc(v4f acc[NT]) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int u = 0; u < NT; ++u) acc[t][u] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < NT; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
 }
 
 // Write the result of the site: y = acc (+ i tw Gamma5 xt) or y = base - (...)
 // (xt: input of the twist term, or null).
 template <int NT>
-__device__ __forceinline__ void store_mfma(const CGeom& cg, int site, v4f acc[4][NT], float tw, const cx<float>* xt,
-                                           const cx<float>* base, float base_sign, int K, long ldv, int lane,
-                                           cx<float>* y) {
-  const int n = cg.n, RT = n >> 4, h = n >> 1;
+__device__ __forceinline__ void store_mfma(const CGeom& cg, int site, int t, v4f acc[NT], float tw,
+                                           const cx<float>* xt, const cx<float>* base, float base_sign, int K,
+                                           long ldv, int lane, cx<float>* y) {
+  const int n = cg.n, h = n >> 1;
   const int col = lane & 15, grp = lane >> 4;
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     const int j = 16 * u + col, r = j >> 1, c = j & 1;
     if (r >= K) continue;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t >= RT) continue;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = 16 * t + 4 * grp + e;
-        const long o = (long)r * ldv + (long)site * n + i;
-        float v = acc[t][u][e];
-        if (xt) {
-          cx<float> xv = xt[o];
-          float g = i < h ? -tw : tw;
-          v += c == 0 ? -g * xv.im : g * xv.re;
-        }
-        if (base) {
-          const float* bp = reinterpret_cast<const float*>(base + o);
-          v = bp[c] + base_sign * v;
-        }
-        reinterpret_cast<float*>(y + o)[c] = v;
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * t + 4 * grp + e;
+      const long o = (long)r * ldv + (long)site * n + i;
+      float v = acc[u][e];
+      if (xt) {
+        cx<float> xv = xt[o];
+        float g = i < h ? -tw : tw;
+        v += c == 0 ? -g * xv.im : g * xv.re;
       }
+      if (base) {
+        const float* bp = reinterpret_cast<const float*>(base + o);
+        v = bp[c] + base_sign * v;
+      }
+      reinterpret_cast<float*>(y + o)[c] = v;
     }
   }
 }
@@ -203,13 +195,12 @@ template <class S, int NT>
 __global__ void __launch_bounds__(256) k_coarse_apply_mrhs(CGeom cg, const typename store_traits<S>::elem* __restrict__ D,
                                                            float tw, int K, long ldv, const cx<float>* __restrict__ x,
                                                            const cx<float>* __restrict__ b, cx<float>* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int site = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (site >= cg.nsites) return;
-  v4f acc[4][NT];
+  const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+  const int site = blockIdx.x;
+  v4f acc[NT];
   zero_acc<NT>(acc);
-  stencil_mfma<S, NT>(cg, D, site, x, x, 1.0f, K, ldv, lane, acc);
-  store_mfma<NT>(cg, site, acc, tw, x, b, -1.0f, K, ldv, lane, y);
+  stencil_mfma<S, NT>(cg, D, site, t, x, x, 1.0f, K, ldv, lane, acc);
+  store_mfma<NT>(cg, site, t, acc, tw, x, b, -1.0f, K, ldv, lane, y);
 }
 
 // even sites of the odd-even reduced system: mode 0: y = (S + i tw G5) v - H t;
@@ -221,20 +212,19 @@ __global__ void __launch_bounds__(256) k_coarse_schur_even_mrhs(CGeom cg,
                                                                 const cx<float>* __restrict__ v,
                                                                 const cx<float>* __restrict__ t,
                                                                 cx<float>* __restrict__ y, int mode) {
-  const int lane = threadIdx.x & 63;
-  const int site = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (site >= cg.neven) return;
-  v4f acc[4][NT];
+  const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+  const int site = blockIdx.x;
+  v4f acc[NT];
   zero_acc<NT>(acc);
-  stencil_mfma<S, NT>(cg, D, site, mode == 0 ? v : nullptr, t, -1.0f, K, ldv, lane, acc);
-  if (mode == 0) store_mfma<NT>(cg, site, acc, tw, v, nullptr, 1.0f, K, ldv, lane, y);
-  else store_mfma<NT>(cg, site, acc, 0.0f, nullptr, v, 1.0f, K, ldv, lane, y);
+  stencil_mfma<S, NT>(cg, D, site, rt, mode == 0 ? v : nullptr, t, -1.0f, K, ldv, lane, acc);
+  if (mode == 0) store_mfma<NT>(cg, site, rt, acc, tw, v, nullptr, 1.0f, K, ldv, lane, y);
+  else store_mfma<NT>(cg, site, rt, acc, 0.0f, nullptr, v, 1.0f, K, ldv, lane, y);
 }
 
-// odd sites: y = Minv (base - H x) (base may be null: y = Minv (-(-H x)) = Minv H x
-// with the sign convention of the single right-hand-side kernel: y = Minv H x)
-// Minv: [odd site][n][n] FP32 column-major.  The hop result goes through LDS
-// ([n][K] per wavefront) to the FP32 matrix-vector products with Minv.
+// odd sites: y = Minv H x, or y = Minv (base - H x) with base.  Minv:
+// [odd site][n][n] FP32 column-major.  The hop result goes through LDS
+// ([n][16] complex) to the FP32 products with Minv, which all threads of the
+// workgroup share: thread -> row i = tid % n, columns r = tid / n + 4 q.
 template <class S, int NT>
 __global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
                                                                  const typename store_traits<S>::elem* __restrict__ D,
@@ -242,52 +232,44 @@ __global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
                                                                  const cx<float>* __restrict__ x,
                                                                  const cx<float>* __restrict__ base,
                                                                  cx<float>* __restrict__ y) {
-  __shared__ cx<float> us[4][64 * 16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int io = blockIdx.x * 4 + wv;
+  __shared__ cx<float> us[64 * 16];
+  const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+  const int io = blockIdx.x;
   const int site = cg.neven + io;
-  const bool valid = site < cg.nsites;
-  const int n = cg.n, RT = n >> 4;
-  if (valid) {
-    v4f acc[4][NT];
+  const int n = cg.n;
+  {
+    v4f acc[NT];
     zero_acc<NT>(acc);
-    stencil_mfma<S, NT>(cg, D, site, nullptr, x, 1.0f, K, ldv, lane, acc);
-    // u = H x or base - H x, into LDS as us[i * 16 + r]
+    stencil_mfma<S, NT>(cg, D, site, rt, nullptr, x, 1.0f, K, ldv, lane, acc);
     const int col = lane & 15, grp = lane >> 4;
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
       const int j = 16 * u + col, r = j >> 1, c = j & 1;
       if (r >= K) continue;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t >= RT) continue;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = 16 * t + 4 * grp + e;
-          float v = acc[t][u][e];
-          if (base) v = reinterpret_cast<const float*>(base + (long)r * ldv + (long)site * n + i)[c] - v;
-          reinterpret_cast<float*>(&us[wv][i * 16 + r])[c] = v;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * rt + 4 * grp + e;
+        float v = acc[u][e];
+        if (base) v = reinterpret_cast<const float*>(base + (long)r * ldv + (long)site * n + i)[c] - v;
+        reinterpret_cast<float*>(&us[i * 16 + r])[c] = v;
       }
     }
   }
   __syncthreads();
-  if (valid && lane < n) {
-    const cx<float>* M = Minv + (long)io * n * n;
-    cx<float> out[16];
+  const int i = threadIdx.x % n, r0 = threadIdx.x / n;  // r0 < 4 (blockDim = 4 n)
+  const cx<float>* M = Minv + (long)io * n * n;
+  cx<float> out[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) out[r] = mk<float>(0, 0);
-    for (int l = 0; l < n; ++l) {
-      cx<float> m = M[(long)l * n + lane];
-      const cx<float>* ul = &us[wv][l * 16];
+  for (int q = 0; q < 4; ++q) out[q] = mk<float>(0, 0);
+  for (int l = 0; l < n; ++l) {
+    cx<float> m = M[(long)l * n + i];
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r < K) cmac(out[r], m, ul[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      if (r < K) y[(long)r * ldv + (long)site * n + lane] = out[r];
+    for (int q = 0; q < 4; ++q)
+      if (r0 + 4 * q < K) cmac(out[q], m, us[l * 16 + r0 + 4 * q]);
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (r0 + 4 * q < K) y[(long)(r0 + 4 * q) * ldv + (long)site * n + i] = out[q];
 }
 
 static inline int nt_of(int K) { return K <= 8 ? 1 : 2; }
@@ -295,37 +277,35 @@ static inline int nt_of(int K) { return K <= 8 ? 1 : 2; }
 template <class S>
 void launch_coarse_apply_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* x,
                               const cx<float>* b, cx<float>* y, hipStream_t st) {
-  dim3 grid((cg.nsites + 3) / 4);
+  dim3 grid(cg.nsites), blk(4 * cg.n);
   auto Dp = (const typename store_traits<S>::elem*)D;
   if (nt_of(K) == 1)
-    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 1>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
+    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 1>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
   else
-    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 2>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
+    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 2>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
 }
 
 template <class S>
 void launch_coarse_schur_even_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* v,
                                    const cx<float>* t, cx<float>* y, int mode, hipStream_t st) {
-  dim3 grid((cg.neven + 3) / 4);
+  dim3 grid(cg.neven), blk(4 * cg.n);
   auto Dp = (const typename store_traits<S>::elem*)D;
   if (nt_of(K) == 1)
-    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 1>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, v, t, y,
-                       mode);
+    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 1>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, v, t, y, mode);
   else
-    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 2>), grid, dim3(256), 0, st, cg, Dp, (float)tw, K, ldv, v, t, y,
-                       mode);
+    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 2>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, v, t, y, mode);
 }
 
 template <class S>
 void launch_coarse_hop_inv_odd_mrhs(const CGeom& cg, const void* D, const cx<float>* Minv, int K, long ldv,
                                     const cx<float>* x, const cx<float>* base, cx<float>* y, hipStream_t st) {
   int nodd = cg.nsites - cg.neven;
-  dim3 grid((nodd + 3) / 4);
+  dim3 grid(nodd), blk(4 * cg.n);
   auto Dp = (const typename store_traits<S>::elem*)D;
   if (nt_of(K) == 1)
-    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 1>), grid, dim3(256), 0, st, cg, Dp, Minv, K, ldv, x, base, y);
+    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 1>), grid, blk, 0, st, cg, Dp, Minv, K, ldv, x, base, y);
   else
-    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 2>), grid, dim3(256), 0, st, cg, Dp, Minv, K, ldv, x, base, y);
+    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 2>), grid, blk, 0, st, cg, Dp, Minv, K, ldv, x, base, y);
 }
 
 #define INST_MRHS(S)                                                                                              \

@@ -75,6 +75,9 @@ void launch_coarse_residual(const CGeom& cg, const void* D, double tw, const cx<
 template <class R, class S>
 void launch_coarse_sap(const CGeom& cg, const void* D, double tw, int nblk_colour, int bsz, const int* blk_sites,
                        const int* blk_nbr, const cx<R>* r, cx<R>* x, int n_mr, hipStream_t st);
+template <class R, class S>
+void launch_coarse_sap_multi(const CGeom& cg, const void* D, double tw, int nblk_colour, int bsz, const int* blk_sites,
+                             const int* blk_nbr, const cx<R>* r, cx<R>* x, int n_mr, int K, long ld, hipStream_t st);
 // restriction / prolongation between coarse levels
 template <class R>
 void launch_restrict_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<R>* Q, long qstride,
@@ -110,6 +113,11 @@ void launch_net_mix(const Geom& g, int C, const cx<float>* U, const cx<float>* i
                     bool adj, hipStream_t st);
 void launch_net_gate(const Geom& g, int C, const cx<float>* z, const float* a, const float* b, cx<float>* y, float* sv,
                      hipStream_t st);
+// the forward mixing layer on the matrix cores (inference; C = 8, 16, 24): the
+// layer's weights packed once by launch_net_pack (9 * C * C * 16 * 2 floats)
+void launch_net_pack(int C, const cx<float>* W, float* P, hipStream_t st);
+void launch_net_mix_mfma(const Geom& g, int C, const cx<float>* U, const cx<float>* in, const float* P,
+                         cx<float>* out, hipStream_t st);
 void launch_net_gate_inplace(const Geom& g, int C, const float* a, const float* b, cx<float>* z, hipStream_t st);
 void launch_net_gate_bwd(const Geom& g, int C, const cx<float>* Gy, const cx<float>* z, const float* sv,
                          const float* a, cx<float>* Gz, double* partial, float* Ga, float* Gb, hipStream_t st);

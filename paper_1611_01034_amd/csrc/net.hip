@@ -128,6 +128,130 @@ __global__ void __launch_bounds__(256) k_net_mix(Geom g, const cx<float>* __rest
 }
 
 // ---------------------------------------------------------------------------
+// The mixing layer on the matrix cores (inference).  Per site and colour k the
+// layer is z[(c,s)] = sum_{(d,c',t)} W[d][c][c'][s][t] (T_d x_{c'})[t][k]: a
+// complex matrix of 4C rows (c,s) and 9*4C columns (d,c',t) times one column
+// per (site, colour).  It runs as a real FP32 product with the embedding
+//   A[i][(l,0)] = Re W_il, A[i][(l,1)] = Im W_il,
+//   B[(l,0)][(col,0)] = Re v, B[(l,1)][(col,0)] = -Im v, B[(l,0)][(col,1)] = Im v,
+//   B[(l,1)][(col,1)] = Re v,
+// on v_mfma_f32_16x16x4f32 (lane L: A[L%16][L/16], B[L/16][L%16], result
+// rows 4(L/16)+e, column L%16): FP32 products and sums, like the VALU kernel,
+// in another order.  A workgroup takes 64 sites, wavefront w sites 16w..16w+15
+// (96 real columns: 6 tiles); the transported inputs of 8 channels of one
+// offset are staged in LDS per step as in the VALU kernel.  The weights are
+// packed once per layer in fragment order (k_net_pack): one contiguous 256 B
+// load per A fragment.
+typedef float v4f_n __attribute__((ext_vector_type(4)));
+
+// packed[((chunk * 16 + step) * RT + t) * 64 + lane], chunk = d * (C/8) + k0/8
+__global__ void k_net_pack(int C, const cx<float>* __restrict__ W, float* __restrict__ P) {
+  const int RT = C / 4, nch = C / 8;
+  const long total = 9L * nch * 16 * RT * 64;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int lane = (int)(e & 63);
+    long r = e >> 6;
+    const int t = (int)(r % RT);
+    r /= RT;
+    const int step = (int)(r & 15);
+    const int chunk = (int)(r >> 4);
+    const int d = chunk / nch, k0 = (chunk % nch) * 8;
+    const int i = 16 * t + (lane & 15);           // row (c, s)
+    const int q = 4 * step + (lane >> 4);          // real inner index in the chunk
+    const int l = q >> 1, cp = q & 1;              // complex inner (c', t), part
+    const int ci = k0 + (l >> 2), tt = l & 3;
+    const int co = i >> 2, sp = i & 3;
+    cx<float> w = W[((long)(d * C + co) * C + ci) * 16 + sp * 4 + tt];
+    P[e] = cp == 0 ? w.re : w.im;
+  }
+}
+void launch_net_pack(int C, const cx<float>* W, float* P, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_pack, dim3(256), dim3(256), 0, st, C, W, P);
+}
+
+template <int RT>
+__global__ void __launch_bounds__(256) k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U,
+                                                      const cx<float>* __restrict__ in, const float* __restrict__ P,
+                                                      cx<float>* __restrict__ out) {
+  constexpr int C = 4 * RT, NCH = C / 8;
+  __shared__ cx<float> txs[8][12][64];
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const long fl = g.V * 12;
+  v4f_n acc[RT][6];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int u = 0; u < 6; ++u) acc[a][u] = v4f_n{0.f, 0.f, 0.f, 0.f};
+  // this lane's B columns: j = 16u + lane%16 = c + 2 (k + 3 site), site in 0..15 of the wave
+  const int kk = lane >> 4;
+#pragma unroll 1
+  for (int chunk = 0; chunk < 9 * NCH; ++chunk) {
+    const int d = chunk / NCH, k0 = (chunk % NCH) * 8;
+    __syncthreads();
+    for (int p = t; p < 64 * 8; p += 256) {
+      int i = p & 63, ch = p >> 6;
+      long gs = (long)blockIdx.x * 64 + i;
+      int Bi = (int)(gs / g.bs), si = (int)(gs - (long)Bi * g.bs);
+      cx<float> v[12];
+      transport_site(g, U, in + (long)(k0 + ch) * fl, d, Bi, si, v);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) txs[ch][c][i] = v[c];
+    }
+    __syncthreads();
+    const float* Pc = P + (long)chunk * 16 * RT * 64 + lane;
+#pragma unroll 2
+    for (int step = 0; step < 16; ++step) {
+      const int q = 4 * step + kk;
+      const int l = q >> 1, cp = q & 1;
+      const int ch = l >> 2, tt = l & 3;
+      float bf[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        const int j = 16 * u + (lane & 15);
+        const int c = j & 1, k = (j >> 1) % 3, site = (j >> 1) / 3;
+        cx<float> v = txs[ch][3 * tt + k][16 * w + site];
+        bf[u] = cp == 0 ? (c == 0 ? v.re : v.im) : (c == 0 ? -v.im : v.re);
+      }
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        const float af = Pc[(step * RT + a) * 64];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) acc[a][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[u], acc[a][u], 0, 0, 0);
+      }
+    }
+  }
+  // rows 16a + 4 kk + e = (c, s) = (i/4, i%4); column j -> (site, colour, part)
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int j = 16 * u + (lane & 15);
+    const int c = j & 1, k = (j >> 1) % 3, site = (j >> 1) / 3;
+    const long gs = (long)blockIdx.x * 64 + 16 * w + site;
+    const int Bs = (int)(gs / g.bs), ss = (int)(gs - (long)Bs * g.bs);
+    const long base = fidx(g, Bs, ss, 12);
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * a + 4 * kk + e;
+        const int co = i >> 2, sp = i & 3;
+        reinterpret_cast<float*>(out + (long)co * fl + base + (long)(3 * sp + k) * TILE)[c] = acc[a][u][e];
+      }
+  }
+}
+
+void launch_net_mix_mfma(const Geom& g, int C, const cx<float>* U, const cx<float>* in, const float* P,
+                         cx<float>* out, hipStream_t st) {
+  dim3 grid((unsigned)(g.V / 64));
+  switch (C) {
+    case 8: hipLaunchKernelGGL((k_net_mix_mfma<2>), grid, dim3(256), 0, st, g, U, in, P, out); break;
+    case 16: hipLaunchKernelGGL((k_net_mix_mfma<4>), grid, dim3(256), 0, st, g, U, in, P, out); break;
+    case 24: hipLaunchKernelGGL((k_net_mix_mfma<6>), grid, dim3(256), 0, st, g, U, in, P, out); break;
+    default: throw Error(INVALID_ARG, "matrix-core network layer needs 8, 16 or 24 channels");
+  }
+}
+
+// ---------------------------------------------------------------------------
 // gate: y = z * sigmoid(a |z|^2 + b); keeps the sigmoid for the backward pass
 __global__ void k_net_gate(Geom g, int C, const cx<float>* __restrict__ z, const float* __restrict__ a,
                            const float* __restrict__ b, cx<float>* __restrict__ y, float* __restrict__ sv) {

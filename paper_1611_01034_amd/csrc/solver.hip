@@ -788,6 +788,35 @@ struct MG : MGBase {
         launch_sap_multi<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, K, c.fine_len(), c.st);
       }
   }
+  // SAP on K fields of an intermediate level: residuals of all fields in one
+  // launch, then one launch per colour for all fields
+  void coarse_sap_m(int l, const cx<R>* b, cx<R>* x, int K, int iters) {
+    CoarseGeo& G = *geos[l];
+    CGeom cg = G.cg();
+    const long len = level_len(l);
+    cx<R>* r = wkm[l][1].template as<cx<R>>();
+    for (int it = 0; it < iters; ++it)
+      for (int col = 0; col < 2; ++col) {
+        {
+          TimeScope ts(c.timer, 2);
+          bool done = false;
+          if constexpr (kMfma) {
+            if (mfma_level(l)) {
+              launch_coarse_apply_mrhs<S>(cg, Dst(l), tw[l], K, len, x, b, r, c.st);
+              done = true;
+            }
+          }
+          if (!done)
+            for (int k = 0; k < K; ++k)
+              launch_coarse_residual<R, S>(cg, Dst(l), tw[l], b + k * len, x + k * len, r + k * len, c.st);
+        }
+        int off = col == 0 ? 0 : G.nsblk_col[0];
+        launch_coarse_sap_multi<R, S>(cg, Dst(l), tw[l], G.nsblk_col[col], G.ssz,
+                                      G.sap_sites.template as<int>() + off * G.ssz,
+                                      G.sap_nbr.template as<int>() + (long)off * G.ssz * 8, r, x, p.coarse_mr_steps, K,
+                                      len, c.st);
+      }
+  }
   void coarse_sap(int l, const cx<R>* b, cx<R>* x, int iters) {
     CoarseGeo& G = *geos[l];
     CGeom cg = G.cg();
@@ -989,10 +1018,8 @@ struct MG : MGBase {
     } else {
       for (int k = 0; k < K; ++k) restrict_(l, v + k * len, rc_ + k * lenc);
       coarse_solve_m(l + 1, rc_, ec_, K);
-      for (int k = 0; k < K; ++k) {
-        prolong_(l, ec_ + k * lenc, x + k * len, 0);
-        coarse_sap(l, v + k * len, x + k * len, p.coarse_sap_post);
-      }
+      for (int k = 0; k < K; ++k) prolong_(l, ec_ + k * lenc, x + k * len, 0);
+      coarse_sap_m(l, v, x, K, p.coarse_sap_post);
     }
   }
 

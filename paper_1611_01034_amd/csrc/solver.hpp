@@ -187,6 +187,7 @@ struct NetState {
   long nreal = 0;     // real parameters in total
   DevBuf params, grads, m, v;
   DevBuf act, zb, sb, g1, g2, wpart, gpart, lscr, lpart, host_stage;
+  DevBuf packed;      // weights in matrix-core fragment order (inference)
   long V = 0;         // lattice the buffers are sized for
   long step = 0;
   cx<float>* W(int l) const { return params.as<cx<float>>() + (long)l * nWc; }
