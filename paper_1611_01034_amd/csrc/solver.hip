@@ -306,14 +306,20 @@ void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex) {
     HIP_CHECK(hipHostMalloc((void**)&h_scal, sizeof(cx<double>) * 4 * 64, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void**)&h_act, sizeof(int) * 64, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void**)&h_jd, sizeof(int) * 64, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void**)&h_act_ring, sizeof(int) * 64, hipHostMallocDefault));
   }
+  for (auto& e : ready)
+    if (!e) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 template <class R>
 KrylovWSm<R>::~KrylovWSm() {
+  for (auto e : ready)
+    if (e) (void)hipEventDestroy(e);
   if (h_resid) (void)hipHostFree(h_resid);
   if (h_scal) (void)hipHostFree(h_scal);
   if (h_act) (void)hipHostFree(h_act);
   if (h_jd) (void)hipHostFree(h_jd);
+  if (h_act_ring) (void)hipHostFree(h_act_ring);
 }
 template struct KrylovWSm<double>;
 template struct KrylovWSm<float>;
@@ -321,7 +327,7 @@ template struct KrylovWSm<float>;
 template <class R>
 KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>& A, const OpM<R>* M, const cx<R>* b,
                            cx<R>* x, double tol, int max_iter, bool fixed, bool x_is_zero) {
-  if (K < 1 || K > ws.K || K > 64) throw Error(INVALID_ARG, "lock-step solve: bad column count");
+  if (K < 1 || K > ws.K || K > 16) throw Error(INVALID_ARG, "lock-step solve: bad column count");
   hipStream_t st = c.st;
   const int m = ws.m, ldh = m + 1;
   const long ld = ws.ld, hcs = (long)ldh * m;
@@ -346,8 +352,14 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
     HIP_CHECK(hipMemcpyAsync(ws.h_scal, scal, sizeof(cx<double>) * 4 * K, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
   };
+  // Each push copies from its own staging slot: with the look-ahead a slot is
+  // reused only after the host has waited on an event recorded after its copy
+  // (one is waited on per step, and a push happens at most once per step).
   auto push_act = [&]() {
-    HIP_CHECK(hipMemcpyAsync(act, ws.h_act, sizeof(int) * K, hipMemcpyHostToDevice, st));
+    int* slot = ws.h_act_ring + 16 * ws.act_slot;
+    ws.act_slot = (ws.act_slot + 1) & 3;
+    for (int k = 0; k < K; ++k) slot[k] = ws.h_act[k];
+    HIP_CHECK(hipMemcpyAsync(act, slot, sizeof(int) * K, hipMemcpyHostToDevice, st));
   };
   KrylovResultM res;
   res.iters.assign(K, 0);
@@ -385,6 +397,12 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
     launch_scale_by_inv_b<R>(r, ld, scal + 1, 4, V, ld, N, K, act, 1, st);
     launch_init_g_b(g, ldh, scal + 1, 4, K, act, st);
     for (int k = 0; k < K; ++k) ws.h_jd[k] = 0;
+    // Without a preconditioner the test of step j is taken while step j+1 is
+    // already queued; a column that met its tolerance at step j then drops
+    // step j+1, which changed only its Hessenberg column j+1 and g[j+1..j+2].
+    const bool lookahead = !fixed && M == nullptr;
+    int pend = -1;                 // step whose estimates are in flight
+    int act_at[2][16];             // columns active in the step of each slot
     for (int j = 0; j < mm; ++j) {
       cx<R>* Vj = V + (long)j * K * ld;
       cx<R>* Vn = V + (long)(j + 1) * K * ld;
@@ -414,7 +432,30 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
           ws.h_jd[k] = j + 1;
           ++res.iters[k];
         }
-      if (!fixed) {
+      if (lookahead) {
+        const int slot = j & 1;
+        HIP_CHECK(hipMemcpyAsync(ws.h_resid + 32 * slot, ws.resid.p, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipEventRecord(ws.ready[slot], st));
+        for (int k = 0; k < K; ++k) act_at[slot][k] = ws.h_act[k];
+        if (pend >= 0) {
+          const int ps = pend & 1;
+          HIP_CHECK(hipEventSynchronize(ws.ready[ps]));
+          bool changed = false;
+          for (int k = 0; k < K; ++k)
+            if (act_at[ps][k] && ws.h_act[k] && ws.h_resid[32 * ps + k] <= tol * bn[k]) {
+              ws.h_act[k] = 0;
+              changed = true;
+              if (act_at[slot][k]) {  // it also ran step j: drop it
+                --res.iters[k];
+                ws.h_jd[k] = pend + 1;
+              }
+            }
+          for (int k = 0; k < K; ++k) still += ws.h_act[k];
+          if (changed) push_act();
+          if (still == 0) break;
+        }
+        pend = j;
+      } else if (!fixed) {
         HIP_CHECK(hipMemcpyAsync(ws.h_resid, ws.resid.p, sizeof(double) * K, hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
         bool changed = false;
@@ -429,6 +470,7 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
       }
       if (steps >= max_iter) break;
     }
+    if (pend >= 0) HIP_CHECK(hipEventSynchronize(ws.ready[pend & 1]));
     HIP_CHECK(hipMemcpyAsync(jd, ws.h_jd, sizeof(int) * K, hipMemcpyHostToDevice, st));
     launch_trisolve_b(H, ldh, m, g, y, jd, K, st);
     launch_multi_axpy_b<R>(Z, (long)K * ld, ld, m, jd, y, ldh, 1.0, x, ld, N, K, nullptr, st);

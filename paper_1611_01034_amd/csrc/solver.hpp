@@ -89,9 +89,12 @@ struct KrylovWSm {
   long ld = 0;
   bool flexible = false;
   DevBuf V, Z, r, H, cs, sn, g, y, part, scal, resid, act, jd;
-  double* h_resid = nullptr;   // pinned: K residual estimates
+  double* h_resid = nullptr;   // pinned: K residual estimates (two slots of 32 for the look-ahead)
+  hipEvent_t ready[2] = {nullptr, nullptr};
   cx<double>* h_scal = nullptr;  // pinned: K x 4 scalars
-  int* h_act = nullptr;        // pinned: K flags
+  int* h_act = nullptr;        // pinned: K flags (host copy)
+  int* h_act_ring = nullptr;   // pinned: 4 x 16 staging slots for the asynchronous pushes of h_act
+  int act_slot = 0;
   int* h_jd = nullptr;         // pinned: K counts
   int nwg = 0;
   void init(int m_, int K_, long ld_, long N, bool flex);
