@@ -703,37 +703,95 @@ __global__ void __launch_bounds__(256) k_assemble_fine(Geom g, int Nv, const cx<
                                                        const cx<RQ>* __restrict__ Q, long qstride,
                                                        const int* __restrict__ f2c, cx<double>* __restrict__ Dc,
                                                        cx<double>* __restrict__ Xs) {
+  // The block's contributions are a list of terms (x, type): type 4 = site term
+  // Q(x)^dag H(x) Q(x), type mu = link term Q(x)^dag [-1/2 (1-g_mu) U_mu(x)]
+  // Q(x+mu).  kind 0 takes every site term and every link inside the block,
+  // kind 1+mu the links across the upper mu face.  Terms are processed TB at a
+  // time: stage Q(x) of each, build the n columns of its right factor (one
+  // thread per (term, column)), then every output entry accumulates the TB
+  // rank-6 updates.  Site terms go to S, internal links to X (kind 0).
+  constexpr int TB = 4;
   const int n = 2 * Nv;
-  __shared__ cx<double> qx[32 * 12];   // Q_i(x)[c]
-  __shared__ cx<double> W[64 * 12];    // W[l][c]
-  int B = blockIdx.x / 5, kind = blockIdx.x % 5;
-  int t = threadIdx.x;
+  __shared__ cx<double> qx[TB][32 * 12];   // Q_i(x)[c]
+  __shared__ cx<double> W[TB][64 * 12];    // right factor, column col, component c
+  __shared__ int tsite[TB], ttype[TB];
+  const int B = blockIdx.x / 5, kind = blockIdx.x % 5;
+  const int t = threadIdx.x;
   const int nent = n * n;
   cx<double> accS[16], accX[16];
   for (int m = 0; m < 16; ++m) accS[m] = accX[m] = mk(0.0, 0.0);
   int bc[4];
   block_coords(g, B, bc);
-  for (int sx = 0; sx < g.bs; ++sx) {
-    int l[4];
-    slot_local(g, sx, l);
-    if (kind > 0 && l[kind - 1] != g.b[kind - 1] - 1) continue;
+  // term index -> (site, type): sites in slot order; per site the site term (kind 0)
+  // then the links it carries; computed on the fly with a running cursor
+  int cur_site = 0, cur_sub = 0;
+  auto next_term = [&](int& sx, int& ty) -> bool {
+    while (cur_site < g.bs) {
+      int l[4];
+      slot_local(g, cur_site, l);
+      // sub 0: site term (kind 0 only); sub 1..4: link mu = sub-1
+      while (cur_sub < 5) {
+        const int sub = cur_sub++;
+        if (sub == 0) {
+          if (kind == 0) {
+            sx = cur_site;
+            ty = 4;
+            return true;
+          }
+          continue;
+        }
+        const int mu = sub - 1;
+        const bool take = kind == 0 ? (l[mu] + 1 < g.b[mu]) : (mu == kind - 1 && l[mu] == g.b[mu] - 1);
+        if (take) {
+          sx = cur_site;
+          ty = mu;
+          return true;
+        }
+      }
+      ++cur_site;
+      cur_sub = 0;
+    }
+    return false;
+  };
+  bool more = true;
+  while (more) {
+    // every thread walks the same list (uniform control flow)
+    int nt = 0, sx_[TB], ty_[TB];
+    while (nt < TB) {
+      int sx, ty;
+      if (!next_term(sx, ty)) {
+        more = false;
+        break;
+      }
+      sx_[nt] = sx;
+      ty_[nt] = ty;
+      ++nt;
+    }
+    if (nt == 0) break;
+    __syncthreads();  // previous group done with qx / W / the term list
+    if (t == 0)
+      for (int k = 0; k < nt; ++k) {
+        tsite[k] = sx_[k];
+        ttype[k] = ty_[k];
+      }
     __syncthreads();
-    for (int e = t; e < Nv * 12; e += 256) {
-      int i = e / 12, c = e % 12;
-      cx<RQ> v = Q[(long)i * qstride + fidx(g, B, sx, 12) + (long)c * TILE];
-      qx[e] = mk<double>(v.re, v.im);
+    for (int e = t; e < nt * Nv * 12; e += 256) {
+      const int tt = e / (Nv * 12), r = e - tt * Nv * 12;
+      const int i = r / 12, c = r % 12;
+      cx<RQ> v = Q[(long)i * qstride + fidx(g, B, tsite[tt], 12) + (long)c * TILE];
+      qx[tt][r] = mk<double>(v.re, v.im);
     }
     __syncthreads();
-    if (kind == 0) {
-      // site term W[l] = H_{half(l)} Q_{i_l}(x) on half(l), zero elsewhere
-      const double* hp = H + fidx(g, B, sx, 72);
-      for (int e = t; e < n * 12; e += 256) {
-        int col = e / 12, c = e % 12;
-        int hcol = col >= Nv ? 1 : 0, i = col - hcol * Nv;
-        cx<double> acc = mk(0.0, 0.0);
-        if (c / 6 == hcol) {
-          const double* h = hp + 36L * hcol * TILE;
-          int r = c % 6;
+    if (t < nt * n) {
+      const int tt = t / n, col = t - tt * n;
+      const int hcol = col >= Nv ? 1 : 0, i = col - hcol * Nv;
+      const int sx = tsite[tt], ty = ttype[tt];
+      if (ty == 4) {
+        // W = H_{half(col)} Q_i(x) on half(col), zero elsewhere
+        const double* h = H + fidx(g, B, sx, 72) + 36L * hcol * TILE;
+        for (int c = 0; c < 12; ++c) W[tt][col * 12 + c] = mk(0.0, 0.0);
+        for (int r = 0; r < 6; ++r) {
+          cx<double> acc = mk(0.0, 0.0);
           for (int j = 0; j < 6; ++j) {
             cx<double> hv;
             if (j == r) hv = mk(h[(long)r * TILE], 0.0);
@@ -744,65 +802,56 @@ __global__ void __launch_bounds__(256) k_assemble_fine(Geom g, int Nv, const cx<
               int k = 6 + 2 * herm_idx(j, r);
               hv = mk(h[(long)k * TILE], -h[(long)(k + 1) * TILE]);
             }
-            cmac(acc, hv, qx[i * 12 + 6 * hcol + j]);
+            cmac(acc, hv, qx[tt][i * 12 + 6 * hcol + j]);
           }
+          W[tt][col * 12 + 6 * hcol + r] = acc;
         }
-        W[col * 12 + c] = acc;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        int e = t + 256 * m;
-        if (e < nent) {
-          int col = e / n, row = e % n;
-          int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
-          cx<double> acc = accS[m];
-          for (int c = 0; c < 6; ++c) cjmac(acc, qx[ir * 12 + 6 * hr + c], W[col * 12 + 6 * hr + c]);
-          accS[m] = acc;
+      } else {
+        // W = -1/2 (1-g_mu) U_mu(x) Q_col(x+mu)
+        const int mu = ty;
+        int l[4];
+        slot_local(g, sx, l);
+        int By, sy;
+        {
+          SiteNbr me;
+          for (int d = 0; d < 4; ++d) {
+            me.bc[d] = bc[d];
+            me.l[d] = l[d];
+          }
+          nbr_of(g, me, mu, +1, By, sy);
         }
-      }
-    }
-    // links: kind 0 -> internal forward links of every direction, kind 1+mu -> the face link
-    for (int mu = 0; mu < 4; ++mu) {
-      bool take = (kind == 0) ? (l[mu] + 1 < g.b[mu]) : (mu == kind - 1);
-      if (!take) continue;
-      int By, sy;
-      {
-        SiteNbr me;
-        for (int d = 0; d < 4; ++d) {
-          me.bc[d] = bc[d];
-          me.l[d] = l[d];
-        }
-        nbr_of(g, me, mu, +1, By, sy);
-      }
-      __syncthreads();
-      // W[col] = -1/2 (1-g_mu) U_mu(x) Q_col(y)
-      if (t < n) {
-        int col = t, hcol = col >= Nv ? 1 : 0, i = col - hcol * Nv;
         cx<double> psi[12], out[12], u[9];
         for (int c = 0; c < 12; ++c) {
           psi[c] = mk(0.0, 0.0);
           out[c] = mk(0.0, 0.0);
         }
+        // static register indices (both halves written, one of them zero)
+#pragma unroll
         for (int c = 0; c < 6; ++c) {
           cx<RQ> v = Q[(long)i * qstride + fidx(g, By, sy, 12) + (long)(6 * hcol + c) * TILE];
-          psi[6 * hcol + c] = mk<double>(v.re, v.im);
+          cx<double> vd = mk<double>(v.re, v.im);
+          psi[c] = hcol == 0 ? vd : mk(0.0, 0.0);
+          psi[6 + c] = hcol == 0 ? mk(0.0, 0.0) : vd;
         }
         long ub = fidx(g, B, sx, 36) + (long)mu * 9 * TILE;
+#pragma unroll
         for (int k = 0; k < 9; ++k) u[k] = U[ub + (long)k * TILE];
         hop_accum<0>(mu, psi, u, out);
-        for (int c = 0; c < 12; ++c) W[col * 12 + c] = out[c];
-      }
-      __syncthreads();
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        int e = t + 256 * m;
-        if (e < nent) {
-          int col = e / n, row = e % n;
-          int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
+        for (int c = 0; c < 12; ++c) W[tt][col * 12 + c] = out[c];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      int e = t + 256 * m;
+      if (e < nent) {
+        const int col = e / n, row = e % n;
+        const int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
+        for (int tt = 0; tt < nt; ++tt) {
           cx<double> acc = mk(0.0, 0.0);
-          for (int c = 0; c < 6; ++c) cjmac(acc, qx[ir * 12 + 6 * hr + c], W[col * 12 + 6 * hr + c]);
-          if (kind == 0) accX[m] += acc;
+          for (int c = 0; c < 6; ++c) cjmac(acc, qx[tt][ir * 12 + 6 * hr + c], W[tt][col * 12 + 6 * hr + c]);
+          if (kind == 0 && ttype[tt] != 4) accX[m] += acc;
           else accS[m] += acc;
         }
       }
