@@ -476,8 +476,10 @@ void launch_assemble_coarse(const CGeom& cg, int Nv, int nagg, const int ab[4], 
                      agg_sites, D, Q, qstride, Dn, Xs);
 }
 
-// S += Gamma5 X^dag Gamma5 (self blocks, column-major)
-__global__ void k_self_fixup(int n, int nsites, cx<double>* __restrict__ D, const cx<double>* __restrict__ Xs) {
+// S += Gamma5 X^dag Gamma5 (self blocks, column-major), and S += X first when
+// the assembly wrote the internal forward links to X only (add_x)
+__global__ void k_self_fixup(int n, int nsites, cx<double>* __restrict__ D, const cx<double>* __restrict__ Xs,
+                             int add_x) {
   long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long nn = (long)n * n;
   if (gid >= (long)nsites * nn) return;
@@ -486,11 +488,13 @@ __global__ void k_self_fixup(int n, int nsites, cx<double>* __restrict__ D, cons
   int col = e / n, row = e - col * n;
   cx<double> xv = Xs[(long)site * nn + (long)row * n + col];  // X(col,row)
   double s = g5(row, n) * g5(col, n);
-  D[(long)site * 5 * nn + e] += s * conj(xv);
+  cx<double> d = D[(long)site * 5 * nn + e] + s * conj(xv);
+  if (add_x) d += Xs[(long)site * nn + e];
+  D[(long)site * 5 * nn + e] = d;
 }
-void launch_self_fixup(int n, int nsites, cx<double>* D, const cx<double>* Xs, hipStream_t st) {
+void launch_self_fixup(int n, int nsites, cx<double>* D, const cx<double>* Xs, int add_x, hipStream_t st) {
   long tot = (long)nsites * n * n;
-  hipLaunchKernelGGL(k_self_fixup, dim3((tot + 255) / 256), dim3(256), 0, st, n, nsites, D, Xs);
+  hipLaunchKernelGGL(k_self_fixup, dim3((tot + 255) / 256), dim3(256), 0, st, n, nsites, D, Xs, add_x);
 }
 
 // ---------------------------------------------------------------------------

@@ -691,188 +691,216 @@ template void launch_qr_fine<float, float>(const Geom&, int, const cx<float>*, l
                                            hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Galerkin assembly of the first coarse operator, FP64.  One workgroup per
-// (block, kind): kind 0 = self block (site terms Q^dag H Q and the links inside
-// the block), kind 1+mu = forward block for the links leaving the block across
-// its upper mu face.  Output blocks column-major: element (k,l) at l*n + k.
-// The self kind also writes X (internal forward links) for the Gamma5 fix-up
-// S += Gamma5 X^dag Gamma5 done by k_self_fixup.
-template <class RQ>
-__global__ void __launch_bounds__(256) k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U,
-                                                       const double* __restrict__ H,
-                                                       const cx<RQ>* __restrict__ Q, long qstride,
-                                                       const int* __restrict__ f2c, cx<double>* __restrict__ Dc,
-                                                       cx<double>* __restrict__ Xs) {
-  // The block's contributions are a list of terms (x, type): type 4 = site term
-  // Q(x)^dag H(x) Q(x), type mu = link term Q(x)^dag [-1/2 (1-g_mu) U_mu(x)]
-  // Q(x+mu).  kind 0 takes every site term and every link inside the block,
-  // kind 1+mu the links across the upper mu face.  Terms are processed TB at a
-  // time: stage Q(x) of each, build the n columns of its right factor (one
-  // thread per (term, column)), then every output entry accumulates the TB
-  // rank-6 updates.  Site terms go to S, internal links to X (kind 0).
-  constexpr int TB = 4;
-  const int n = 2 * Nv;
-  __shared__ cx<double> qx[TB][32 * 12];   // Q_i(x)[c]
-  __shared__ cx<double> W[TB][64 * 12];    // right factor, column col, component c
-  __shared__ int tsite[TB], ttype[TB];
-  const int B = blockIdx.x / 5, kind = blockIdx.x % 5;
-  const int t = threadIdx.x;
-  const int nent = n * n;
-  cx<double> accS[16], accX[16];
-  for (int m = 0; m < 16; ++m) accS[m] = accX[m] = mk(0.0, 0.0);
-  int bc[4];
-  block_coords(g, B, bc);
-  // term index -> (site, type): sites in slot order; per site the site term (kind 0)
-  // then the links it carries; computed on the fly with a running cursor
-  int cur_site = 0, cur_sub = 0;
-  auto next_term = [&](int& sx, int& ty) -> bool {
-    while (cur_site < g.bs) {
-      int l[4];
-      slot_local(g, cur_site, l);
-      // sub 0: site term (kind 0 only); sub 1..4: link mu = sub-1
-      while (cur_sub < 5) {
-        const int sub = cur_sub++;
-        if (sub == 0) {
-          if (kind == 0) {
-            sx = cur_site;
-            ty = 4;
-            return true;
-          }
-          continue;
-        }
-        const int mu = sub - 1;
-        const bool take = kind == 0 ? (l[mu] + 1 < g.b[mu]) : (mu == kind - 1 && l[mu] == g.b[mu] - 1);
-        if (take) {
-          sx = cur_site;
-          ty = mu;
-          return true;
-        }
-      }
-      ++cur_site;
-      cur_sub = 0;
-    }
-    return false;
-  };
-  bool more = true;
-  while (more) {
-    // every thread walks the same list (uniform control flow)
-    int nt = 0, sx_[TB], ty_[TB];
-    while (nt < TB) {
-      int sx, ty;
-      if (!next_term(sx, ty)) {
-        more = false;
-        break;
-      }
-      sx_[nt] = sx;
-      ty_[nt] = ty;
-      ++nt;
-    }
-    if (nt == 0) break;
-    __syncthreads();  // previous group done with qx / W / the term list
-    if (t == 0)
-      for (int k = 0; k < nt; ++k) {
-        tsite[k] = sx_[k];
-        ttype[k] = ty_[k];
-      }
-    __syncthreads();
-    for (int e = t; e < nt * Nv * 12; e += 256) {
-      const int tt = e / (Nv * 12), r = e - tt * Nv * 12;
-      const int i = r / 12, c = r % 12;
-      cx<RQ> v = Q[(long)i * qstride + fidx(g, B, tsite[tt], 12) + (long)c * TILE];
-      qx[tt][r] = mk<double>(v.re, v.im);
-    }
-    __syncthreads();
-    if (t < nt * n) {
-      const int tt = t / n, col = t - tt * n;
-      const int hcol = col >= Nv ? 1 : 0, i = col - hcol * Nv;
-      const int sx = tsite[tt], ty = ttype[tt];
-      if (ty == 4) {
-        // W = H_{half(col)} Q_i(x) on half(col), zero elsewhere
-        const double* h = H + fidx(g, B, sx, 72) + 36L * hcol * TILE;
-        for (int c = 0; c < 12; ++c) W[tt][col * 12 + c] = mk(0.0, 0.0);
-        for (int r = 0; r < 6; ++r) {
-          cx<double> acc = mk(0.0, 0.0);
-          for (int j = 0; j < 6; ++j) {
-            cx<double> hv;
-            if (j == r) hv = mk(h[(long)r * TILE], 0.0);
-            else if (j > r) {
-              int k = 6 + 2 * herm_idx(r, j);
-              hv = mk(h[(long)k * TILE], h[(long)(k + 1) * TILE]);
-            } else {
-              int k = 6 + 2 * herm_idx(j, r);
-              hv = mk(h[(long)k * TILE], -h[(long)(k + 1) * TILE]);
-            }
-            cmac(acc, hv, qx[tt][i * 12 + 6 * hcol + j]);
-          }
-          W[tt][col * 12 + 6 * hcol + r] = acc;
-        }
-      } else {
-        // W = -1/2 (1-g_mu) U_mu(x) Q_col(x+mu)
-        const int mu = ty;
-        int l[4];
-        slot_local(g, sx, l);
-        int By, sy;
-        {
-          SiteNbr me;
-          for (int d = 0; d < 4; ++d) {
-            me.bc[d] = bc[d];
-            me.l[d] = l[d];
-          }
-          nbr_of(g, me, mu, +1, By, sy);
-        }
-        cx<double> psi[12], out[12], u[9];
-        for (int c = 0; c < 12; ++c) {
-          psi[c] = mk(0.0, 0.0);
-          out[c] = mk(0.0, 0.0);
-        }
-        // static register indices (both halves written, one of them zero)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          cx<RQ> v = Q[(long)i * qstride + fidx(g, By, sy, 12) + (long)(6 * hcol + c) * TILE];
-          cx<double> vd = mk<double>(v.re, v.im);
-          psi[c] = hcol == 0 ? vd : mk(0.0, 0.0);
-          psi[6 + c] = hcol == 0 ? mk(0.0, 0.0) : vd;
-        }
-        long ub = fidx(g, B, sx, 36) + (long)mu * 9 * TILE;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) u[k] = U[ub + (long)k * TILE];
-        hop_accum<0>(mu, psi, u, out);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) W[tt][col * 12 + c] = out[c];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      int e = t + 256 * m;
-      if (e < nent) {
-        const int col = e / n, row = e % n;
-        const int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
-        for (int tt = 0; tt < nt; ++tt) {
-          cx<double> acc = mk(0.0, 0.0);
-          for (int c = 0; c < 6; ++c) cjmac(acc, qx[tt][ir * 12 + 6 * hr + c], W[tt][col * 12 + 6 * hr + c]);
-          if (kind == 0 && ttype[tt] != 4) accX[m] += acc;
-          else accS[m] += acc;
-        }
-      }
+// Galerkin assembly of the first coarse operator on the matrix cores.  One
+// workgroup (4 wavefronts) per (block, kind), each kind a sum over a list of
+// sites x of rank-6 products
+//   C[(i,a),(j,b)] += sum_{c in half a} conj(Q_i(x)_c) Y_(j,b)(x)_c,
+// with Y_(j,b) a right factor applied to the chirality-b half of Q_j:
+//   kind 0 (self block S, every site):  Y = H(x) P_b Q_j(x)
+//   kind 1 (internal links X, every site):
+//       Y = sum_{mu: x+mu in block} -1/2 (1-g_mu) U_mu(x) P_b Q_j(x+mu)
+//   kind 2+mu (forward block mu, sites on the upper mu face):
+//       Y = -1/2 (1-g_mu) U_mu(x) P_b Q_j(x+mu)
+// S goes to the self block, X to Xs for the fix-up S += X + Gamma5 X^dag Gamma5
+// (k_self_fixup), the face kinds to the forward blocks; output blocks are
+// column-major (element (k,l) at l*n + k).
+// The complex products run as real ones on 16x16x4 MFMA (FP64 for an FP64 Q,
+// FP32 for an FP32 Q): rows (i,a) are padded to 32 per half, wavefront w owning
+// half a = w/2 and rows 16(w%2)..+15; the contraction index is (x, c in half a,
+// re/im); columns (j,b) go in groups of 16 with a real and an imaginary tile
+// (conj(q) y = (q.re y.re + q.im y.im) + i (q.re y.im - q.im y.re)).  CS sites
+// at a time are staged in LDS: Q(x), and Y built in FP64 by one thread per
+// (site, column).
+namespace {
+typedef double v4d_a __attribute__((ext_vector_type(4)));
+typedef float v4f_a __attribute__((ext_vector_type(4)));
+// lane L supplies A[L%16][L/16] and B[L/16][L%16]; element e of the
+// accumulator holds D[row(L, e)][L%16], with row = L/16 + 4e for FP64 and
+// 4(L/16) + e for FP32 (measured on gfx950)
+template <class T> struct mfma_k4;
+template <> struct mfma_k4<double> {
+  typedef v4d_a acc;
+  static __device__ __forceinline__ acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+template <> struct mfma_k4<float> {
+  typedef v4f_a acc;
+  static __device__ __forceinline__ acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+
+// slot of face site f of the upper mu face (the other coordinates in TZYX order)
+__device__ __forceinline__ int face_slot(const Geom& g, int mu, int f) {
+  int l[4];
+  for (int d = 3; d >= 0; --d) {
+    if (d == mu) {
+      l[d] = g.b[d] - 1;
+    } else {
+      l[d] = f % g.b[d];
+      f /= g.b[d];
     }
   }
-  long site = f2c[B];
-  cx<double>* out = Dc + ((long)site * 5 + kind) * nent;
+  return local_slot(g, l);
+}
+
+// y += -1/2 (1-g_MU) U psi, psi = chirality-HB half of a spinor (other half zero);
+// qn: component 0 of that spinor, up: the link, both with stride TILE
+template <int MU, int HB, class RQ>
+__device__ __forceinline__ void half_hop(const cx<RQ>* qn, const cx<double>* up, cx<double> y[12]) {
+  cx<double> psi[12], u[9];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    int e = t + 256 * m;
-    if (e < nent) {
-      out[e] = accS[m] + accX[m];
-      if (kind == 0) Xs[(long)site * nent + e] = accX[m];
+  for (int c = 0; c < 12; ++c) psi[c] = mk(0.0, 0.0);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const cx<RQ> v = qn[(long)(6 * HB + c) * TILE];
+    psi[6 * HB + c] = mk<double>(v.re, v.im);
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[k] = up[(long)k * TILE];
+  hop_accum_t<0, MU>(psi, u, y);
+}
+template <class RQ>
+__device__ __forceinline__ void half_hop(int mu, int hb, const cx<RQ>* qn, const cx<double>* up, cx<double> y[12]) {
+  switch (2 * mu + hb) {
+    case 0: half_hop<0, 0>(qn, up, y); break;
+    case 1: half_hop<0, 1>(qn, up, y); break;
+    case 2: half_hop<1, 0>(qn, up, y); break;
+    case 3: half_hop<1, 1>(qn, up, y); break;
+    case 4: half_hop<2, 0>(qn, up, y); break;
+    case 5: half_hop<2, 1>(qn, up, y); break;
+    case 6: half_hop<3, 0>(qn, up, y); break;
+    default: half_hop<3, 1>(qn, up, y); break;
+  }
+}
+}  // namespace
+
+template <class RQ, class T, int CS, int NG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* __restrict__ H,
+                const cx<RQ>* __restrict__ Q, long qstride, const int* __restrict__ f2c, cx<double>* __restrict__ Dc,
+                cx<double>* __restrict__ Xs) {
+  using MF = mfma_k4<T>;
+  using acc_t = typename MF::acc;
+  constexpr int NC = 16 * NG;         // padded complex columns
+  __shared__ cx<T> qs[CS][12][32];    // Q_i(x)_c, rows i padded to 32
+  __shared__ cx<T> ys[CS][12][NC];    // Y_col(x)_c
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int B = wg / 6, kind = wg - 6 * (wg / 6);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int n = 2 * Nv;
+  const int nsites = kind < 2 ? g.bs : g.bs / g.b[kind - 2];
+  int bc[4];
+  block_coords(g, B, bc);
+  acc_t acc[NG][2];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) acc[q][0] = acc[q][1] = acc_t{0, 0, 0, 0};
+
+  for (int x0 = 0; x0 < nsites; x0 += CS) {
+    // stage Q(x) of the CS sites (zero past the list and past Nv)
+    for (int e = t; e < CS * 12 * 32; e += 256) {
+      const int xs = e / 384, r = e - xs * 384, c = r >> 5, i = r & 31;
+      cx<T> v = mk<T>(0, 0);
+      if (x0 + xs < nsites && i < Nv) {
+        const int sx = kind < 2 ? x0 + xs : face_slot(g, kind - 2, x0 + xs);
+        const cx<RQ> q = Q[(long)i * qstride + fidx(g, B, sx, 12) + (long)c * TILE];
+        v = mk<T>((T)q.re, (T)q.im);
+      }
+      qs[xs][c][i] = v;
+    }
+    // right factors: one thread per (site, column)
+    for (int it = t; it < CS * NC; it += 256) {
+      const int xs = it / NC, col = it - xs * NC;
+      cx<double> y[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) y[c] = mk(0.0, 0.0);
+      if (x0 + xs < nsites && col < n) {
+        const int sx = kind < 2 ? x0 + xs : face_slot(g, kind - 2, x0 + xs);
+        const int hb = col >= Nv ? 1 : 0, j = col - hb * Nv;
+        const cx<RQ>* qj = Q + (long)j * qstride;
+        if (kind == 0) {
+          cx<double> psi[6], hy[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            const cx<RQ> v = qj[fidx(g, B, sx, 12) + (long)(6 * hb + c) * TILE];
+            psi[c] = mk<double>(v.re, v.im);
+          }
+          herm_mv(H + fidx(g, B, sx, 72) + 36L * hb * TILE, TILE, psi, hy);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            y[c] = hb == 0 ? hy[c] : mk(0.0, 0.0);
+            y[6 + c] = hb == 0 ? mk(0.0, 0.0) : hy[c];
+          }
+        } else {
+          SiteNbr me;
+          for (int d = 0; d < 4; ++d) me.bc[d] = bc[d];
+          slot_local(g, sx, me.l);
+#pragma unroll
+          for (int mu = 0; mu < 4; ++mu) {
+            const bool take = mu < g.ndir && (kind == 1 ? me.l[mu] + 1 < g.b[mu] : mu == kind - 2);
+            if (!take) continue;
+            int By, sy;
+            nbr_of(g, me, mu, +1, By, sy);
+            half_hop(mu, hb, qj + fidx(g, By, sy, 12), U + fidx(g, B, sx, 36) + (long)mu * 9 * TILE, y);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) ys[xs][c][col] = mk<T>((T)y[c].re, (T)y[c].im);
+    }
+    __syncthreads();
+    {
+      const int a = w >> 1, i0 = 16 * (w & 1), r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+      for (int xs = 0; xs < CS; ++xs)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          const int kl = 4 * s + kq, c = 6 * a + (kl >> 1), p = kl & 1;
+          const cx<T> qv = qs[xs][c][i0 + r16];
+          const T av = p ? qv.im : qv.re;
+#pragma unroll
+          for (int q = 0; q < NG; ++q) {
+            const cx<T> yv = ys[xs][c][16 * q + r16];
+            const T bre = p ? yv.im : yv.re;
+            const T bim = p ? -yv.re : yv.im;
+            acc[q][0] = MF::step(av, bre, acc[q][0]);
+            acc[q][1] = MF::step(av, bim, acc[q][1]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  const long site = f2c[B];
+  const long nn = (long)n * n;
+  cx<double>* out = kind == 1 ? Xs + site * nn : Dc + (site * 5 + (kind == 0 ? 0 : kind - 1)) * nn;
+  const int a = w >> 1, i0 = 16 * (w & 1);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int col = 16 * q + (lane & 15);
+    if (col >= n) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + MF::row(lane, e);
+      if (i < Nv) out[(long)col * n + a * Nv + i] = mk<double>(acc[q][0][e], acc[q][1][e]);
     }
   }
 }
 template <class RQ>
 void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, const cx<RQ>* Q, long qstride,
                           const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble_fine<RQ>, dim3(5 * g.nblocks), dim3(256), 0, st, g, Nv, U, H, Q, qstride, f2c, Dc,
-                     Xs);
+  if (Nv < 1 || Nv > 32) throw Error(INVALID_ARG, "assembly: nvec must be in [1, 32]");
+  // sites per stage: LDS of two workgroups per CU
+  constexpr int CS = 4, CS4 = sizeof(RQ) == 8 ? 3 : 4;
+  const dim3 grid(6 * g.nblocks), blk(256);
+  switch ((2 * Nv + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS, 1>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    case 2: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS, 2>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    case 3: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS, 3>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    default: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS4, 4>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+  }
 }
 template void launch_assemble_fine<double>(const Geom&, int, const cx<double>*, const double*, const cx<double>*,
                                            long, const int*, cx<double>*, cx<double>*, hipStream_t);

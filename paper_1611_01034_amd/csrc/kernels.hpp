@@ -92,7 +92,7 @@ template <class RQ>
 void launch_assemble_coarse(const CGeom& cg, int Nv, int nagg, const int ab[4], const int* agg_sites,
                             const cx<double>* D, const cx<RQ>* Q, long qstride, cx<double>* Dn, cx<double>* Xs,
                             hipStream_t st);
-void launch_self_fixup(int n, int nsites, cx<double>* D, const cx<double>* Xs, hipStream_t st);
+void launch_self_fixup(int n, int nsites, cx<double>* D, const cx<double>* Xs, int add_x, hipStream_t st);
 // inverse of the site blocks (S + i tw Gamma5) on odd sites of the coarsest level
 template <class R>
 void launch_coarse_odd_inverse(const CGeom& cg, const cx<double>* D, double tw, cx<double>* scratch, cx<R>* Minv,

@@ -1172,7 +1172,8 @@ struct MG : MGBase {
                                 D64[l].template as<cx<double>>(), Q[l].template as<cx<R>>(), len,
                                 D64[l + 1].template as<cx<double>>(), Xs.template as<cx<double>>(), c.st);
     }
-    launch_self_fixup(Gn.n, Gn.nsites, D64[l + 1].template as<cx<double>>(), Xs.template as<cx<double>>(), c.st);
+    launch_self_fixup(Gn.n, Gn.nsites, D64[l + 1].template as<cx<double>>(), Xs.template as<cx<double>>(),
+                      l == 0 ? 1 : 0, c.st);
     if constexpr (!std::is_same<S, double>::value)
       launch_cvt_cx<S>((long)Gn.n * Gn.n * 5 * Gn.nsites, D64[l + 1].template as<cx<double>>(), DS[l + 1].p, c.st);
     if (l + 1 == L - 1)
