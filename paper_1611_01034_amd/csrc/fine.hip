@@ -709,8 +709,8 @@ template void launch_qr_fine<float, float>(const Geom&, int, const cx<float>*, l
 // half a = w/2 and rows 16(w%2)..+15; the contraction index is (x, c in half a,
 // re/im); columns (j,b) go in groups of 16 with a real and an imaginary tile
 // (conj(q) y = (q.re y.re + q.im y.im) + i (q.re y.im - q.im y.re)).  CS sites
-// at a time are staged in LDS: Q(x), and Y built in FP64 by one thread per
-// (site, column).
+// at a time are staged in LDS: Q(x) with H(x) or U(x), then Y, built in the
+// product's precision by one thread per (site, column).
 namespace {
 typedef double v4d_a __attribute__((ext_vector_type(4)));
 typedef float v4f_a __attribute__((ext_vector_type(4)));
@@ -747,39 +747,28 @@ __device__ __forceinline__ int face_slot(const Geom& g, int mu, int f) {
   return local_slot(g, l);
 }
 
-// y += -1/2 (1-g_MU) U psi, psi = chirality-HB half of a spinor (other half zero);
-// qn: component 0 of that spinor, up: the link, both with stride TILE
-template <int MU, int HB, class RQ>
-__device__ __forceinline__ void half_hop(const cx<RQ>* qn, const cx<double>* up, cx<double> y[12]) {
-  cx<double> psi[12], u[9];
+// y += -1/2 (1-g_MU) U psi, psi = the chirality-HB half p6 of a spinor (other
+// half zero), U = up[0..8]; arithmetic in T
+template <int MU, int HB, class RQ, class T>
+__device__ __forceinline__ void half_hop(const cx<RQ> p6[6], const cx<T>* up, cx<T> y[12]) {
+  cx<T> psi[12], u[9];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) psi[c] = mk(0.0, 0.0);
+  for (int c = 0; c < 12; ++c) psi[c] = mk<T>(0, 0);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    const cx<RQ> v = qn[(long)(6 * HB + c) * TILE];
-    psi[6 * HB + c] = mk<double>(v.re, v.im);
-  }
+  for (int c = 0; c < 6; ++c) psi[6 * HB + c] = mk<T>((T)p6[c].re, (T)p6[c].im);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) u[k] = up[(long)k * TILE];
+  for (int k = 0; k < 9; ++k) u[k] = up[k];
   hop_accum_t<0, MU>(psi, u, y);
 }
-template <class RQ>
-__device__ __forceinline__ void half_hop(int mu, int hb, const cx<RQ>* qn, const cx<double>* up, cx<double> y[12]) {
-  switch (2 * mu + hb) {
-    case 0: half_hop<0, 0>(qn, up, y); break;
-    case 1: half_hop<0, 1>(qn, up, y); break;
-    case 2: half_hop<1, 0>(qn, up, y); break;
-    case 3: half_hop<1, 1>(qn, up, y); break;
-    case 4: half_hop<2, 0>(qn, up, y); break;
-    case 5: half_hop<2, 1>(qn, up, y); break;
-    case 6: half_hop<3, 0>(qn, up, y); break;
-    default: half_hop<3, 1>(qn, up, y); break;
-  }
+template <int MU, class RQ, class T>
+__device__ __forceinline__ void half_hop(int hb, const cx<RQ> p6[6], const cx<T>* up, cx<T> y[12]) {
+  if (hb) half_hop<MU, 1>(p6, up, y);
+  else half_hop<MU, 0>(p6, up, y);
 }
 }  // namespace
 
 template <class RQ, class T, int CS, int NG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4, 8)))
 k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* __restrict__ H,
                 const cx<RQ>* __restrict__ Q, long qstride, const int* __restrict__ f2c, cx<double>* __restrict__ Dc,
                 cx<double>* __restrict__ Xs) {
@@ -788,6 +777,8 @@ k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* 
   constexpr int NC = 16 * NG;         // padded complex columns
   __shared__ cx<T> qs[CS][12][32];    // Q_i(x)_c, rows i padded to 32
   __shared__ cx<T> ys[CS][12][NC];    // Y_col(x)_c
+  __shared__ cx<T> us[CS][4][9];      // U_mu(x) (link kinds)
+  __shared__ T hs[CS][72];            // H(x) (site kind)
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int B = wg / 6, kind = wg - 6 * (wg / 6);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -800,7 +791,7 @@ k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* 
   for (int q = 0; q < NG; ++q) acc[q][0] = acc[q][1] = acc_t{0, 0, 0, 0};
 
   for (int x0 = 0; x0 < nsites; x0 += CS) {
-    // stage Q(x) of the CS sites (zero past the list and past Nv)
+    // stage Q(x), and H(x) or U(x), of the CS sites (zero past the list and past Nv)
     for (int e = t; e < CS * 12 * 32; e += 256) {
       const int xs = e / 384, r = e - xs * 384, c = r >> 5, i = r & 31;
       cx<T> v = mk<T>(0, 0);
@@ -811,45 +802,71 @@ k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* 
       }
       qs[xs][c][i] = v;
     }
+    if (kind == 0) {
+      for (int e = t; e < CS * 72; e += 256) {
+        const int xs = e / 72, k = e - xs * 72;
+        hs[xs][k] = x0 + xs < nsites ? (T)H[fidx(g, B, x0 + xs, 72) + (long)k * TILE] : T(0);
+      }
+    } else {
+      for (int e = t; e < CS * 36; e += 256) {
+        const int xs = e / 36, k = e - xs * 36;
+        cx<T> v = mk<T>(0, 0);
+        if (x0 + xs < nsites) {
+          const int sx = kind < 2 ? x0 + xs : face_slot(g, kind - 2, x0 + xs);
+          const cx<double> ud = U[fidx(g, B, sx, 36) + (long)k * TILE];
+          v = mk<T>((T)ud.re, (T)ud.im);
+        }
+        us[xs][k / 9][k % 9] = v;
+      }
+    }
+    __syncthreads();
     // right factors: one thread per (site, column)
     for (int it = t; it < CS * NC; it += 256) {
       const int xs = it / NC, col = it - xs * NC;
-      cx<double> y[12];
+      cx<T> y[12];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) y[c] = mk(0.0, 0.0);
+      for (int c = 0; c < 12; ++c) y[c] = mk<T>(0, 0);
       if (x0 + xs < nsites && col < n) {
-        const int sx = kind < 2 ? x0 + xs : face_slot(g, kind - 2, x0 + xs);
         const int hb = col >= Nv ? 1 : 0, j = col - hb * Nv;
-        const cx<RQ>* qj = Q + (long)j * qstride;
         if (kind == 0) {
-          cx<double> psi[6], hy[6];
+          cx<T> psi[6], hy[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) psi[c] = qs[xs][6 * hb + c][j];
+          herm_mv(&hs[xs][36 * hb], 1, psi, hy);
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
-            const cx<RQ> v = qj[fidx(g, B, sx, 12) + (long)(6 * hb + c) * TILE];
-            psi[c] = mk<double>(v.re, v.im);
-          }
-          herm_mv(H + fidx(g, B, sx, 72) + 36L * hb * TILE, TILE, psi, hy);
-#pragma unroll
-          for (int c = 0; c < 6; ++c) {
-            y[c] = hb == 0 ? hy[c] : mk(0.0, 0.0);
-            y[6 + c] = hb == 0 ? mk(0.0, 0.0) : hy[c];
+            y[c] = hb == 0 ? hy[c] : mk<T>(0, 0);
+            y[6 + c] = hb == 0 ? mk<T>(0, 0) : hy[c];
           }
         } else {
+          const int sx = kind < 2 ? x0 + xs : face_slot(g, kind - 2, x0 + xs);
           SiteNbr me;
           for (int d = 0; d < 4; ++d) me.bc[d] = bc[d];
           slot_local(g, sx, me.l);
+          // every direction loads (from x itself when its link is not taken), so
+          // that all gathers are in flight together
+          bool take[4];
+          long off[4];
 #pragma unroll
           for (int mu = 0; mu < 4; ++mu) {
-            const bool take = mu < g.ndir && (kind == 1 ? me.l[mu] + 1 < g.b[mu] : mu == kind - 2);
-            if (!take) continue;
-            int By, sy;
-            nbr_of(g, me, mu, +1, By, sy);
-            half_hop(mu, hb, qj + fidx(g, By, sy, 12), U + fidx(g, B, sx, 36) + (long)mu * 9 * TILE, y);
+            take[mu] = mu < g.ndir && (kind == 1 ? me.l[mu] + 1 < g.b[mu] : mu == kind - 2);
+            int By = B, sy = sx;
+            if (take[mu]) nbr_of(g, me, mu, +1, By, sy);
+            off[mu] = (long)j * qstride + fidx(g, By, sy, 12) + (long)(6 * hb) * TILE;
           }
+          cx<RQ> pv[4][6];
+#pragma unroll
+          for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pv[mu][c] = Q[off[mu] + (long)c * TILE];
+          if (take[0]) half_hop<0>(hb, pv[0], us[xs][0], y);
+          if (take[1]) half_hop<1>(hb, pv[1], us[xs][1], y);
+          if (take[2]) half_hop<2>(hb, pv[2], us[xs][2], y);
+          if (take[3]) half_hop<3>(hb, pv[3], us[xs][3], y);
         }
       }
 #pragma unroll
-      for (int c = 0; c < 12; ++c) ys[xs][c][col] = mk<T>((T)y[c].re, (T)y[c].im);
+      for (int c = 0; c < 12; ++c) ys[xs][c][col] = y[c];
     }
     __syncthreads();
     {
