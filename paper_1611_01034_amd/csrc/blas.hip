@@ -427,17 +427,9 @@ void launch_zero_b(long N, cx<R>* x, long cs, int K, hipStream_t st) {
   if (N > 0) hipLaunchKernelGGL(k_zero_b<R>, dim3((N + 255) / 256, K), dim3(256), 0, st, N, x, cs);
 }
 
-// Givens step j of every active column: thread r handles column r.  Scalar
-// arrays per column: H (ldh*m, column-major, leading dimension ldh), cs, sn (m),
-// g (ldh), resid (1).
-__global__ void k_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>* sn, cx<double>* g, int j,
-                           double* resid, int K, const int* act) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= K || (act && !act[r])) return;
-  cx<double>* h = H + (long)r * ldh * m + (long)j * ldh;
-  double* c_ = cs + (long)r * m;
-  cx<double>* s_ = sn + (long)r * m;
-  cx<double>* g_ = g + (long)r * ldh;
+// Givens step j of one column: apply the previous rotations to Hessenberg
+// column j (h = H + j*ldh), form rotation j, update g and the residual estimate.
+__device__ void givens_col(cx<double>* h, double* c_, cx<double>* s_, cx<double>* g_, int j, double* resid) {
   for (int i = 0; i < j; ++i) {
     cx<double> a = h[i], b = h[i + 1];
     h[i] = c_[i] * a + s_[i] * b;
@@ -465,7 +457,18 @@ __global__ void k_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>
   cx<double> gj = g_[j];
   g_[j + 1] = -(conj(s) * gj);
   g_[j] = c * gj;
-  resid[r] = sqrt(norm2(g_[j + 1]));
+  *resid = sqrt(norm2(g_[j + 1]));
+}
+
+// Givens step j of every active column: thread r handles column r.  Scalar
+// arrays per column: H (ldh*m, column-major, leading dimension ldh), cs, sn (m),
+// g (ldh), resid (1).
+__global__ void k_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>* sn, cx<double>* g, int j,
+                           double* resid, int K, const int* act) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= K || (act && !act[r])) return;
+  givens_col(H + (long)r * ldh * m + (long)j * ldh, cs + (long)r * m, sn + (long)r * m, g + (long)r * ldh, j,
+             resid + r);
 }
 void launch_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>* sn, cx<double>* g, int j, double* resid,
                      int K, const int* act, hipStream_t st) {
@@ -504,6 +507,296 @@ __global__ void k_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs
 void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int K, const int* act, hipStream_t st) {
   hipLaunchKernelGGL(k_init_g_b, dim3(K), dim3(64), 0, st, g, ldh, s, scs, K, act);
 }
+
+
+// ---------------------------------------------------------------------------
+// Classical Gram-Schmidt (twice), norm and Givens step of K lock-step Arnoldi
+// processes in four launches.  Grid (nwg, K), column r = blockIdx.y; inactive
+// columns return at once (the last launch zeroes their next basis vector).
+// Every workgroup stores per-workgroup partial sums; the next launch begins by
+// reducing them in every workgroup (fixed order, so results are deterministic
+// and no workgroup waits for another).  Partials alternate between two
+// buffers, pa and pb, each [K][ldh][nwg] complex.  Basis V_0..V_{k-1} at
+// stride ldv, k <= KM <= 32.
+namespace {
+// sum over the wavefront of v[0..NV) (NV a power of two <= 64): lane l ends
+// with the total of v[l % NV] (transposing butterfly: plain xor steps across
+// groups of NV lanes, then steps that each halve the values kept per lane)
+template <int NV, class T>
+__device__ __forceinline__ T wave_transpose_sum(T (&v)[NV], int lane) {
+#pragma unroll
+  for (int o = 32; o >= NV; o >>= 1)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], o, 64);
+#pragma unroll
+  for (int S = NV; S > 1; S >>= 1) {
+    const int o = S >> 1;
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int q = 0; q < S / 2; ++q) {
+      const T lo = v[q], hi = v[q + S / 2];
+      v[q] = (up ? hi : lo) + __shfl_xor(up ? lo : hi, o, 64);
+    }
+  }
+  return v[0];
+}
+
+// this workgroup's sums of acc[0..nval) -> partd[(v/2) * nwg + wg] (as doubles;
+// NW wavefronts, the wavefront totals added in FP64 in wavefront order)
+template <int KM, int NW, class A>
+__device__ __forceinline__ void store_partials(A (&acc)[2 * KM], int nval, double* partd) {
+  __shared__ double red[NW][2 * KM];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const A v = wave_transpose_sum<2 * KM>(acc, lane);
+  if (lane < 2 * KM) red[wv][lane] = (double)v;
+  __syncthreads();
+  if (t < nval) {
+    double sv = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) sv += red[q][t];
+    partd[2 * ((long)(t >> 1) * gridDim.x + blockIdx.x) + (t & 1)] = sv;
+  }
+}
+
+// totals of values v < nval over the nwg partials of the previous launch ->
+// out[v], out[v] = 0 for nval <= v < nout (<= 64).  tpv lanes of one wavefront
+// per value (the largest power of two with tpv * nval <= blockDim, at most 64)
+// sum strided partials with four independent sums, then combine by xor
+// shuffles: a fixed order.  Ends with a barrier.
+__device__ __forceinline__ void reduce_partials(const double* partd, int nval, int nout, int nwg, double* out) {
+  int tpv = 64;
+  while (tpv > 1 && tpv * nval > (int)blockDim.x) tpv >>= 1;
+  const int t = threadIdx.x, v = t / tpv, q = t - v * tpv;
+  double x = 0.0;
+  if (v < nval) {
+    const double* p = partd + 2L * (v >> 1) * nwg + (v & 1);
+    double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+    int w = q;
+    for (; w + 3 * tpv < nwg; w += 4 * tpv) {
+      x += p[2L * w];
+      x1 += p[2L * (w + tpv)];
+      x2 += p[2L * (w + 2 * tpv)];
+      x3 += p[2L * (w + 3 * tpv)];
+    }
+    for (; w < nwg; w += tpv) x += p[2L * w];
+    x = (x + x1) + (x2 + x3);
+  }
+  for (int o = 1; o < tpv; o <<= 1) x += __shfl_xor(x, o, 64);
+  if (v < nval && q == 0) out[v] = x;
+  for (int z = nval + t; z < nout; z += blockDim.x) out[z] = 0.0;
+  __syncthreads();
+}
+}  // namespace
+
+// Per-thread sums and the updates w -= sum_i c_i V_i are in R (FP32 for FP32
+// vectors; the coefficients are rounded to R), every sum across threads in FP64
+// from the wavefront totals on.
+// pa_r: partials of V_{r,i}^H w_r  (i < k)
+template <class R, int KM, int BS>
+__global__ void __launch_bounds__(BS) k_cgs_dot(const cx<R>* __restrict__ V, long ldv, long csV, int k,
+                                                const cx<R>* __restrict__ w, long csw, long N, double* pa,
+                                                long pcs, const int* act) {
+  const int r = blockIdx.y;
+  if (act && !act[r]) return;
+  V += r * csV;
+  w += r * csw;
+  R acc[2 * KM];
+#pragma unroll
+  for (int q = 0; q < 2 * KM; ++q) acc[q] = R(0);
+  const long stride = (long)gridDim.x * BS;
+  for (long e = (long)blockIdx.x * BS + threadIdx.x; e < N; e += stride) {
+    const cx<R> x = w[e];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {  // every load issued (index clamped); sums past k unused
+      const cx<R> v = V[(long)min(i, k - 1) * ldv + e];
+      acc[2 * i] += v.re * x.re + v.im * x.im;
+      acc[2 * i + 1] += v.re * x.im - v.im * x.re;
+    }
+  }
+  store_partials<KM, BS / 64>(acc, 2 * k, pa + 2 * r * pcs);
+}
+
+// h_r = sum of pa_r (workgroup 0 stores it in hcol_r);  w_r -= sum_i h_r[i] V_{r,i};
+// pb_r: partials of V_{r,i}^H w_r
+template <class R, int KM, int BS>
+__global__ void __launch_bounds__(BS) k_cgs_axpy_dot(const cx<R>* __restrict__ V, long ldv, long csV, int k,
+                                                     cx<R>* w, long csw, long N, const double* pa, double* pb,
+                                                     long pcs, cx<double>* hcol, long hcs, const int* act) {
+  const int r = blockIdx.y;
+  if (act && !act[r]) return;
+  V += r * csV;
+  w += r * csw;
+  __shared__ double cf[2 * KM];
+  __shared__ cx<R> cfr[KM];
+  reduce_partials(pa + 2 * r * pcs, 2 * k, 2 * KM, gridDim.x, cf);
+  if (blockIdx.x == 0 && threadIdx.x < 2 * k) reinterpret_cast<double*>(hcol + r * hcs)[threadIdx.x] = cf[threadIdx.x];
+  if (threadIdx.x < KM) cfr[threadIdx.x] = mk<R>((R)cf[2 * threadIdx.x], (R)cf[2 * threadIdx.x + 1]);
+  __syncthreads();
+  R acc[2 * KM];
+#pragma unroll
+  for (int q = 0; q < 2 * KM; ++q) acc[q] = R(0);
+  const long stride = (long)gridDim.x * BS;
+  for (long e = (long)blockIdx.x * BS + threadIdx.x; e < N; e += stride) {
+    const cx<R> x0 = w[e];
+    cx<R> s = mk<R>(0, 0);
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {  // coefficients past k are zero
+      const cx<R> v = V[(long)min(i, k - 1) * ldv + e];
+      cmac(s, cfr[i], v);
+    }
+    const cx<R> x = mk<R>(x0.re - s.re, x0.im - s.im);
+    w[e] = x;
+    // reload the basis entries (cache hits) rather than hold KM of them in registers
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+      const cx<R> v = V[(long)min(i, k - 1) * ldv + e];
+      acc[2 * i] += v.re * x.re + v.im * x.im;
+      acc[2 * i + 1] += v.re * x.im - v.im * x.re;
+    }
+  }
+  store_partials<KM, BS / 64>(acc, 2 * k, pb + 2 * r * pcs);
+}
+
+// c_r = sum of pb_r (workgroup 0: hcol_r += c_r);  w_r -= sum_i c_r[i] V_{r,i};
+// pa_r: partials of ||w_r||^2
+template <class R, int KM, int BS>
+__global__ void __launch_bounds__(BS) k_cgs_axpy_norm(const cx<R>* __restrict__ V, long ldv, long csV, int k,
+                                                      cx<R>* w, long csw, long N, const double* pb, double* pa,
+                                                      long pcs, cx<double>* hcol, long hcs, const int* act) {
+  const int r = blockIdx.y;
+  if (act && !act[r]) return;
+  V += r * csV;
+  w += r * csw;
+  __shared__ double cf[2 * KM];
+  __shared__ cx<R> cfr[KM];
+  reduce_partials(pb + 2 * r * pcs, 2 * k, 2 * KM, gridDim.x, cf);
+  if (blockIdx.x == 0 && threadIdx.x < 2 * k) reinterpret_cast<double*>(hcol + r * hcs)[threadIdx.x] += cf[threadIdx.x];
+  if (threadIdx.x < KM) cfr[threadIdx.x] = mk<R>((R)cf[2 * threadIdx.x], (R)cf[2 * threadIdx.x + 1]);
+  __syncthreads();
+  R acc[2] = {R(0), R(0)};
+  const long stride = (long)gridDim.x * BS;
+  for (long e = (long)blockIdx.x * BS + threadIdx.x; e < N; e += stride) {
+    const cx<R> x0 = w[e];
+    cx<R> s = mk<R>(0, 0);
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {  // coefficients past k are zero
+      const cx<R> v = V[(long)min(i, k - 1) * ldv + e];
+      cmac(s, cfr[i], v);
+    }
+    const cx<R> x = mk<R>(x0.re - s.re, x0.im - s.im);
+    w[e] = x;
+    acc[0] += x.re * x.re + x.im * x.im;
+  }
+  store_partials<1, BS / 64>(acc, 1, pa + 2 * r * pcs);
+}
+
+// ||w_r|| from pa_r; workgroup 0 stores it as H_r[j+1][j] and takes Givens
+// step j (column j, rotations and g staged in LDS); every workgroup scales its
+// part of w_r by 1/||w_r|| (w_r zeroed for an inactive column)
+template <class R, int BS>
+__global__ void __launch_bounds__(BS) k_cgs_scale_givens(cx<R>* w, long csw, long N, const double* pa, long pcs,
+                                                          cx<double>* H, int ldh, int m, double* cs, cx<double>* sn,
+                                                          cx<double>* g, int j, double* resid, const int* act) {
+  const int r = blockIdx.y;
+  const long stride = (long)gridDim.x * BS;
+  w += r * csw;
+  if (act && !act[r]) {
+    for (long e = (long)blockIdx.x * BS + threadIdx.x; e < N; e += stride) w[e] = mk<R>(0, 0);
+    return;
+  }
+  __shared__ double nn[1];
+  reduce_partials(pa + 2 * r * pcs, 1, 1, gridDim.x, nn);
+  const double nv = sqrt(nn[0] > 0 ? nn[0] : 0.0);
+  if (blockIdx.x == 0) {
+    __shared__ cx<double> hl[64], sl[64], gl[64];
+    __shared__ double cl[64];
+    cx<double>* h = H + (long)r * ldh * m + (long)j * ldh;
+    const int t = threadIdx.x;
+    if (t <= j) {
+      hl[t] = h[t];
+      if (t < j) {
+        cl[t] = cs[(long)r * m + t];
+        sl[t] = sn[(long)r * m + t];
+      }
+    }
+    if (t == 0) {
+      hl[j + 1] = mk(nv, 0.0);
+      gl[j] = g[(long)r * ldh + j];
+    }
+    __syncthreads();
+    if (t == 0) {
+      givens_col(hl, cl, sl, gl, j, resid + r);
+      // rotation j and the new g entries are the only state kept besides H
+      cs[(long)r * m + j] = cl[j];
+      sn[(long)r * m + j] = sl[j];
+      g[(long)r * ldh + j] = gl[j];
+      g[(long)r * ldh + j + 1] = gl[j + 1];
+    }
+    __syncthreads();
+    if (t <= j + 1) h[t] = hl[t];
+  }
+  const double f = nv > 0 ? 1.0 / nv : 0.0;
+  for (long e = (long)blockIdx.x * BS + threadIdx.x; e < N; e += stride) {
+    const cx<R> x = w[e];
+    w[e] = mk<R>((R)(f * x.re), (R)(f * x.im));
+  }
+}
+
+template <class R, int BS>
+static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, double* a, double* b,
+                        long pcs, int nwg, cx<double>* hcol, long hcs, cx<double>* H, int ldh, int m, double* cs,
+                        cx<double>* sn, cx<double>* g, int j, double* resid, int K, const int* act, hipStream_t st) {
+  const dim3 grid(nwg, K), blk(BS);
+  // the axpy kernels of 16 or more vectors hold twice the registers: half the
+  // threads per workgroup (same workgroup count, so the partials match)
+#define CGS_LAUNCH(KM)                                                                                                 \
+  {                                                                                                                    \
+    constexpr int BA = (BS == 1024 && KM >= 16) ? 512 : BS;                                                            \
+    hipLaunchKernelGGL((k_cgs_dot<R, KM, BS>), grid, blk, 0, st, V, ldv, csV, k, (const cx<R>*)w, csw, N, a, pcs,     \
+                       act);                                                                                           \
+    hipLaunchKernelGGL((k_cgs_axpy_dot<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,                 \
+                       (const double*)a, b, pcs, hcol, hcs, act);                                                      \
+    hipLaunchKernelGGL((k_cgs_axpy_norm<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,                \
+                       (const double*)b, a, pcs, hcol, hcs, act);                                                      \
+  }
+  if (k <= 8) {
+    CGS_LAUNCH(8)
+  } else if (k <= 16) {
+    CGS_LAUNCH(16)
+  } else {
+    CGS_LAUNCH(32)
+  }
+#undef CGS_LAUNCH
+  hipLaunchKernelGGL((k_cgs_scale_givens<R, BS>), grid, blk, 0, st, w, csw, N, (const double*)a, pcs, H, ldh, m, cs,
+                     sn, g, j, resid, act);
+}
+
+// FP32 vectors: 1024-thread workgroups with FP32 per-thread sums (at most 128
+// registers); FP64 vectors: 256-thread workgroups
+template <class R>
+int cgs_block_size() {
+  return sizeof(R) == 4 ? 1024 : 256;
+}
+template <class R>
+void launch_cgs_step(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, cx<double>* pa,
+                     cx<double>* pb, long pcs, int nwg, cx<double>* hcol, long hcs, cx<double>* H, int ldh, int m,
+                     double* cs, cx<double>* sn, cx<double>* g, int j, double* resid, int K, const int* act,
+                     hipStream_t st) {
+  double* a = reinterpret_cast<double*>(pa);
+  double* b = reinterpret_cast<double*>(pb);
+  if constexpr (sizeof(R) == 4)
+    cgs_step_bs<R, 1024>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, K, act, st);
+  else
+    cgs_step_bs<R, 256>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, K, act, st);
+}
+#define INST_CGS(R)                                                                                             \
+  template int cgs_block_size<R>();                                                                               \
+  template void launch_cgs_step<R>(const cx<R>*, long, long, int, cx<R>*, long, long, cx<double>*, cx<double>*,   \
+                                   long, int, cx<double>*, long, cx<double>*, int, int, double*, cx<double>*,     \
+                                   cx<double>*, int, double*, int, const int*, hipStream_t);
+INST_CGS(double)
+INST_CGS(float)
 
 #define INST_BB(R)                                                                                                  \
   template void launch_multidot_b<R>(const cx<R>*, long, long, int, const cx<R>*, long, long, cx<double>*, long,   \

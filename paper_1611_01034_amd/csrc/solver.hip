@@ -281,6 +281,16 @@ KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(co
 // meets its tolerance drops out of the reductions and its next basis vector is
 // zeroed, so nested solves see a zero right-hand side for it.  The iterates are
 // those of K separate solves in exact arithmetic.
+// workgroups per column of the fused Arnoldi step: about one element per
+// thread of an FP32 vector (at most 128 workgroups, so every workgroup's
+// prologue sums few partials), four per thread of an FP64 one (at most 1024)
+template <class R>
+static int cgs_nwg(long N) {
+  const long per = sizeof(R) == 4 ? cgs_block_size<R>() : 4L * cgs_block_size<R>();
+  const long cap = sizeof(R) == 4 ? 128 : 1024;
+  return (int)std::min<long>(cap, std::max<long>(1, (N + per - 1) / per));
+}
+
 template <class R>
 void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex) {
   m = m_;
@@ -296,7 +306,8 @@ void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex) {
   g.ensure(sizeof(cx<double>) * (m + 1) * K);
   y.ensure(sizeof(cx<double>) * (m + 1) * K);
   nwg = (int)std::min<long>(256, std::max<long>(1, (N + 255) / 256));
-  part.ensure(sizeof(cx<double>) * (size_t)nwg * (m + 1) * K);
+  nwgf = cgs_nwg<R>(N);
+  part.ensure(sizeof(cx<double>) * (size_t)std::max(nwg, nwgf) * (m + 1) * K * 2);  // two halves for the fused step
   scal.ensure(sizeof(cx<double>) * 4 * K);
   resid.ensure(sizeof(double) * K);
   act.ensure(sizeof(int) * K);
@@ -332,7 +343,8 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
   const int m = ws.m, ldh = m + 1;
   const long ld = ws.ld, hcs = (long)ldh * m;
   const int nwg = (int)std::min<long>(ws.nwg, std::max<long>(1, (N + 255) / 256));
-  const long pcs = (long)nwg * ldh;
+  const int nwgf = std::min(ws.nwgf, cgs_nwg<R>(N));  // fused Arnoldi launches
+  const long pcs = (long)std::max(ws.nwg, ws.nwgf) * ldh;
   cx<R>* V = ws.V.template as<cx<R>>();
   cx<R>* Z = M ? ws.Z.template as<cx<R>>() : V;
   cx<R>* r = ws.r.template as<cx<R>>();
@@ -413,18 +425,25 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
       }
       A(z, Vn, K);
       cx<double>* hcol = H + (long)j * ldh;
-      launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
-      launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 0, K, act, st);
-      launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, hcol, hcs, -1.0, Vn, ld, N, K, act, st);
-      launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
-      launch_reduce_b(part, pcs, j + 1, nwg, y, ldh, 0, K, act, st);
-      launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 1, K, act, st);
-      launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, y, ldh, -1.0, Vn, ld, N, K, act, st);
-      launch_multidot_b<R>(Vn, 0, ld, 1, Vn, ld, N, part, pcs, nwg, K, act, st);
-      launch_reduce_b(part, pcs, 1, nwg, hcol + j + 1, hcs, 2, K, act, st);
-      launch_scale_by_inv_b<R>(Vn, ld, hcol + j + 1, hcs, Vn, ld, N, K, act, 1, st);
-      launch_givens_b(H, ldh, m, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), g, j,
-                      ws.resid.template as<double>(), K, act, st);
+      if (j + 1 <= 32) {
+        // classical Gram-Schmidt twice, norm, scaling and Givens step in four launches
+        launch_cgs_step<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, part + (long)K * pcs, pcs, nwgf, hcol, hcs, H,
+                           ldh, m, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), g, j,
+                           ws.resid.template as<double>(), K, act, st);
+      } else {
+        launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
+        launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 0, K, act, st);
+        launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, hcol, hcs, -1.0, Vn, ld, N, K, act, st);
+        launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
+        launch_reduce_b(part, pcs, j + 1, nwg, y, ldh, 0, K, act, st);
+        launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 1, K, act, st);
+        launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, y, ldh, -1.0, Vn, ld, N, K, act, st);
+        launch_multidot_b<R>(Vn, 0, ld, 1, Vn, ld, N, part, pcs, nwg, K, act, st);
+        launch_reduce_b(part, pcs, 1, nwg, hcol + j + 1, hcs, 2, K, act, st);
+        launch_scale_by_inv_b<R>(Vn, ld, hcol + j + 1, hcs, Vn, ld, N, K, act, 1, st);
+        launch_givens_b(H, ldh, m, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), g, j,
+                        ws.resid.template as<double>(), K, act, st);
+      }
       ++steps;
       int still = 0;
       for (int k = 0; k < K; ++k)

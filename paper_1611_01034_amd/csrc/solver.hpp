@@ -91,6 +91,7 @@ struct KrylovWSm {
   DevBuf V, Z, r, H, cs, sn, g, y, part, scal, resid, act, jd;
   double* h_resid = nullptr;   // pinned: K residual estimates (two slots of 32 for the look-ahead)
   hipEvent_t ready[2] = {nullptr, nullptr};
+  int nwgf = 0;                  // workgroups per column of the fused Arnoldi step
   cx<double>* h_scal = nullptr;  // pinned: K x 4 scalars
   int* h_act = nullptr;        // pinned: K flags (host copy)
   int* h_act_ring = nullptr;   // pinned: 4 x 16 staging slots for the asynchronous pushes of h_act
