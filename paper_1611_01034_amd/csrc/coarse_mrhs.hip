@@ -109,46 +109,64 @@ __device__ __forceinline__ typename mm16<S>::frag a_frag_bwd(const typename stor
 
 // acc[u] += sum over the selected blocks, output rows 16t..16t+15, columns 16u..
 //   self: S(site) xs(site);  hops: hs * (forward + backward hops of xh)
-template <class S, int NT>
+// RT = n / 16 k-steps per block.  For one column tile every fragment of a block
+// is loaded before its products and two blocks are in flight, so a wavefront
+// waits on about one memory latency per two blocks.
+template <class S, int NT, int RT>
 __device__ __forceinline__ void stencil_mfma(const CGeom& cg, const typename store_traits<S>::elem* D, int site,
                                              int t, const cx<float>* xs, const cx<float>* xh, float hs, int K,
                                              long ldv, int lane, v4f acc[NT]) {
-  const int n = cg.n, RT = n >> 4, h = n >> 1;
-  const long nn = (long)n * n;
+  constexpr int n = 16 * RT, h = n / 2;
+  constexpr long nn = (long)n * n;
   const int row = lane & 15, grp = lane >> 4;
-#pragma unroll 1
+  const int i = 16 * t + row;
+#pragma unroll(NT == 1 ? 2 : 1)
   for (int b = xs ? 0 : 1; b < (xh ? 9 : 1); ++b) {
     const typename store_traits<S>::elem* blk;
     const cx<float>* x;
     float sgn = 1.0f;
-    bool bwd = b >= 5;
+    const bool bwd = b >= 5;
     if (b == 0) {
       blk = D + (long)site * 5 * nn;
       x = xs + (long)site * n;
     } else if (!bwd) {
-      int mu = b - 1;
+      const int mu = b - 1;
       blk = D + ((long)site * 5 + 1 + mu) * nn;
       x = xh + (long)cg.nbr[site * 8 + mu] * n;
       sgn = hs;
     } else {
-      int mu = b - 5;
-      int cb = cg.nbr[site * 8 + 4 + mu];
+      const int mu = b - 5;
+      const int cb = cg.nbr[site * 8 + 4 + mu];
       blk = D + ((long)cb * 5 + 1 + mu) * nn;
       x = xh + (long)cb * n;
       sgn = hs;
     }
+    if constexpr (NT == 1) {
+      typename mm16<S>::frag af[RT], bf[RT];
+#pragma unroll
+      for (int s = 0; s < RT; ++s) {
+        const int lc = 16 * s + 4 * grp;
+        // g_l of the backward block goes on the input (lc..lc+3 lie in one half)
+        const float gs = bwd ? (lc < h ? -sgn : sgn) : sgn;
+        bf[s] = b_frag<S>(x, ldv, K, row, lc, gs);
+        af[s] = bwd ? a_frag_bwd<S>(blk, n, i, lc, i < h) : a_frag_col<S>(blk, n, i, lc);
+      }
+#pragma unroll
+      for (int s = 0; s < RT; ++s) acc[0] = mm16<S>::mma(af[s], bf[s], acc[0]);
+    } else {
+      // two column tiles: one k-step at a time keeps the registers (and the
+      // occupancy) of the wider products
 #pragma unroll 1
-    for (int s = 0; s < RT; ++s) {
-      const int lc = 16 * s + 4 * grp;
-      // g_l of the backward block goes on the input (lc..lc+3 lie in one half)
-      const float gs = bwd ? (lc < h ? -sgn : sgn) : sgn;
-      typename mm16<S>::frag bf[NT];
+      for (int s = 0; s < RT; ++s) {
+        const int lc = 16 * s + 4 * grp;
+        const float gs = bwd ? (lc < h ? -sgn : sgn) : sgn;
+        typename mm16<S>::frag bf[NT];
 #pragma unroll
-      for (int u = 0; u < NT; ++u) bf[u] = b_frag<S>(x, ldv, K, 16 * u + row, lc, gs);
-      const int i = 16 * t + row;
-      typename mm16<S>::frag af = bwd ? a_frag_bwd<S>(blk, n, i, lc, i < h) : a_frag_col<S>(blk, n, i, lc);
+        for (int u = 0; u < NT; ++u) bf[u] = b_frag<S>(x, ldv, K, 16 * u + row, lc, gs);
+        const typename mm16<S>::frag af = bwd ? a_frag_bwd<S>(blk, n, i, lc, i < h) : a_frag_col<S>(blk, n, i, lc);
 #pragma unroll
-      for (int u = 0; u < NT; ++u) acc[u] = mm16<S>::mma(af, bf[u], acc[u]);
+        for (int u = 0; u < NT; ++u) acc[u] = mm16<S>::mma(af, bf[u], acc[u]);
+      }
     }
   }
 }
@@ -191,7 +209,7 @@ __device__ __forceinline__ void store_mfma(const CGeom& cg, int site, int t, v4f
 }
 
 // y_r = D x_r (b == null) or y_r = b_r - D x_r, all sites
-template <class S, int NT>
+template <class S, int NT, int RT>
 __global__ void __launch_bounds__(256) k_coarse_apply_mrhs(CGeom cg, const typename store_traits<S>::elem* __restrict__ D,
                                                            float tw, int K, long ldv, const cx<float>* __restrict__ x,
                                                            const cx<float>* __restrict__ b, cx<float>* __restrict__ y) {
@@ -199,13 +217,13 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mrhs(CGeom cg, const typen
   const int site = blockIdx.x;
   v4f acc[NT];
   zero_acc<NT>(acc);
-  stencil_mfma<S, NT>(cg, D, site, t, x, x, 1.0f, K, ldv, lane, acc);
+  stencil_mfma<S, NT, RT>(cg, D, site, t, x, x, 1.0f, K, ldv, lane, acc);
   store_mfma<NT>(cg, site, t, acc, tw, x, b, -1.0f, K, ldv, lane, y);
 }
 
 // even sites of the odd-even reduced system: mode 0: y = (S + i tw G5) v - H t;
 // mode 1: y = v - H t   (H: the hops, t lives on the odd sites)
-template <class S, int NT>
+template <class S, int NT, int RT>
 __global__ void __launch_bounds__(256) k_coarse_schur_even_mrhs(CGeom cg,
                                                                 const typename store_traits<S>::elem* __restrict__ D,
                                                                 float tw, int K, long ldv,
@@ -216,7 +234,7 @@ __global__ void __launch_bounds__(256) k_coarse_schur_even_mrhs(CGeom cg,
   const int site = blockIdx.x;
   v4f acc[NT];
   zero_acc<NT>(acc);
-  stencil_mfma<S, NT>(cg, D, site, rt, mode == 0 ? v : nullptr, t, -1.0f, K, ldv, lane, acc);
+  stencil_mfma<S, NT, RT>(cg, D, site, rt, mode == 0 ? v : nullptr, t, -1.0f, K, ldv, lane, acc);
   if (mode == 0) store_mfma<NT>(cg, site, rt, acc, tw, v, nullptr, 1.0f, K, ldv, lane, y);
   else store_mfma<NT>(cg, site, rt, acc, 0.0f, nullptr, v, 1.0f, K, ldv, lane, y);
 }
@@ -224,23 +242,26 @@ __global__ void __launch_bounds__(256) k_coarse_schur_even_mrhs(CGeom cg,
 // odd sites: y = Minv H x, or y = Minv (base - H x) with base.  Minv:
 // [odd site][n][n] FP32 column-major.  The hop result goes through LDS
 // ([n][16] complex) to the FP32 products with Minv, which all threads of the
-// workgroup share: thread -> row i = tid % n, columns r = tid / n + 4 q.
-template <class S, int NT>
+// workgroup share: thread -> row i = tid % n and a quarter g = tid / n of the
+// inner index (16 terms, all loads in flight), the four partial sums added in
+// LDS in fixed order.
+template <class S, int NT, int RT>
 __global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
                                                                  const typename store_traits<S>::elem* __restrict__ D,
                                                                  const cx<float>* __restrict__ Minv, int K, long ldv,
                                                                  const cx<float>* __restrict__ x,
                                                                  const cx<float>* __restrict__ base,
                                                                  cx<float>* __restrict__ y) {
+  constexpr int n = 16 * RT, LQ = n / 4;
   __shared__ cx<float> us[64 * 16];
+  __shared__ cx<float> ps[4][64 * 16];
   const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
   const int io = blockIdx.x;
   const int site = cg.neven + io;
-  const int n = cg.n;
   {
     v4f acc[NT];
     zero_acc<NT>(acc);
-    stencil_mfma<S, NT>(cg, D, site, rt, nullptr, x, 1.0f, K, ldv, lane, acc);
+    stencil_mfma<S, NT, RT>(cg, D, site, rt, nullptr, x, 1.0f, K, ldv, lane, acc);
     const int col = lane & 15, grp = lane >> 4;
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
@@ -256,33 +277,55 @@ __global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
     }
   }
   __syncthreads();
-  const int i = threadIdx.x % n, r0 = threadIdx.x / n;  // r0 < 4 (blockDim = 4 n)
+  const int i = threadIdx.x % n, gq = threadIdx.x / n;  // gq < 4 (blockDim = 4 n)
   const cx<float>* M = Minv + (long)io * n * n;
-  cx<float> out[4];
+  cx<float> m[LQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) out[q] = mk<float>(0, 0);
-  for (int l = 0; l < n; ++l) {
-    cx<float> m = M[(long)l * n + i];
+  for (int l = 0; l < LQ; ++l) m[l] = M[(long)(gq * LQ + l) * n + i];
+  for (int r = 0; r < K; ++r) {
+    cx<float> o = mk<float>(0, 0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (r0 + 4 * q < K) cmac(out[q], m, us[l * 16 + r0 + 4 * q]);
+    for (int l = 0; l < LQ; ++l) cmac(o, m[l], us[(gq * LQ + l) * 16 + r]);
+    ps[gq][i * 16 + r] = o;
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (r0 + 4 * q < K) y[(long)(r0 + 4 * q) * ldv + (long)site * n + i] = out[q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
+    const int ii = e % n, r = e / n;
+    const cx<float> o = (ps[0][ii * 16 + r] + ps[1][ii * 16 + r]) + (ps[2][ii * 16 + r] + ps[3][ii * 16 + r]);
+    y[(long)r * ldv + (long)site * n + ii] = o;
+  }
 }
 
 static inline int nt_of(int K) { return K <= 8 ? 1 : 2; }
+
+// instantiate KERNEL<S, NT, RT> for NT = nt_of(K), RT = n / 16
+#define MRHS_DISPATCH(KERNEL, ...)                                                   \
+  do {                                                                               \
+    const int nt = nt_of(K), rt = cg.n / 16;                                         \
+    if (cg.n % 16 || rt < 1 || rt > 4) throw Error(INVALID_ARG, "coarse n must be 16, 32, 48 or 64"); \
+    if (nt == 1) {                                                                   \
+      switch (rt) {                                                                  \
+        case 1: hipLaunchKernelGGL((KERNEL<S, 1, 1>), __VA_ARGS__); break;           \
+        case 2: hipLaunchKernelGGL((KERNEL<S, 1, 2>), __VA_ARGS__); break;           \
+        case 3: hipLaunchKernelGGL((KERNEL<S, 1, 3>), __VA_ARGS__); break;           \
+        default: hipLaunchKernelGGL((KERNEL<S, 1, 4>), __VA_ARGS__); break;          \
+      }                                                                              \
+    } else {                                                                         \
+      switch (rt) {                                                                  \
+        case 1: hipLaunchKernelGGL((KERNEL<S, 2, 1>), __VA_ARGS__); break;           \
+        case 2: hipLaunchKernelGGL((KERNEL<S, 2, 2>), __VA_ARGS__); break;           \
+        case 3: hipLaunchKernelGGL((KERNEL<S, 2, 3>), __VA_ARGS__); break;           \
+        default: hipLaunchKernelGGL((KERNEL<S, 2, 4>), __VA_ARGS__); break;          \
+      }                                                                              \
+    }                                                                                \
+  } while (0)
 
 template <class S>
 void launch_coarse_apply_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* x,
                               const cx<float>* b, cx<float>* y, hipStream_t st) {
   dim3 grid(cg.nsites), blk(4 * cg.n);
   auto Dp = (const typename store_traits<S>::elem*)D;
-  if (nt_of(K) == 1)
-    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 1>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
-  else
-    hipLaunchKernelGGL((k_coarse_apply_mrhs<S, 2>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
+  MRHS_DISPATCH(k_coarse_apply_mrhs, grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
 }
 
 template <class S>
@@ -290,10 +333,7 @@ void launch_coarse_schur_even_mrhs(const CGeom& cg, const void* D, double tw, in
                                    const cx<float>* t, cx<float>* y, int mode, hipStream_t st) {
   dim3 grid(cg.neven), blk(4 * cg.n);
   auto Dp = (const typename store_traits<S>::elem*)D;
-  if (nt_of(K) == 1)
-    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 1>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, v, t, y, mode);
-  else
-    hipLaunchKernelGGL((k_coarse_schur_even_mrhs<S, 2>), grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, v, t, y, mode);
+  MRHS_DISPATCH(k_coarse_schur_even_mrhs, grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, v, t, y, mode);
 }
 
 template <class S>
@@ -302,10 +342,7 @@ void launch_coarse_hop_inv_odd_mrhs(const CGeom& cg, const void* D, const cx<flo
   int nodd = cg.nsites - cg.neven;
   dim3 grid(nodd), blk(4 * cg.n);
   auto Dp = (const typename store_traits<S>::elem*)D;
-  if (nt_of(K) == 1)
-    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 1>), grid, blk, 0, st, cg, Dp, Minv, K, ldv, x, base, y);
-  else
-    hipLaunchKernelGGL((k_coarse_hop_inv_odd_mrhs<S, 2>), grid, blk, 0, st, cg, Dp, Minv, K, ldv, x, base, y);
+  MRHS_DISPATCH(k_coarse_hop_inv_odd_mrhs, grid, blk, 0, st, cg, Dp, Minv, K, ldv, x, base, y);
 }
 
 #define INST_MRHS(S)                                                                                              \

@@ -1277,9 +1277,17 @@ struct MG : MGBase {
     permute<double, R>(G.n, G.nsites, G.d_order.template as<int>(), s, dst, 1, c.st);
   }
 
+  // SAP smoothing of K fields of level l (zero right-hand sides b)
+  void smooth_level_m(int l, const cx<R>* b, cx<R>* x, int K, int iters) {
+    if (l == 0) fine_sap_m(b, x, K, iters, p.mr_steps);
+    else coarse_sap_m(l, b, x, K, iters);
+  }
+
   void build(const void* const* vecs, int on_device, bool run_setup) override {
     for (int l = 0; l < L - 1; ++l) {
       long len = level_len(l);
+      const bool smooth = run_setup && p.init_sap_iters > 0;
+      const bool batched = smooth && p.batch > 1;
       for (int i = 0; i < Nv[l]; ++i) {
         cx<R>* vi = Vraw[l].template as<cx<R>>() + (long)i * len;
         if (l == 0 && fine_loaded) {
@@ -1288,10 +1296,27 @@ struct MG : MGBase {
           const char* src = (const char*)vecs[l] + sizeof(cx<double>) * (size_t)len * i;
           upload_vec(l, src, on_device, vi);
         }
-        if (run_setup && p.init_sap_iters > 0) {
+        if (smooth && !batched) {
           launch_zero<R>(len, setup_zero(l), c.st);
           smooth_level(l, setup_zero(l), vi, p.init_sap_iters);
         }
+      }
+      if (batched) {
+        // the initial smoothing of chunks of p.batch test vectors in one
+        // K-field SAP (every field takes the arithmetic of a one-field sweep)
+        const int K = std::min(p.batch, Nv[l]);
+        ensure_multi(K);
+        cx<R>* zb;
+        if (l == 0) {
+          fxm.ensure(sizeof(cx<R>) * len * K);
+          zb = fxm.template as<cx<R>>();
+        } else {
+          zb = ecm[l].template as<cx<R>>();
+        }
+        launch_zero<R>(len * K, zb, c.st);
+        for (int i0 = 0; i0 < Nv[l]; i0 += K)
+          smooth_level_m(l, zb, Vraw[l].template as<cx<R>>() + (long)i0 * len, std::min(K, Nv[l] - i0),
+                         p.init_sap_iters);
       }
       build_next(l);
     }
