@@ -519,28 +519,6 @@ void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int 
 // buffers, pa and pb, each [K][ldh][nwg] complex.  Basis V_0..V_{k-1} at
 // stride ldv, k <= KM <= 32.
 namespace {
-// sum over the wavefront of v[0..NV) (NV a power of two <= 64): lane l ends
-// with the total of v[l % NV] (transposing butterfly: plain xor steps across
-// groups of NV lanes, then steps that each halve the values kept per lane)
-template <int NV, class T>
-__device__ __forceinline__ T wave_transpose_sum(T (&v)[NV], int lane) {
-#pragma unroll
-  for (int o = 32; o >= NV; o >>= 1)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], o, 64);
-#pragma unroll
-  for (int S = NV; S > 1; S >>= 1) {
-    const int o = S >> 1;
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int q = 0; q < S / 2; ++q) {
-      const T lo = v[q], hi = v[q + S / 2];
-      v[q] = (up ? hi : lo) + __shfl_xor(up ? lo : hi, o, 64);
-    }
-  }
-  return v[0];
-}
-
 // this workgroup's sums of acc[0..nval) -> partd[(v/2) * nwg + wg] (as doubles;
 // NW wavefronts, the wavefront totals added in FP64 in wavefront order)
 template <int KM, int NW, class A>

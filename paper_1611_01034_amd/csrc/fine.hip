@@ -599,6 +599,136 @@ template void launch_prolong_fine<double>(const Geom&, int, const cx<double>*, l
 template void launch_prolong_fine<float>(const Geom&, int, const cx<float>*, long, const cx<float>*, const int*,
                                          cx<float>*, int, hipStream_t);
 
+// K-column restriction: one thread per slot (threads past the block's slots
+// contribute zero), columns in groups of KC whose inputs stay in registers, test
+// vectors in groups of four, so Q is read once per group of columns.  The 16 KC
+// values (vector, column, half, re/im) of a group are summed over the wavefront
+// by a transposing butterfly and over the wavefronts in LDS in fixed order.
+template <class R, int KC>
+__global__ void __launch_bounds__(256) k_restrict_fine_m(Geom g, int Nv, const cx<R>* __restrict__ Q, long vstride,
+                                                         const cx<R>* __restrict__ r, long rld, int K,
+                                                         const int* __restrict__ f2c, cx<R>* __restrict__ rc,
+                                                         long cld) {
+  constexpr int NVAL = 16 * KC;
+  __shared__ R red[4][NVAL];
+  const int B = blockIdx.x, s = threadIdx.x, lane = s & 63, wv = s >> 6, nw = blockDim.x >> 6;
+  const bool live = s < g.bs;
+  const long site = f2c[B];
+  const long base = live ? fidx(g, B, s, 12) : 0;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    cx<R> rv[KC][12];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int c = 0; c < 12; ++c)
+        rv[kk][c] = live && k0 + kk < K ? r[(long)(k0 + kk) * rld + base + (long)c * TILE] : mk<R>(0, 0);
+    for (int i0 = 0; i0 < Nv; i0 += 4) {
+      R acc[NVAL];
+#pragma unroll
+      for (int v = 0; v < NVAL; ++v) acc[v] = R(0);
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int i = i0 + ii;
+        if (i < Nv && live) {
+          cx<R> q[12];
+#pragma unroll
+          for (int c = 0; c < 12; ++c) q[c] = Q[(long)i * vstride + base + (long)c * TILE];
+#pragma unroll
+          for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+              const int v = ((ii * KC + kk) * 2 + c / 6) * 2;
+              acc[v] += q[c].re * rv[kk][c].re + q[c].im * rv[kk][c].im;
+              acc[v + 1] += q[c].re * rv[kk][c].im - q[c].im * rv[kk][c].re;
+            }
+        }
+      }
+      const R tot = wave_transpose_sum<NVAL>(acc, lane);
+      if (lane < NVAL) red[wv][lane] = tot;
+      __syncthreads();
+      if (s < NVAL) {
+        R sum = R(0);
+        for (int w = 0; w < nw; ++w) sum += red[w][s];
+        const int p = s & 1, h = (s >> 1) & 1, kk = (s >> 2) % KC, ii = (s >> 2) / KC;
+        const int i = i0 + ii, k = k0 + kk;
+        if (i < Nv && k < K) reinterpret_cast<R*>(rc + (long)k * cld + site * 2 * Nv + h * Nv + i)[p] = sum;
+      }
+      __syncthreads();
+    }
+  }
+}
+template <class R>
+void launch_restrict_fine_m(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* r, long rld, int K,
+                            const int* f2c, cx<R>* rc, long cld, hipStream_t st) {
+  const dim3 grid(g.nblocks), blk(((g.bs + 63) / 64) * 64);
+  if (K == 1)
+    hipLaunchKernelGGL((k_restrict_fine_m<R, 1>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
+  else if (K == 2 || sizeof(R) == 8)
+    hipLaunchKernelGGL((k_restrict_fine_m<R, 2>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
+  else
+    hipLaunchKernelGGL((k_restrict_fine_m<R, 4>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
+}
+template void launch_restrict_fine_m<double>(const Geom&, int, const cx<double>*, long, const cx<double>*, long, int,
+                                             const int*, cx<double>*, long, hipStream_t);
+template void launch_restrict_fine_m<float>(const Geom&, int, const cx<float>*, long, const cx<float>*, long, int,
+                                            const int*, cx<float>*, long, hipStream_t);
+
+// K-column prolongation: x_k (+)= sum_i Q_i e_k, one thread per site, columns in
+// groups of KC accumulated in registers (Q read once per group)
+template <class R, int KC>
+__global__ void __launch_bounds__(256) k_prolong_fine_m(Geom g, int Nv, const cx<R>* __restrict__ Q, long vstride,
+                                                        const cx<R>* __restrict__ ec, long cld, int K,
+                                                        const int* __restrict__ f2c, cx<R>* __restrict__ x, long xld,
+                                                        int accumulate) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  const int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  const cx<R>* e = ec + (long)f2c[B] * 2 * Nv;
+  const long base = fidx(g, B, s, 12);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    cx<R> acc[KC][12];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int c = 0; c < 12; ++c)
+        acc[kk][c] = accumulate && k0 + kk < K ? x[(long)(k0 + kk) * xld + base + (long)c * TILE] : mk<R>(0, 0);
+    for (int i = 0; i < Nv; ++i) {
+      cx<R> q[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) q[c] = Q[(long)i * vstride + base + (long)c * TILE];
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        if (k0 + kk >= K) continue;
+        const cx<R> e0 = e[(long)(k0 + kk) * cld + i], e1 = e[(long)(k0 + kk) * cld + Nv + i];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) cmac(acc[kk][c], q[c], e0);
+#pragma unroll
+        for (int c = 6; c < 12; ++c) cmac(acc[kk][c], q[c], e1);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+      if (k0 + kk < K)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) x[(long)(k0 + kk) * xld + base + (long)c * TILE] = acc[kk][c];
+  }
+}
+template <class R>
+void launch_prolong_fine_m(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* ec, long cld, int K,
+                           const int* f2c, cx<R>* x, long xld, int accumulate, hipStream_t st) {
+  const dim3 grid((unsigned)((g.V + 255) / 256)), blk(256);
+  if (K == 1)
+    hipLaunchKernelGGL((k_prolong_fine_m<R, 1>), grid, blk, 0, st, g, Nv, Q, vstride, ec, cld, K, f2c, x, xld, accumulate);
+  else if (K == 2 || sizeof(R) == 8)
+    hipLaunchKernelGGL((k_prolong_fine_m<R, 2>), grid, blk, 0, st, g, Nv, Q, vstride, ec, cld, K, f2c, x, xld, accumulate);
+  else
+    hipLaunchKernelGGL((k_prolong_fine_m<R, 4>), grid, blk, 0, st, g, Nv, Q, vstride, ec, cld, K, f2c, x, xld, accumulate);
+}
+template void launch_prolong_fine_m<double>(const Geom&, int, const cx<double>*, long, const cx<double>*, long, int,
+                                            const int*, cx<double>*, long, int, hipStream_t);
+template void launch_prolong_fine_m<float>(const Geom&, int, const cx<float>*, long, const cx<float>*, long, int,
+                                           const int*, cx<float>*, long, int, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // block orthonormalisation (classical Gram-Schmidt, twice) per aggregate half,
 // FP64 arithmetic; columns in the order v_1..v_Nv, diag(R) = norms (real > 0).

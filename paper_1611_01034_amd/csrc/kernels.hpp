@@ -18,6 +18,28 @@ __device__ __forceinline__ T wave_sum_n(T v, int nact) {
   }
   return v;
 }
+
+// Sum over the wavefront of v[0..NV) (NV a power of two <= 64): lane l ends
+// with the total of v[l % NV] (transposing butterfly: plain xor steps across
+// groups of NV lanes, then steps that each halve the values kept per lane).
+template <int NV, class T>
+__device__ __forceinline__ T wave_transpose_sum(T (&v)[NV], int lane) {
+#pragma unroll
+  for (int o = 32; o >= NV; o >>= 1)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], o, 64);
+#pragma unroll
+  for (int S = NV; S > 1; S >>= 1) {
+    const int o = S >> 1;
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int q = 0; q < S / 2; ++q) {
+      const T lo = v[q], hi = v[q + S / 2];
+      v[q] = (up ? hi : lo) + __shfl_xor(up ? lo : hi, o, 64);
+    }
+  }
+  return v[0];
+}
 #endif
 
 // coarse-level geometry as seen by the kernels
@@ -47,6 +69,14 @@ void launch_clover_from_lex(const Geom& g, const cx<double>* lex, double diag, d
 void launch_clover_to_lex(const Geom& g, const double* H, double diag, cx<double>* lex, hipStream_t st);
 void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, hipStream_t st);
 void launch_odd_inverse(const Geom& g, const double* H, double tw, double* M, hipStream_t st);
+// K-column forms (column k at in + k*ld_in, out + k*ld_out): Q is read once
+// per group of columns
+template <class R>
+void launch_restrict_fine_m(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* r, long rld, int K,
+                            const int* f2c, cx<R>* rc, long cld, hipStream_t st);
+template <class R>
+void launch_prolong_fine_m(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* ec, long cld, int K,
+                           const int* f2c, cx<R>* x, long xld, int accumulate, hipStream_t st);
 template <class R>
 void launch_restrict_fine(const Geom& g, int Nv, const cx<R>* Q, long vstride, const cx<R>* r, const int* f2c,
                           cx<R>* rc, hipStream_t st);

@@ -1064,17 +1064,23 @@ struct MG : MGBase {
         launch_zero<R>(len * K, x, c.st);
         fine_sap_m(v, x, K, p.sap_pre, p.mr_steps);
       }
-      for (int k = 0; k < K; ++k) {
-        const cx<R>* rin = v + k * len;
-        if (p.sap_pre > 0) {
+      if (p.sap_pre > 0) {
+        for (int k = 0; k < K; ++k) {
           fine_dirac(x + k * len, fr.template as<cx<R>>());
           launch_sub<R>(len, v + k * len, fr.template as<cx<R>>(), fr.template as<cx<R>>(), c.st);
-          rin = fr.template as<cx<R>>();
+          restrict_(0, fr.template as<cx<R>>(), rc_ + k * lenc);
         }
-        restrict_(0, rin, rc_ + k * lenc);
+      } else {
+        TimeScope ts(c.timer, 3);
+        launch_restrict_fine_m<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), len, v, len, K, f2c.template as<int>(), rc_,
+                                  lenc, c.st);
       }
       coarse_solve_m(1, rc_, ec_, K);
-      for (int k = 0; k < K; ++k) prolong_(0, ec_ + k * lenc, x + k * len, p.sap_pre > 0);
+      {
+        TimeScope ts(c.timer, 3);
+        launch_prolong_fine_m<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), len, ec_, lenc, K, f2c.template as<int>(), x,
+                                 len, p.sap_pre > 0, c.st);
+      }
       fine_sap_m(v, x, K, p.sap_post, p.mr_steps);
     } else {
       for (int k = 0; k < K; ++k) restrict_(l, v + k * len, rc_ + k * lenc);
