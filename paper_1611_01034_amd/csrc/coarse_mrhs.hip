@@ -296,6 +296,175 @@ __global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
   }
 }
 
+// SAP on the blocks of one colour of an intermediate level for K fields in
+// one workgroup per block: n_mr MR steps on the block operator D_B (hops
+// leaving the block dropped).  Wavefront j takes block site j and computes
+// q = D_B rho for its n rows and all K fields on the matrix cores (the
+// operator is read once per step for all fields); rho of the block lives in
+// LDS as [site][field][n] complex FP32 and is rounded to the storage format for
+// the products, as in the K-column stencil.  Per field the MR coefficient
+// <q, rho> / <q, q> is summed over the block in fixed order (FP32 per lane,
+// FP64 over the sites).  x += the accumulated correction at the end.
+template <class S, int NT, int RT>
+__global__ void __launch_bounds__(1024) k_coarse_sap_mrhs(CGeom cg,
+                                                          const typename store_traits<S>::elem* __restrict__ D,
+                                                          float tw, int bsz, const int* __restrict__ blk_sites,
+                                                          const int* __restrict__ blk_nbr,
+                                                          const cx<float>* __restrict__ r, cx<float>* __restrict__ x,
+                                                          int n_mr, int K, long ld) {
+  constexpr int n = 16 * RT, h = n / 2;
+  constexpr long nn = (long)n * n;
+  extern __shared__ char smem_raw[];
+  cx<float>* rho = reinterpret_cast<cx<float>*>(smem_raw);  // [bsz][K][n]
+  __shared__ float red[16][16][3];                          // [site][field][<q,rho> re, im, <q,q>]
+  __shared__ cx<float> alpha[16];
+  const int blk = blockIdx.x;
+  const int j = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, grp = lane >> 4;
+  const int site = blk_sites[blk * bsz + j];
+  const int* lnb = blk_nbr + ((long)blk * bsz + j) * 8;
+  for (int e = lane; e < K * n; e += 64) {
+    const int rr = e / n, l = e - rr * n;
+    rho[((long)j * K + rr) * n + l] = r[(long)rr * ld + (long)site * n + l];
+  }
+  float eps[RT][NT][4], qm[RT][NT][4], qp[RT][NT][4];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) eps[t][u][e] = 0.f;
+  for (int it = 0; it < n_mr; ++it) {
+    __syncthreads();  // rho of every site complete
+    v4f acc[RT][NT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) zero_acc<NT>(acc[t]);
+#pragma unroll 1
+    for (int b = 0; b < 9; ++b) {
+      const typename store_traits<S>::elem* bp;
+      int jn;
+      const bool bwd = b >= 5;
+      if (b == 0) {
+        jn = j;
+        bp = D + (long)site * 5 * nn;
+      } else if (!bwd) {
+        jn = lnb[b - 1];
+        if (jn < 0) continue;
+        bp = D + ((long)site * 5 + b) * nn;
+      } else {
+        jn = lnb[b - 1];
+        if (jn < 0) continue;
+        bp = D + ((long)blk_sites[blk * bsz + jn] * 5 + b - 4) * nn;
+      }
+      const cx<float>* xr = rho + (long)jn * K * n;
+#pragma unroll
+      for (int s = 0; s < RT; ++s) {
+        const int lc = 16 * s + 4 * grp;
+        const float gs = bwd ? (lc < h ? -1.0f : 1.0f) : 1.0f;
+        typename mm16<S>::frag bf[NT], af[RT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) bf[u] = b_frag<S>(xr, n, K, 16 * u + row, lc, gs);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int i = 16 * t + row;
+          af[t] = bwd ? a_frag_bwd<S>(bp, n, i, lc, i < h) : a_frag_col<S>(bp, n, i, lc);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[t][u] = mm16<S>::mma(af[t], bf[u], acc[t][u]);
+      }
+    }
+    // twist, then the complex q of every entry (own part and the partner lane's)
+    float pr[NT][3];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) pr[u][0] = pr[u][1] = pr[u][2] = 0.f;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int jc = 16 * u + row, rr = jc >> 1, c = jc & 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = 16 * t + 4 * grp + e;
+          float v = acc[t][u][e];
+          cx<float> rv = mk<float>(0.f, 0.f);
+          if (rr < K) {
+            rv = rho[((long)j * K + rr) * n + i];
+            const float g = i < h ? -tw : tw;
+            v += c == 0 ? -g * rv.im : g * rv.re;
+          }
+          const float o = __shfl_xor(v, 1, 64);
+          qm[t][u][e] = v;
+          qp[t][u][e] = o;
+          const float qre = c == 0 ? v : o, qim = c == 0 ? o : v;
+          if (c == 0 && rr < K) {
+            pr[u][0] += qre * rv.re + qim * rv.im;
+            pr[u][1] += qre * rv.im - qim * rv.re;
+            pr[u][2] += qre * qre + qim * qim;
+          }
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float v = pr[u][k];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        const int rr = (16 * u + row) >> 1;
+        if (grp == 0 && (row & 1) == 0 && rr < K) red[j][rr][k] = v;
+      }
+    __syncthreads();
+    if (threadIdx.x < K) {
+      double sr = 0, si = 0, sq = 0;
+      for (int q = 0; q < bsz; ++q) {
+        sr += red[q][threadIdx.x][0];
+        si += red[q][threadIdx.x][1];
+        sq += red[q][threadIdx.x][2];
+      }
+      alpha[threadIdx.x] = sq > 0 ? mk<float>((float)(sr / sq), (float)(si / sq)) : mk<float>(0.f, 0.f);
+    }
+    __syncthreads();
+    // eps += alpha rho;  rho -= alpha q   (own component c of each entry)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int jc = 16 * u + row, rr = jc >> 1, c = jc & 1;
+        const cx<float> a = alpha[rr < K ? rr : 0];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = 16 * t + 4 * grp + e;
+          // each lane reads and writes only its own component c of rho; the
+          // other one comes from the partner lane
+          float* rp = reinterpret_cast<float*>(&rho[((long)j * K + (rr < K ? rr : 0)) * n + i]);
+          const float ro = rr < K ? rp[c] : 0.f;
+          const float rq = __shfl_xor(ro, 1, 64);
+          const float qo = qm[t][u][e], qq = qp[t][u][e];
+          // (a z)_c: c = 0 -> a.re z.re - a.im z.im;  c = 1 -> a.re z.im + a.im z.re
+          const float sgn = c == 0 ? -1.f : 1.f;
+          if (rr < K) {
+            eps[t][u][e] += a.re * ro + sgn * a.im * rq;
+            rp[c] = ro - (a.re * qo + sgn * a.im * qq);
+          }
+        }
+      }
+  }
+  // x += eps
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int jc = 16 * u + row, rr = jc >> 1, c = jc & 1;
+      if (rr >= K) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * t + 4 * grp + e;
+        reinterpret_cast<float*>(x + (long)rr * ld + (long)site * n + i)[c] += eps[t][u][e];
+      }
+    }
+}
+
 static inline int nt_of(int K) { return K <= 8 ? 1 : 2; }
 
 // instantiate KERNEL<S, NT, RT> for NT = nt_of(K), RT = n / 16
@@ -345,13 +514,26 @@ void launch_coarse_hop_inv_odd_mrhs(const CGeom& cg, const void* D, const cx<flo
   MRHS_DISPATCH(k_coarse_hop_inv_odd_mrhs, grid, blk, 0, st, cg, Dp, Minv, K, ldv, x, base, y);
 }
 
+template <class S>
+void launch_coarse_sap_mrhs(const CGeom& cg, const void* D, double tw, int nblk_colour, int bsz, const int* blk_sites,
+                            const int* blk_nbr, const cx<float>* r, cx<float>* x, int n_mr, int K, long ld,
+                            hipStream_t st) {
+  if (bsz < 1 || bsz > 16 || K < 1 || K > 16) throw Error(INVALID_ARG, "K-field coarse SAP: bad block or field count");
+  const size_t sm = (size_t)bsz * K * cg.n * sizeof(cx<float>);
+  dim3 grid(nblk_colour), blk(64 * bsz);
+  auto Dp = (const typename store_traits<S>::elem*)D;
+  MRHS_DISPATCH(k_coarse_sap_mrhs, grid, blk, sm, st, cg, Dp, (float)tw, bsz, blk_sites, blk_nbr, r, x, n_mr, K, ld);
+}
+
 #define INST_MRHS(S)                                                                                              \
   template void launch_coarse_apply_mrhs<S>(const CGeom&, const void*, double, int, long, const cx<float>*,      \
                                             const cx<float>*, cx<float>*, hipStream_t);                          \
   template void launch_coarse_schur_even_mrhs<S>(const CGeom&, const void*, double, int, long, const cx<float>*, \
                                                  const cx<float>*, cx<float>*, int, hipStream_t);                \
   template void launch_coarse_hop_inv_odd_mrhs<S>(const CGeom&, const void*, const cx<float>*, int, long,        \
-                                                  const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
+                                                  const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);  \
+  template void launch_coarse_sap_mrhs<S>(const CGeom&, const void*, double, int, int, const int*, const int*,  \
+                                          const cx<float>*, cx<float>*, int, int, long, hipStream_t);
 INST_MRHS(f16)
 INST_MRHS(bf16)
 

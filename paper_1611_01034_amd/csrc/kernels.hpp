@@ -228,6 +228,12 @@ void launch_coarse_apply_mrhs(const CGeom& cg, const void* D, double tw, int K, 
 template <class S>
 void launch_coarse_schur_even_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* v,
                                    const cx<float>* t, cx<float>* y, int mode, hipStream_t st);
+// SAP colour sweep of an intermediate level for K fields (K <= 16), one
+// workgroup per block (bsz <= 16 sites), matrix cores
+template <class S>
+void launch_coarse_sap_mrhs(const CGeom& cg, const void* D, double tw, int nblk_colour, int bsz, const int* blk_sites,
+                            const int* blk_nbr, const cx<float>* r, cx<float>* x, int n_mr, int K, long ld,
+                            hipStream_t st);
 template <class S>
 void launch_coarse_hop_inv_odd_mrhs(const CGeom& cg, const void* D, const cx<float>* Minv, int K, long ldv,
                                     const cx<float>* x, const cx<float>* base, cx<float>* y, hipStream_t st);

@@ -872,6 +872,15 @@ struct MG : MGBase {
               launch_coarse_residual<R, S>(cg, Dst(l), tw[l], b + k * len, x + k * len, r + k * len, c.st);
         }
         int off = col == 0 ? 0 : G.nsblk_col[0];
+        if constexpr (kMfma) {
+          if (mfma_level(l) && G.ssz <= 16) {
+            launch_coarse_sap_mrhs<S>(cg, Dst(l), tw[l], G.nsblk_col[col], G.ssz,
+                                      G.sap_sites.template as<int>() + off * G.ssz,
+                                      G.sap_nbr.template as<int>() + (long)off * G.ssz * 8, r, x, p.coarse_mr_steps, K,
+                                      len, c.st);
+            continue;
+          }
+        }
         launch_coarse_sap_multi<R, S>(cg, Dst(l), tw[l], G.nsblk_col[col], G.ssz,
                                       G.sap_sites.template as<int>() + off * G.ssz,
                                       G.sap_nbr.template as<int>() + (long)off * G.ssz * 8, r, x, p.coarse_mr_steps, K,
