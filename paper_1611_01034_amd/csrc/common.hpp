@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 namespace ddamg {
 
@@ -35,12 +36,30 @@ template <class T> __host__ __device__ __forceinline__ cx<T>& operator-=(cx<T>& 
 template <class T> __host__ __device__ __forceinline__ cx<T> conj(cx<T> a) { return mk(a.re, -a.im); }
 template <class T> __host__ __device__ __forceinline__ cx<T> times_i(cx<T> a) { return mk(-a.im, a.re); }
 template <class T> __host__ __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return mk(a.im, -a.re); }
-// a += b*c  and  a += conj(b)*c
+// a += b*c  and  a += conj(b)*c.  In FP32 on the device as two chained fused
+// multiply-adds per component (the arithmetic-bound FP32 kernels: one
+// instruction fewer per component than a product, a difference and a sum); in
+// FP64 as sums of products (the FP64 kernels are bound by memory, and the
+// shorter dependency chains keep their registers within budget).
 template <class T> __host__ __device__ __forceinline__ void cmac(cx<T>& a, cx<T> b, cx<T> c) {
+#ifdef __HIP_DEVICE_COMPILE__
+  if constexpr (std::is_same<T, float>::value) {
+    a.re = __builtin_fmaf(-b.im, c.im, __builtin_fmaf(b.re, c.re, a.re));
+    a.im = __builtin_fmaf(b.im, c.re, __builtin_fmaf(b.re, c.im, a.im));
+    return;
+  }
+#endif
   a.re += b.re * c.re - b.im * c.im;
   a.im += b.re * c.im + b.im * c.re;
 }
 template <class T> __host__ __device__ __forceinline__ void cjmac(cx<T>& a, cx<T> b, cx<T> c) {
+#ifdef __HIP_DEVICE_COMPILE__
+  if constexpr (std::is_same<T, float>::value) {
+    a.re = __builtin_fmaf(b.im, c.im, __builtin_fmaf(b.re, c.re, a.re));
+    a.im = __builtin_fmaf(-b.im, c.re, __builtin_fmaf(b.re, c.im, a.im));
+    return;
+  }
+#endif
   a.re += b.re * c.re + b.im * c.im;
   a.im += b.re * c.im - b.im * c.re;
 }
