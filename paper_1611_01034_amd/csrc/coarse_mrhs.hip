@@ -208,13 +208,15 @@ __device__ __forceinline__ void store_mfma(const CGeom& cg, int site, int t, v4f
   }
 }
 
-// y_r = D x_r (b == null) or y_r = b_r - D x_r, all sites
+// y_r = D x_r (b == null) or y_r = b_r - D x_r, on every site or on the sites
+// of a list
 template <class S, int NT, int RT>
 __global__ void __launch_bounds__(256) k_coarse_apply_mrhs(CGeom cg, const typename store_traits<S>::elem* __restrict__ D,
                                                            float tw, int K, long ldv, const cx<float>* __restrict__ x,
-                                                           const cx<float>* __restrict__ b, cx<float>* __restrict__ y) {
+                                                           const cx<float>* __restrict__ b, cx<float>* __restrict__ y,
+                                                           const int* __restrict__ sites) {
   const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
-  const int site = blockIdx.x;
+  const int site = sites ? sites[blockIdx.x] : blockIdx.x;
   v4f acc[NT];
   zero_acc<NT>(acc);
   stencil_mfma<S, NT, RT>(cg, D, site, t, x, x, 1.0f, K, ldv, lane, acc);
@@ -491,10 +493,11 @@ static inline int nt_of(int K) { return K <= 8 ? 1 : 2; }
 
 template <class S>
 void launch_coarse_apply_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* x,
-                              const cx<float>* b, cx<float>* y, hipStream_t st) {
-  dim3 grid(cg.nsites), blk(4 * cg.n);
+                              const cx<float>* b, cx<float>* y, hipStream_t st, const int* sites, int nlist) {
+  dim3 grid(sites ? nlist : cg.nsites), blk(4 * cg.n);
+  if (grid.x == 0) return;
   auto Dp = (const typename store_traits<S>::elem*)D;
-  MRHS_DISPATCH(k_coarse_apply_mrhs, grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, x, b, y);
+  MRHS_DISPATCH(k_coarse_apply_mrhs, grid, blk, 0, st, cg, Dp, (float)tw, K, ldv, x, b, y, sites);
 }
 
 template <class S>
@@ -527,7 +530,7 @@ void launch_coarse_sap_mrhs(const CGeom& cg, const void* D, double tw, int nblk_
 
 #define INST_MRHS(S)                                                                                              \
   template void launch_coarse_apply_mrhs<S>(const CGeom&, const void*, double, int, long, const cx<float>*,      \
-                                            const cx<float>*, cx<float>*, hipStream_t);                          \
+                                            const cx<float>*, cx<float>*, hipStream_t, const int*, int);         \
   template void launch_coarse_schur_even_mrhs<S>(const CGeom&, const void*, double, int, long, const cx<float>*, \
                                                  const cx<float>*, cx<float>*, int, hipStream_t);                \
   template void launch_coarse_hop_inv_odd_mrhs<S>(const CGeom&, const void*, const cx<float>*, int, long,        \

@@ -224,7 +224,8 @@ void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int 
 // side r at offset r * ldv.
 template <class S>
 void launch_coarse_apply_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* x,
-                              const cx<float>* b, cx<float>* y, hipStream_t st);
+                              const cx<float>* b, cx<float>* y, hipStream_t st, const int* sites = nullptr,
+                              int nlist = 0);
 template <class S>
 void launch_coarse_schur_even_mrhs(const CGeom& cg, const void* D, double tw, int K, long ldv, const cx<float>* v,
                                    const cx<float>* t, cx<float>* y, int mode, hipStream_t st);

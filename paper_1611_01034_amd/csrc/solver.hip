@@ -863,7 +863,10 @@ struct MG : MGBase {
           bool done = false;
           if constexpr (kMfma) {
             if (mfma_level(l)) {
-              launch_coarse_apply_mrhs<S>(cg, Dst(l), tw[l], K, len, x, b, r, c.st);
+              // the residual is read on the sites of this colour's blocks only
+              const int off = col == 0 ? 0 : G.nsblk_col[0];
+              launch_coarse_apply_mrhs<S>(cg, Dst(l), tw[l], K, len, x, b, r, c.st,
+                                          G.sap_sites.template as<int>() + off * G.ssz, G.nsblk_col[col] * G.ssz);
               done = true;
             }
           }

@@ -117,7 +117,7 @@ def traffic(a):
     write_b = w_k * sw
     alg = a.site_bytes * a.sites
     src = sources_sha256(a.source.split(","))
-    res = {"kernel": a.kernel, "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
+    res = {"kernel": a.kernel, "copy_kernel": a.copy, "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
            "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes_each_way": a.copy_bytes,
            "scale_fetch": sf, "scale_write": sw, "fetch_bytes": fetch_b, "write_bytes": write_b,
            "bytes_per_launch": fetch_b + write_b, "algorithmic_bytes_per_launch": alg,
