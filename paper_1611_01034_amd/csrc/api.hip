@@ -341,7 +341,6 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
     if (!(tol > 0) || !std::isfinite(tol)) throw Error(INVALID_ARG, "tol must be > 0");
     auto t0 = std::chrono::steady_clock::now();
     long N = c.fine_len();
-    c.outer.init(c.p.restart, N, N, true);
     c.f64c.ensure(sizeof(cx<double>) * N);
     std::function<void(const cx<double>*, cx<double>*)> A = [&c](const cx<double>* in, cx<double>* out) {
       c.dirac64(in, out, c.mu);
@@ -357,9 +356,7 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
     const int Kb = std::min(nrhs, c.p.rhs_batch);
     if (Kb > 1) {
       // right-hand sides in groups of Kb through one lock-step outer FGMRES
-      c.outer.V.release();
-      c.outer.Z.release();
-      c.outer.tmp.release();
+      // (the one-column workspace is not allocated on this path)
       KrylovWSm<double> ws;
       ws.init(c.p.restart, Kb, N, N, true);
       DevBuf bK, xK;
@@ -389,6 +386,7 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
       }
       kr.resid = worst;
     }
+    if (Kb <= 1) c.outer.init(c.p.restart, N, N, true);
     for (int r = Kb > 1 ? nrhs : 0; r < nrhs; ++r) {
       const char* bs = (const char*)b + sizeof(cx<double>) * (size_t)N * r;
       char* xs = (char*)x + sizeof(cx<double>) * (size_t)N * r;

@@ -313,7 +313,7 @@ void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex) {
   act.ensure(sizeof(int) * K);
   jd.ensure(sizeof(int) * K);
   if (!h_resid) {
-    HIP_CHECK(hipHostMalloc((void**)&h_resid, sizeof(double) * 64, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void**)&h_resid, sizeof(double) * 96, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void**)&h_scal, sizeof(cx<double>) * 4 * 64, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void**)&h_act, sizeof(int) * 64, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void**)&h_jd, sizeof(int) * 64, hipHostMallocDefault));
@@ -409,12 +409,15 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
     launch_scale_by_inv_b<R>(r, ld, scal + 1, 4, V, ld, N, K, act, 1, st);
     launch_init_g_b(g, ldh, scal + 1, 4, K, act, st);
     for (int k = 0; k < K; ++k) ws.h_jd[k] = 0;
-    // Without a preconditioner the test of step j is taken while step j+1 is
-    // already queued; a column that met its tolerance at step j then drops
-    // step j+1, which changed only its Hessenberg column j+1 and g[j+1..j+2].
+    // Without a preconditioner the test of step s is taken while steps s+1 and
+    // s+2 are already queued (the device never waits for the host); a column
+    // that met its tolerance at step s then drops the later steps it ran, which
+    // changed only its Hessenberg columns after s and g entries after s+1.
     const bool lookahead = !fixed && M == nullptr;
-    int pend = -1;                 // step whose estimates are in flight
-    int act_at[2][16];             // columns active in the step of each slot
+    constexpr int LAG = 2, NSLOT = LAG + 1;
+    int tested = 0;                // steps 0..tested-1 of this cycle are tested
+    int last = -1;                 // last step queued in this cycle
+    int act_at[NSLOT][16];         // columns active in the step of each slot
     for (int j = 0; j < mm; ++j) {
       cx<R>* Vj = V + (long)j * K * ld;
       cx<R>* Vn = V + (long)(j + 1) * K * ld;
@@ -452,28 +455,33 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
           ++res.iters[k];
         }
       if (lookahead) {
-        const int slot = j & 1;
+        const int slot = j % NSLOT;
         HIP_CHECK(hipMemcpyAsync(ws.h_resid + 32 * slot, ws.resid.p, sizeof(double) * K, hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipEventRecord(ws.ready[slot], st));
         for (int k = 0; k < K; ++k) act_at[slot][k] = ws.h_act[k];
-        if (pend >= 0) {
-          const int ps = pend & 1;
+        last = j;
+        bool stop = false;
+        while (tested <= j - LAG) {
+          const int s = tested++, ps = s % NSLOT;
           HIP_CHECK(hipEventSynchronize(ws.ready[ps]));
           bool changed = false;
           for (int k = 0; k < K; ++k)
             if (act_at[ps][k] && ws.h_act[k] && ws.h_resid[32 * ps + k] <= tol * bn[k]) {
               ws.h_act[k] = 0;
               changed = true;
-              if (act_at[slot][k]) {  // it also ran step j: drop it
-                --res.iters[k];
-                ws.h_jd[k] = pend + 1;
-              }
+              for (int t = s + 1; t <= j; ++t)  // the steps it ran after s are dropped
+                if (act_at[t % NSLOT][k]) --res.iters[k];
+              ws.h_jd[k] = s + 1;
             }
+          still = 0;
           for (int k = 0; k < K; ++k) still += ws.h_act[k];
           if (changed) push_act();
-          if (still == 0) break;
+          if (still == 0) {
+            stop = true;
+            break;
+          }
         }
-        pend = j;
+        if (stop) break;
       } else if (!fixed) {
         HIP_CHECK(hipMemcpyAsync(ws.h_resid, ws.resid.p, sizeof(double) * K, hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
@@ -489,7 +497,8 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
       }
       if (steps >= max_iter) break;
     }
-    if (pend >= 0) HIP_CHECK(hipEventSynchronize(ws.ready[pend & 1]));
+    // the estimate slots of untested steps are reused by the next cycle
+    for (int s = tested; s <= last; ++s) HIP_CHECK(hipEventSynchronize(ws.ready[s % NSLOT]));
     HIP_CHECK(hipMemcpyAsync(jd, ws.h_jd, sizeof(int) * K, hipMemcpyHostToDevice, st));
     launch_trisolve_b(H, ldh, m, g, y, jd, K, st);
     launch_multi_axpy_b<R>(Z, (long)K * ld, ld, m, jd, y, ldh, 1.0, x, ld, N, K, nullptr, st);

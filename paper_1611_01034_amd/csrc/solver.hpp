@@ -89,8 +89,8 @@ struct KrylovWSm {
   long ld = 0;
   bool flexible = false;
   DevBuf V, Z, r, H, cs, sn, g, y, part, scal, resid, act, jd;
-  double* h_resid = nullptr;   // pinned: K residual estimates (two slots of 32 for the look-ahead)
-  hipEvent_t ready[2] = {nullptr, nullptr};
+  double* h_resid = nullptr;   // pinned: K residual estimates (three slots of 32 for the look-ahead)
+  hipEvent_t ready[3] = {nullptr, nullptr, nullptr};
   int nwgf = 0;                  // workgroups per column of the fused Arnoldi step
   cx<double>* h_scal = nullptr;  // pinned: K x 4 scalars
   int* h_act = nullptr;        // pinned: K flags (host copy)
