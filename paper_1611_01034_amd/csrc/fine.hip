@@ -34,29 +34,41 @@ template <class R, class S, bool SUB = false>
 __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::elem* U, const Geom& g, int B, int s,
                                               const SiteNbr& me, const cx<R>* lds, int lds_off, cx<R> out[12]) {
   // lds holds a 12 x half field of the opposite parity (component-major);
-  // hops leaving the block are dropped (Dirichlet cut of the SAP domain)
-  cx<R> psi[12], u[9];
+  // hops leaving the block are dropped (Dirichlet cut of the SAP domain).
+  // Both links of a direction are loaded before its arithmetic, and a dropped
+  // hop is masked by a zero link rather than a branch, so each direction costs
+  // one memory latency instead of two.
+  using E = typename store_traits<S>::elem;
+  const long base_s = fidx(g, B, s, 36);
 #pragma unroll 1
   for (int mu = 0; mu < g.ndir; ++mu) {
-    if (me.l[mu] + 1 < g.b[mu]) {
-      int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
-      l[mu] += 1;
-      int sn = local_slot(g, l) - lds_off;
+    int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
+    const int l0 = l[mu];
+    const bool vf = l0 + 1 < g.b[mu], vb = l0 > 0;
+    l[mu] = l0 + 1;
+    const int snf = local_slot(g, l);
+    l[mu] = l0 - 1;
+    const int snb = vb ? local_slot(g, l) : s;
+    const int sf = vf ? snf - lds_off : 0, sb = vb ? snb - lds_off : 0;
+    const long bf = base_s + (long)mu * 9 * TILE;
+    const long bb = fidx(g, B, snb, 36) + (long)mu * 9 * TILE;
+    E lf[9], lb[9];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sn] : lds[c * g.half + sn];
-      load_link<R, S>(U, g, B, s, mu, u);
-      hop_accum<0>(mu, psi, u, out);
+    for (int k = 0; k < 9; ++k) {
+      lf[k] = U[bf + (long)k * TILE];
+      lb[k] = U[bb + (long)k * TILE];
     }
-    if (me.l[mu] > 0) {
-      int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
-      l[mu] -= 1;
-      int slot = local_slot(g, l);
-      int sn = slot - lds_off;
+    cx<R> psi[12], u[9];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sn] : lds[c * g.half + sn];
-      load_link<R, S>(U, g, B, slot, mu, u);
-      hop_accum<1>(mu, psi, u, out);
-    }
+    for (int k = 0; k < 9; ++k) u[k] = vf ? ld<R, S>(lf, k) : mk<R>(0, 0);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sf] : lds[c * g.half + sf];
+    hop_accum<0>(mu, psi, u, out);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = vb ? ld<R, S>(lb, k) : mk<R>(0, 0);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sb] : lds[c * g.half + sb];
+    hop_accum<1>(mu, psi, u, out);
   }
 }
 
@@ -730,97 +742,6 @@ template void launch_prolong_fine_m<float>(const Geom&, int, const cx<float>*, l
                                            const int*, cx<float>*, long, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// block orthonormalisation (classical Gram-Schmidt, twice) per aggregate half,
-// FP64 arithmetic; columns in the order v_1..v_Nv, diag(R) = norms (real > 0).
-// One workgroup per (block, half), one thread per slot (6 rows each).
-template <class RI, class RO>
-__global__ void __launch_bounds__(256) k_qr_fine(Geom g, int Nv, const cx<RI>* __restrict__ V, long vstride,
-                                                 RO* __restrict__ Qout_raw, long qstride, int* __restrict__ fail) {
-  cx<RO>* Qout = reinterpret_cast<cx<RO>*>(Qout_raw);
-  __shared__ double red[32][4][2];
-  __shared__ double dsh[32][2];
-  int B = blockIdx.x >> 1, h = blockIdx.x & 1;
-  int s = threadIdx.x, lane = s & 63, wv = s >> 6, nw = (g.bs + 63) >> 6;
-  long base = fidx(g, B, s, 12) + (long)(6 * h) * TILE;
-  auto reduce = [&](double a, double b, int slot) {
-    int nact = min(64, g.bs - wv * 64);
-    a = wave_sum_n(a, nact);
-    b = wave_sum_n(b, nact);
-    if (lane == 0) {
-      red[slot][wv][0] = a;
-      red[slot][wv][1] = b;
-    }
-  };
-  for (int i = 0; i < Nv; ++i) {
-    cx<double> v[6];
-    for (int c = 0; c < 6; ++c) {
-      cx<RI> vi = V[(long)i * vstride + base + (long)c * TILE];
-      v[c] = mk<double>(vi.re, vi.im);
-    }
-    double n0 = 0;
-    for (int c = 0; c < 6; ++c) n0 += norm2(v[c]);
-    reduce(n0, 0.0, 0);
-    __syncthreads();
-    double nrm0 = 0;
-    for (int w = 0; w < nw; ++w) nrm0 += red[0][w][0];
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int j = 0; j < i; ++j) {
-        double ar = 0, ai = 0;
-        for (int c = 0; c < 6; ++c) {
-          cx<RO> q = Qout[(long)j * qstride + base + (long)c * TILE];
-          ar += (double)q.re * v[c].re + (double)q.im * v[c].im;
-          ai += (double)q.re * v[c].im - (double)q.im * v[c].re;
-        }
-        reduce(ar, ai, j);
-      }
-      __syncthreads();
-      if (s < i) {
-        double re = 0, im = 0;
-        for (int w = 0; w < nw; ++w) {
-          re += red[s][w][0];
-          im += red[s][w][1];
-        }
-        dsh[s][0] = re;
-        dsh[s][1] = im;
-      }
-      __syncthreads();
-      for (int j = 0; j < i; ++j) {
-        cx<double> d = mk(dsh[j][0], dsh[j][1]);
-        for (int c = 0; c < 6; ++c) {
-          cx<RO> q = Qout[(long)j * qstride + base + (long)c * TILE];
-          v[c] = v[c] - d * mk<double>(q.re, q.im);
-        }
-      }
-      __syncthreads();
-    }
-    double n1 = 0;
-    for (int c = 0; c < 6; ++c) n1 += norm2(v[c]);
-    reduce(n1, 0.0, 0);
-    __syncthreads();
-    double nrm = 0;
-    for (int w = 0; w < nw; ++w) nrm += red[0][w][0];
-    __syncthreads();
-    if (!(nrm > 1e-24 * nrm0) && s == 0) atomicOr(fail, 1);
-    double inv = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
-    for (int c = 0; c < 6; ++c) {
-      cx<double> q = inv * v[c];
-      Qout[(long)i * qstride + base + (long)c * TILE] = mk<RO>((RO)q.re, (RO)q.im);
-    }
-  }
-}
-template <class RI, class RO>
-void launch_qr_fine(const Geom& g, int Nv, const cx<RI>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
-                    hipStream_t st) {
-  hipLaunchKernelGGL((k_qr_fine<RI, RO>), dim3(2 * g.nblocks), dim3(g.bs), 0, st, g, Nv, V, vstride, (RO*)Q, qstride,
-                     fail);
-}
-template void launch_qr_fine<double, double>(const Geom&, int, const cx<double>*, long, cx<double>*, long, int*,
-                                             hipStream_t);
-template void launch_qr_fine<float, float>(const Geom&, int, const cx<float>*, long, cx<float>*, long, int*,
-                                           hipStream_t);
-
-// ---------------------------------------------------------------------------
 // Galerkin assembly of the first coarse operator on the matrix cores.  One
 // workgroup (4 wavefronts) per (block, kind), each kind a sum over a list of
 // sites x of rank-6 products
@@ -1078,5 +999,182 @@ __global__ void k_cvt_real(long n, const double* __restrict__ in, float* __restr
 void launch_cvt_real(long n, const double* in, float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_cvt_real, dim3((n + 255) / 256), dim3(256), 0, st, n, in, out);
 }
+
+// ---------------------------------------------------------------------------
+// Block orthonormalisation per aggregate half (Sec. 1 aggregation): the
+// aggregate's rows of v_1..v_Nv are replaced by Q with V = Q R, R upper
+// triangular with a real positive diagonal; that factor is unique, so it is the
+// one Gram-Schmidt in the order v_1..v_Nv produces.  It is computed as a
+// Cholesky QR in FP64: G = V^H V on the matrix cores, G = R^H R in LDS, then
+// Q = V R^{-1} on the matrix cores.  An FP64 output takes a second pass on Q,
+// which brings its orthogonality to working precision; for an FP32 output the
+// one FP64 pass is already below FP32 rounding.  A pivot at or below 1e-24 of
+// the vector's squared norm (linearly dependent test vectors) sets *fail.
+//
+// One workgroup (4 wavefronts) per (block, half); rows r of the aggregate are
+// (tile of 8 slots, component of the half, slot in the tile), so 8 consecutive
+// rows are contiguous in the block layout.  Nv <= 32 (two 16-wide tiles).
+namespace {
+constexpr int QR_NT = 256;
+
+__device__ __forceinline__ long qr_row_addr(const Geom& g, int B, int h, int r) {
+  const int tau = r / 48, rem = r - 48 * tau, c = rem >> 3, sig = rem & 7;
+  return ((long)B * (g.bs / TILE) + tau) * 12 * TILE + (long)(6 * h + c) * TILE + sig;
+}
+
+template <class T>
+__device__ __forceinline__ cx<double> qr_ld(const cx<T>* p, long stride, int j, int Nv, long a) {
+  if (j >= Nv) return mk<double>(0, 0);
+  cx<T> v = p[(long)j * stride + a];
+  return mk<double>((double)v.re, (double)v.im);
+}
+
+// one Cholesky QR pass: src (rows of this aggregate) -> dst; Gr/Gi/Xr/Xi/d0 in LDS
+template <class TS, class TD>
+__device__ void cholqr_pass(const Geom& g, int B, int h, int Nv, const cx<TS>* src, long sstride, cx<TD>* dst,
+                            long dstride, double (*Gr)[33], double (*Gi)[33], double (*Xr)[33], double (*Xi)[33],
+                            double* d0, int* fail) {
+  using MF = mfma_k4<double>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rows = 6 * g.bs;
+  const int NT = Nv > 16 ? 2 : 1;
+  const int j0 = lane & 15, kq = lane >> 4, p = kq & 1;
+  // ---- G = V^H V: wavefront w sums the complex row pairs ks = w, w+4, ...
+  MF::acc a00r = {0, 0, 0, 0}, a00i = {0, 0, 0, 0}, a01r = {0, 0, 0, 0}, a01i = {0, 0, 0, 0}, a11r = {0, 0, 0, 0},
+          a11i = {0, 0, 0, 0};
+#pragma unroll 4
+  for (int ks = w; ks < rows / 2; ks += 4) {
+    const long a = qr_row_addr(g, B, h, 2 * ks + (kq >> 1));
+    const cx<double> v0 = qr_ld(src, sstride, j0, Nv, a);
+    const double x0 = p ? v0.im : v0.re, y0 = p ? -v0.re : v0.im;
+    a00r = MF::step(x0, x0, a00r);
+    a00i = MF::step(x0, y0, a00i);
+    if (NT == 2) {
+      const cx<double> v1 = qr_ld(src, sstride, 16 + j0, Nv, a);
+      const double x1 = p ? v1.im : v1.re, y1 = p ? -v1.re : v1.im;
+      a01r = MF::step(x0, x1, a01r);
+      a01i = MF::step(x0, y1, a01i);
+      a11r = MF::step(x1, x1, a11r);
+      a11i = MF::step(x1, y1, a11i);
+    }
+  }
+  // deterministic sum over the 4 wavefronts, in wavefront order
+  for (int v = 0; v < 4; ++v) {
+    if (w == v) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = MF::row(lane, e), c = j0;
+        Gr[r][c] = (v ? Gr[r][c] : 0.0) + a00r[e];
+        Gi[r][c] = (v ? Gi[r][c] : 0.0) + a00i[e];
+        if (NT == 2) {
+          Gr[r][16 + c] = (v ? Gr[r][16 + c] : 0.0) + a01r[e];
+          Gi[r][16 + c] = (v ? Gi[r][16 + c] : 0.0) + a01i[e];
+          Gr[16 + r][16 + c] = (v ? Gr[16 + r][16 + c] : 0.0) + a11r[e];
+          Gi[16 + r][16 + c] = (v ? Gi[16 + r][16 + c] : 0.0) + a11i[e];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t < Nv) d0[t] = Gr[t][t];
+  __syncthreads();
+  // ---- G = R^H R in place on the upper triangle (R[k][k] real)
+  for (int k = 0; k < Nv; ++k) {
+    const double dk = Gr[k][k];
+    const double rkk = dk > 0 ? sqrt(dk) : 0.0, rinv = rkk > 0 ? 1.0 / rkk : 0.0;
+    __syncthreads();
+    if (t == 0) {
+      if (fail && !(dk > 1e-24 * d0[k])) atomicOr(fail, 1);
+      Gr[k][k] = rkk;
+      Gi[k][k] = 0.0;
+    } else if (t > k && t < Nv) {
+      Gr[k][t] *= rinv;
+      Gi[k][t] *= rinv;
+    }
+    __syncthreads();
+    for (int q = t; q < 32 * 32; q += QR_NT) {
+      const int j = q >> 5, l = q & 31;
+      if (j > k && l >= j && l < Nv) {
+        // G[j][l] -= conj(R[k][j]) R[k][l]
+        const double ar = Gr[k][j], ai = Gi[k][j], br = Gr[k][l], bi = Gi[k][l];
+        Gr[j][l] -= ar * br + ai * bi;
+        Gi[j][l] -= ar * bi - ai * br;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- X = R^{-1} (upper), one thread per column; zero elsewhere (padding)
+  for (int q = t; q < 32 * 32; q += QR_NT) {
+    Xr[q >> 5][q & 31] = 0.0;
+    Xi[q >> 5][q & 31] = 0.0;
+  }
+  __syncthreads();
+  if (t < Nv) {
+    const int i = t;
+    Xr[i][i] = Gr[i][i] > 0 ? 1.0 / Gr[i][i] : 0.0;
+    for (int j = i - 1; j >= 0; --j) {
+      double sr = 0, si = 0;
+      for (int m = j + 1; m <= i; ++m) {
+        const double ar = Gr[j][m], ai = Gi[j][m], xr = Xr[m][i], xi = Xi[m][i];
+        sr += ar * xr - ai * xi;
+        si += ar * xi + ai * xr;
+      }
+      const double ri = Gr[j][j] > 0 ? 1.0 / Gr[j][j] : 0.0;
+      Xr[j][i] = -sr * ri;
+      Xi[j][i] = -si * ri;
+    }
+  }
+  __syncthreads();
+  // ---- Q = V X: wavefront w takes row tiles w, w+4, ...; contraction over (j, re/im)
+  const int nks = (Nv + 1) / 2;
+  for (int rt = w; rt < rows / 16; rt += 4) {
+    const long a = qr_row_addr(g, B, h, 16 * rt + j0);
+    MF::acc q0r = {0, 0, 0, 0}, q0i = {0, 0, 0, 0}, q1r = {0, 0, 0, 0}, q1i = {0, 0, 0, 0};
+    for (int ks = 0; ks < nks; ++ks) {
+      const int j = 2 * ks + (kq >> 1);
+      const cx<double> v = qr_ld(src, sstride, j, Nv, a);
+      const double av = p ? v.im : v.re;
+      const int jj = j < 32 ? j : 31;
+      double xr = Xr[jj][j0], xi = Xi[jj][j0];
+      q0r = MF::step(av, p ? -xi : xr, q0r);
+      q0i = MF::step(av, p ? xr : xi, q0i);
+      if (NT == 2) {
+        xr = Xr[jj][16 + j0];
+        xi = Xi[jj][16 + j0];
+        q1r = MF::step(av, p ? -xi : xr, q1r);
+        q1i = MF::step(av, p ? xr : xi, q1i);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const long ar = qr_row_addr(g, B, h, 16 * rt + MF::row(lane, e));
+      if (j0 < Nv) dst[(long)j0 * dstride + ar] = mk<TD>((TD)q0r[e], (TD)q0i[e]);
+      if (NT == 2 && 16 + j0 < Nv) dst[(long)(16 + j0) * dstride + ar] = mk<TD>((TD)q1r[e], (TD)q1i[e]);
+    }
+  }
+  __syncthreads();
+}
+}  // namespace
+
+template <class RI, class RO>
+__global__ void __launch_bounds__(QR_NT) k_qr_fine(Geom g, int Nv, const cx<RI>* V, long vstride, RO* Qout_raw,
+                                                   long qstride, int* __restrict__ fail) {
+  __shared__ double Gr[32][33], Gi[32][33], Xr[32][33], Xi[32][33], d0[32];
+  cx<RO>* Q = reinterpret_cast<cx<RO>*>(Qout_raw);
+  const int B = blockIdx.x >> 1, h = blockIdx.x & 1;
+  cholqr_pass<RI, RO>(g, B, h, Nv, V, vstride, Q, qstride, Gr, Gi, Xr, Xi, d0, fail);
+  if constexpr (sizeof(RO) == 8) cholqr_pass<RO, RO>(g, B, h, Nv, Q, qstride, Q, qstride, Gr, Gi, Xr, Xi, d0, nullptr);
+}
+template <class RI, class RO>
+void launch_qr_fine(const Geom& g, int Nv, const cx<RI>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
+                    hipStream_t st) {
+  if (Nv < 1 || Nv > 32 || g.bs % TILE) throw Error(INVALID_ARG, "block orthonormalisation needs 1 <= Nv <= 32");
+  hipLaunchKernelGGL((k_qr_fine<RI, RO>), dim3(2 * g.nblocks), dim3(QR_NT), 0, st, g, Nv, V, vstride, (RO*)Q, qstride,
+                     fail);
+}
+template void launch_qr_fine<double, double>(const Geom&, int, const cx<double>*, long, cx<double>*, long, int*,
+                                             hipStream_t);
+template void launch_qr_fine<float, float>(const Geom&, int, const cx<float>*, long, cx<float>*, long, int*,
+                                           hipStream_t);
 
 }  // namespace ddamg
