@@ -510,8 +510,11 @@ void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int 
 
 
 // ---------------------------------------------------------------------------
-// Classical Gram-Schmidt (twice), norm and Givens step of K lock-step Arnoldi
-// processes in four launches.  Grid (nwg, K), column r = blockIdx.y; inactive
+// Classical Gram-Schmidt, norm and Givens step of K lock-step Arnoldi
+// processes: two Gram-Schmidt passes for FP64 vectors (four launches), one for
+// FP32 vectors (three launches; the FP32 inner solves stop at loose relative
+// tolerances, far above the orthogonality one pass keeps in FP32 arithmetic).
+// Grid (nwg, K), column r = blockIdx.y; inactive
 // columns return at once (the last launch zeroes their next basis vector).
 // Every workgroup stores per-workgroup partial sums; the next launch begins by
 // reducing them in every workgroup (fixed order, so results are deterministic
@@ -636,9 +639,9 @@ __global__ void __launch_bounds__(BS) k_cgs_axpy_dot(const cx<R>* __restrict__ V
   store_partials<KM, BS / 64>(acc, 2 * k, pb + 2 * r * pcs);
 }
 
-// c_r = sum of pb_r (workgroup 0: hcol_r += c_r);  w_r -= sum_i c_r[i] V_{r,i};
-// pa_r: partials of ||w_r||^2
-template <class R, int KM, int BS>
+// c_r = sum of pb_r (workgroup 0: hcol_r += c_r, or hcol_r = c_r when this is
+// the only pass);  w_r -= sum_i c_r[i] V_{r,i};  pa_r: partials of ||w_r||^2
+template <class R, int KM, int BS, bool FIRST = false>
 __global__ void __launch_bounds__(BS) k_cgs_axpy_norm(const cx<R>* __restrict__ V, long ldv, long csV, int k,
                                                       cx<R>* w, long csw, long N, const double* pb, double* pa,
                                                       long pcs, cx<double>* hcol, long hcs, const int* act) {
@@ -649,7 +652,10 @@ __global__ void __launch_bounds__(BS) k_cgs_axpy_norm(const cx<R>* __restrict__ 
   __shared__ double cf[2 * KM];
   __shared__ cx<R> cfr[KM];
   reduce_partials(pb + 2 * r * pcs, 2 * k, 2 * KM, gridDim.x, cf);
-  if (blockIdx.x == 0 && threadIdx.x < 2 * k) reinterpret_cast<double*>(hcol + r * hcs)[threadIdx.x] += cf[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x < 2 * k) {
+    double& hv = reinterpret_cast<double*>(hcol + r * hcs)[threadIdx.x];
+    hv = FIRST ? cf[threadIdx.x] : hv + cf[threadIdx.x];
+  }
   if (threadIdx.x < KM) cfr[threadIdx.x] = mk<R>((R)cf[2 * threadIdx.x], (R)cf[2 * threadIdx.x + 1]);
   __syncthreads();
   R acc[2] = {R(0), R(0)};
@@ -726,6 +732,7 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
                         long pcs, int nwg, cx<double>* hcol, long hcs, cx<double>* H, int ldh, int m, double* cs,
                         cx<double>* sn, cx<double>* g, int j, double* resid, int K, const int* act, hipStream_t st) {
   const dim3 grid(nwg, K), blk(BS);
+  constexpr bool two_pass = cgs_two_pass<R>();
   // the axpy kernels of 16 or more vectors hold twice the registers: half the
   // threads per workgroup (same workgroup count, so the partials match)
 #define CGS_LAUNCH(KM)                                                                                                 \
@@ -733,10 +740,15 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
     constexpr int BA = (BS == 1024 && KM >= 16) ? 512 : BS;                                                            \
     hipLaunchKernelGGL((k_cgs_dot<R, KM, BS>), grid, blk, 0, st, V, ldv, csV, k, (const cx<R>*)w, csw, N, a, pcs,     \
                        act);                                                                                           \
-    hipLaunchKernelGGL((k_cgs_axpy_dot<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,                 \
-                       (const double*)a, b, pcs, hcol, hcs, act);                                                      \
-    hipLaunchKernelGGL((k_cgs_axpy_norm<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,                \
-                       (const double*)b, a, pcs, hcol, hcs, act);                                                      \
+    if (two_pass) {                                                                                                    \
+      hipLaunchKernelGGL((k_cgs_axpy_dot<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,               \
+                         (const double*)a, b, pcs, hcol, hcs, act);                                                    \
+      hipLaunchKernelGGL((k_cgs_axpy_norm<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,              \
+                         (const double*)b, a, pcs, hcol, hcs, act);                                                    \
+    } else {                                                                                                           \
+      hipLaunchKernelGGL((k_cgs_axpy_norm<R, KM, BA, true>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,        \
+                         (const double*)a, b, pcs, hcol, hcs, act);                                                    \
+    }                                                                                                                  \
   }
   if (k <= 8) {
     CGS_LAUNCH(8)
@@ -746,8 +758,8 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
     CGS_LAUNCH(32)
   }
 #undef CGS_LAUNCH
-  hipLaunchKernelGGL((k_cgs_scale_givens<R, BS>), grid, blk, 0, st, w, csw, N, (const double*)a, pcs, H, ldh, m, cs,
-                     sn, g, j, resid, act);
+  hipLaunchKernelGGL((k_cgs_scale_givens<R, BS>), grid, blk, 0, st, w, csw, N, (const double*)(two_pass ? a : b), pcs,
+                     H, ldh, m, cs, sn, g, j, resid, act);
 }
 
 // FP32 vectors: 1024-thread workgroups with FP32 per-thread sums (at most 128

@@ -202,12 +202,18 @@ void launch_sub_b(long N, const cx<R>* a, long csa, const cx<R>* b, long csb, cx
                   hipStream_t st);
 template <class R>
 void launch_zero_b(long N, cx<R>* x, long cs, int K, hipStream_t st);
-// Arnoldi step of K lock-step processes: classical Gram-Schmidt twice against
-// V_0..V_{k-1} (k <= 32), norm, scaling of w and Givens step j, in four launches;
+// Arnoldi step of K lock-step processes: classical Gram-Schmidt against
+// V_0..V_{k-1} (k <= 32; two passes for FP64 vectors, one for FP32), norm,
+// scaling of w and Givens step j, in four (three) launches;
 // pa, pb: two partial buffers of pcs >= ldh * nwg complex per column; nwg
 // workgroups of cgs_block_size<R>() threads per column
 template <class R>
 int cgs_block_size();
+// Gram-Schmidt passes of the Arnoldi step: two in FP64, one in FP32
+template <class R>
+constexpr bool cgs_two_pass() {
+  return sizeof(R) == 8;
+}
 template <class R>
 void launch_cgs_step(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, cx<double>* pa,
                      cx<double>* pb, long pcs, int nwg, cx<double>* hcol, long hcs, cx<double>* H, int ldh, int m,

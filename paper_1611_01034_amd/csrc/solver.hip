@@ -226,10 +226,12 @@ KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(co
       launch_multidot<R>(V, ld, j + 1, Vn, N, part, nwg, st);
       launch_reduce(part, j + 1, nwg, hcol, 0, st);
       launch_multi_axpy<R>(V, ld, j + 1, hcol, -1.0, Vn, N, st);
-      launch_multidot<R>(V, ld, j + 1, Vn, N, part, nwg, st);
-      launch_reduce(part, j + 1, nwg, ws.y.template as<cx<double>>(), 0, st);
-      launch_reduce(part, j + 1, nwg, hcol, 1, st);
-      launch_multi_axpy<R>(V, ld, j + 1, ws.y.template as<cx<double>>(), -1.0, Vn, N, st);
+      if (cgs_two_pass<R>()) {  // second classical Gram-Schmidt pass (FP64)
+        launch_multidot<R>(V, ld, j + 1, Vn, N, part, nwg, st);
+        launch_reduce(part, j + 1, nwg, ws.y.template as<cx<double>>(), 0, st);
+        launch_reduce(part, j + 1, nwg, hcol, 1, st);
+        launch_multi_axpy<R>(V, ld, j + 1, ws.y.template as<cx<double>>(), -1.0, Vn, N, st);
+      }
       norm_to(Vn, hcol + j + 1);
       launch_scale_by_inv<R>(Vn, hcol + j + 1, Vn, N, st);
       launch_givens(H, m + 1, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), ws.g.template as<cx<double>>(), j,
@@ -429,7 +431,8 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
       A(z, Vn, K);
       cx<double>* hcol = H + (long)j * ldh;
       if (j + 1 <= 32) {
-        // classical Gram-Schmidt twice, norm, scaling and Givens step in four launches
+        // classical Gram-Schmidt (two passes in FP64, one in FP32), norm, scaling
+        // and Givens step
         launch_cgs_step<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, part + (long)K * pcs, pcs, nwgf, hcol, hcs, H,
                            ldh, m, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), g, j,
                            ws.resid.template as<double>(), K, act, st);
@@ -437,10 +440,12 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
         launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
         launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 0, K, act, st);
         launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, hcol, hcs, -1.0, Vn, ld, N, K, act, st);
-        launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
-        launch_reduce_b(part, pcs, j + 1, nwg, y, ldh, 0, K, act, st);
-        launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 1, K, act, st);
-        launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, y, ldh, -1.0, Vn, ld, N, K, act, st);
+        if (cgs_two_pass<R>()) {
+          launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
+          launch_reduce_b(part, pcs, j + 1, nwg, y, ldh, 0, K, act, st);
+          launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 1, K, act, st);
+          launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, y, ldh, -1.0, Vn, ld, N, K, act, st);
+        }
         launch_multidot_b<R>(Vn, 0, ld, 1, Vn, ld, N, part, pcs, nwg, K, act, st);
         launch_reduce_b(part, pcs, 1, nwg, hcol + j + 1, hcs, 2, K, act, st);
         launch_scale_by_inv_b<R>(Vn, ld, hcol + j + 1, hcs, Vn, ld, N, K, act, 1, st);
