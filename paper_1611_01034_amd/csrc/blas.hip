@@ -677,11 +677,13 @@ __global__ void __launch_bounds__(BS) k_cgs_axpy_norm(const cx<R>* __restrict__ 
 
 // ||w_r|| from pa_r; workgroup 0 stores it as H_r[j+1][j] and takes Givens
 // step j (column j, rotations and g staged in LDS); every workgroup scales its
-// part of w_r by 1/||w_r|| (w_r zeroed for an inactive column)
+// part of w_r by 1/||w_r|| (w_r zeroed for an inactive column).  With
+// resid_host (pinned host memory) the residual estimate is also stored there.
 template <class R, int BS>
 __global__ void __launch_bounds__(BS) k_cgs_scale_givens(cx<R>* w, long csw, long N, const double* pa, long pcs,
                                                           cx<double>* H, int ldh, int m, double* cs, cx<double>* sn,
-                                                          cx<double>* g, int j, double* resid, const int* act) {
+                                                          cx<double>* g, int j, double* resid, double* resid_host,
+                                                          const int* act) {
   const int r = blockIdx.y;
   const long stride = (long)gridDim.x * BS;
   w += r * csw;
@@ -711,6 +713,7 @@ __global__ void __launch_bounds__(BS) k_cgs_scale_givens(cx<R>* w, long csw, lon
     __syncthreads();
     if (t == 0) {
       givens_col(hl, cl, sl, gl, j, resid + r);
+      if (resid_host) resid_host[r] = resid[r];
       // rotation j and the new g entries are the only state kept besides H
       cs[(long)r * m + j] = cl[j];
       sn[(long)r * m + j] = sl[j];
@@ -730,7 +733,8 @@ __global__ void __launch_bounds__(BS) k_cgs_scale_givens(cx<R>* w, long csw, lon
 template <class R, int BS>
 static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, double* a, double* b,
                         long pcs, int nwg, cx<double>* hcol, long hcs, cx<double>* H, int ldh, int m, double* cs,
-                        cx<double>* sn, cx<double>* g, int j, double* resid, int K, const int* act, hipStream_t st) {
+                        cx<double>* sn, cx<double>* g, int j, double* resid, double* resid_host, int K, const int* act,
+                        hipStream_t st) {
   const dim3 grid(nwg, K), blk(BS);
   constexpr bool two_pass = cgs_two_pass<R>();
   // the axpy kernels of 16 or more vectors hold twice the registers: half the
@@ -759,7 +763,7 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
   }
 #undef CGS_LAUNCH
   hipLaunchKernelGGL((k_cgs_scale_givens<R, BS>), grid, blk, 0, st, w, csw, N, (const double*)(two_pass ? a : b), pcs,
-                     H, ldh, m, cs, sn, g, j, resid, act);
+                     H, ldh, m, cs, sn, g, j, resid, resid_host, act);
 }
 
 // FP32 vectors: 1024-thread workgroups with FP32 per-thread sums (at most 128
@@ -771,20 +775,20 @@ int cgs_block_size() {
 template <class R>
 void launch_cgs_step(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, cx<double>* pa,
                      cx<double>* pb, long pcs, int nwg, cx<double>* hcol, long hcs, cx<double>* H, int ldh, int m,
-                     double* cs, cx<double>* sn, cx<double>* g, int j, double* resid, int K, const int* act,
-                     hipStream_t st) {
+                     double* cs, cx<double>* sn, cx<double>* g, int j, double* resid, double* resid_host, int K,
+                     const int* act, hipStream_t st) {
   double* a = reinterpret_cast<double*>(pa);
   double* b = reinterpret_cast<double*>(pb);
   if constexpr (sizeof(R) == 4)
-    cgs_step_bs<R, 1024>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, K, act, st);
+    cgs_step_bs<R, 1024>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, resid_host, K, act, st);
   else
-    cgs_step_bs<R, 256>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, K, act, st);
+    cgs_step_bs<R, 256>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, resid_host, K, act, st);
 }
 #define INST_CGS(R)                                                                                             \
   template int cgs_block_size<R>();                                                                               \
   template void launch_cgs_step<R>(const cx<R>*, long, long, int, cx<R>*, long, long, cx<double>*, cx<double>*,   \
                                    long, int, cx<double>*, long, cx<double>*, int, int, double*, cx<double>*,     \
-                                   cx<double>*, int, double*, int, const int*, hipStream_t);
+                                   cx<double>*, int, double*, double*, int, const int*, hipStream_t);
 INST_CGS(double)
 INST_CGS(float)
 

@@ -40,32 +40,45 @@ __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::el
   // one memory latency instead of two.
   using E = typename store_traits<S>::elem;
   const long base_s = fidx(g, B, s, 36);
-#pragma unroll 1
-  for (int mu = 0; mu < g.ndir; ++mu) {
+  auto issue = [&](int mu, E* lf, E* lb, int& sf, int& sb, bool& vf, bool& vb) {
     int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
+    vf = l[mu] + 1 < g.b[mu];
+    vb = l[mu] > 0;
     const int l0 = l[mu];
-    const bool vf = l0 + 1 < g.b[mu], vb = l0 > 0;
     l[mu] = l0 + 1;
-    const int snf = local_slot(g, l);
+    int snf = local_slot(g, l);
     l[mu] = l0 - 1;
-    const int snb = vb ? local_slot(g, l) : s;
-    const int sf = vf ? snf - lds_off : 0, sb = vb ? snb - lds_off : 0;
+    int snb = vb ? local_slot(g, l) : s;
+    sf = vf ? snf - lds_off : 0;
+    sb = vb ? snb - lds_off : 0;
     const long bf = base_s + (long)mu * 9 * TILE;
     const long bb = fidx(g, B, snb, 36) + (long)mu * 9 * TILE;
-    E lf[9], lb[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       lf[k] = U[bf + (long)k * TILE];
       lb[k] = U[bb + (long)k * TILE];
     }
+  };
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    E cf[9], cb[9];
+    int sf, sb;
+    bool vf, vb;
+    issue(mu, cf, cb, sf, sb, vf, vb);
     cx<R> psi[12], u[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = vf ? ld<R, S>(lf, k) : mk<R>(0, 0);
+    for (int k = 0; k < 9; ++k) {
+      cx<R> v = mk<R>((R)cf[k].re, (R)cf[k].im);
+      u[k] = vf ? v : mk<R>(0, 0);
+    }
 #pragma unroll
     for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sf] : lds[c * g.half + sf];
     hop_accum<0>(mu, psi, u, out);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = vb ? ld<R, S>(lb, k) : mk<R>(0, 0);
+    for (int k = 0; k < 9; ++k) {
+      cx<R> v = mk<R>((R)cb[k].re, (R)cb[k].im);
+      u[k] = vb ? v : mk<R>(0, 0);
+    }
 #pragma unroll
     for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sb] : lds[c * g.half + sb];
     hop_accum<1>(mu, psi, u, out);

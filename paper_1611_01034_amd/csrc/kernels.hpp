@@ -206,7 +206,8 @@ void launch_zero_b(long N, cx<R>* x, long cs, int K, hipStream_t st);
 // V_0..V_{k-1} (k <= 32; two passes for FP64 vectors, one for FP32), norm,
 // scaling of w and Givens step j, in four (three) launches;
 // pa, pb: two partial buffers of pcs >= ldh * nwg complex per column; nwg
-// workgroups of cgs_block_size<R>() threads per column
+// workgroups of cgs_block_size<R>() threads per column; resid_host (pinned host
+// memory, may be null) receives a copy of the K residual estimates
 template <class R>
 int cgs_block_size();
 // Gram-Schmidt passes of the Arnoldi step: two in FP64, one in FP32
@@ -217,8 +218,8 @@ constexpr bool cgs_two_pass() {
 template <class R>
 void launch_cgs_step(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, cx<double>* pa,
                      cx<double>* pb, long pcs, int nwg, cx<double>* hcol, long hcs, cx<double>* H, int ldh, int m,
-                     double* cs, cx<double>* sn, cx<double>* g, int j, double* resid, int K, const int* act,
-                     hipStream_t st);
+                     double* cs, cx<double>* sn, cx<double>* g, int j, double* resid, double* resid_host, int K,
+                     const int* act, hipStream_t st);
 void launch_givens_b(cx<double>* H, int ldh, int m, double* cs, cx<double>* sn, cx<double>* g, int j, double* resid,
                      int K, const int* act, hipStream_t st);
 void launch_trisolve_b(const cx<double>* H, int ldh, int m, const cx<double>* g, cx<double>* y, const int* jd, int K,

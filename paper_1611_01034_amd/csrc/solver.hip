@@ -315,7 +315,8 @@ void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex) {
   act.ensure(sizeof(int) * K);
   jd.ensure(sizeof(int) * K);
   if (!h_resid) {
-    HIP_CHECK(hipHostMalloc((void**)&h_resid, sizeof(double) * 96, hipHostMallocDefault));
+    // coherent: the Arnoldi kernels store residual estimates here directly
+    HIP_CHECK(hipHostMalloc((void**)&h_resid, sizeof(double) * 96, hipHostMallocCoherent));
     HIP_CHECK(hipHostMalloc((void**)&h_scal, sizeof(cx<double>) * 4 * 64, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void**)&h_act, sizeof(int) * 64, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void**)&h_jd, sizeof(int) * 64, hipHostMallocDefault));
@@ -433,9 +434,11 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
       if (j + 1 <= 32) {
         // classical Gram-Schmidt (two passes in FP64, one in FP32), norm, scaling
         // and Givens step
+        // the look-ahead estimate goes straight to its pinned slot (no copy launch)
         launch_cgs_step<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, part + (long)K * pcs, pcs, nwgf, hcol, hcs, H,
                            ldh, m, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), g, j,
-                           ws.resid.template as<double>(), K, act, st);
+                           ws.resid.template as<double>(), lookahead ? ws.h_resid + 32 * (j % NSLOT) : nullptr, K,
+                           act, st);
       } else {
         launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
         launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 0, K, act, st);
@@ -461,7 +464,8 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
         }
       if (lookahead) {
         const int slot = j % NSLOT;
-        HIP_CHECK(hipMemcpyAsync(ws.h_resid + 32 * slot, ws.resid.p, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+        if (j + 1 > 32)
+          HIP_CHECK(hipMemcpyAsync(ws.h_resid + 32 * slot, ws.resid.p, sizeof(double) * K, hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipEventRecord(ws.ready[slot], st));
         for (int k = 0; k < K; ++k) act_at[slot][k] = ws.h_act[k];
         last = j;
