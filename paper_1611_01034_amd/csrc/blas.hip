@@ -493,9 +493,43 @@ __global__ void k_trisolve_b(const cx<double>* H, int ldh, int m, const cx<doubl
     yr[i] = dn > 0 ? (1.0 / dn) * (s * conj(d)) : mk(0.0, 0.0);
   }
 }
+// the same for m <= 32: one workgroup per column, the triangle staged in LDS
+// with all loads in flight, then column-oriented substitution (after y_k,
+// every row t < k takes s_t -= H[t][k] y_k in parallel)
+__global__ void __launch_bounds__(64) k_trisolve_lds_b(const cx<double>* __restrict__ H, int ldh, int m,
+                                                       const cx<double>* __restrict__ g, cx<double>* __restrict__ y,
+                                                       const int* __restrict__ jd) {
+  __shared__ cx<double> Hs[32][33];  // Hs[k][i] = H[i][k] (column k of the triangle)
+  __shared__ cx<double> sv[32], yv[32];
+  const int r = blockIdx.x, t = threadIdx.x;
+  const cx<double>* Hr = H + (long)r * ldh * m;
+  const cx<double>* gr = g + (long)r * ldh;
+  cx<double>* yr = y + (long)r * ldh;
+  const int j = jd[r];
+  for (int q = t; q < j * 32; q += 64) {
+    const int k = q >> 5, i = q & 31;
+    if (i <= k) Hs[k][i] = Hr[(long)k * ldh + i];
+  }
+  if (t < j) sv[t] = gr[t];
+  __syncthreads();
+  for (int k = j - 1; k >= 0; --k) {
+    if (t == 0) {
+      const cx<double> d = Hs[k][k];
+      const double dn = norm2(d);
+      yv[k] = dn > 0 ? (1.0 / dn) * (sv[k] * conj(d)) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (t < k) sv[t] = sv[t] - Hs[k][t] * yv[k];
+    __syncthreads();
+  }
+  for (int i = t; i <= m; i += 64) yr[i] = i < j ? yv[i] : mk(0.0, 0.0);
+}
 void launch_trisolve_b(const cx<double>* H, int ldh, int m, const cx<double>* g, cx<double>* y, const int* jd, int K,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_trisolve_b, dim3(1), dim3(64), 0, st, H, ldh, m, g, y, jd, K);
+  if (m <= 32)
+    hipLaunchKernelGGL(k_trisolve_lds_b, dim3(K), dim3(64), 0, st, H, ldh, m, g, y, jd);
+  else
+    hipLaunchKernelGGL(k_trisolve_b, dim3(1), dim3(64), 0, st, H, ldh, m, g, y, jd, K);
 }
 
 // g_r = 0 except g_r[0] = s_r  (start of a cycle)

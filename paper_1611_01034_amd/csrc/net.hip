@@ -170,7 +170,7 @@ void launch_net_pack(int C, const cx<float>* W, float* P, hipStream_t st) {
 }
 
 template <int RT>
-__global__ void __launch_bounds__(256) k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U,
                                                       const cx<float>* __restrict__ in, const float* __restrict__ P,
                                                       cx<float>* __restrict__ out) {
   constexpr int C = 4 * RT, NCH = C / 8;
