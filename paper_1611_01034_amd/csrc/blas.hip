@@ -788,7 +788,11 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
                          (const double*)a, b, pcs, hcol, hcs, act);                                                    \
     }                                                                                                                  \
   }
-  if (k <= 8) {
+  if (k <= 2) {
+    CGS_LAUNCH(2)
+  } else if (k <= 4) {
+    CGS_LAUNCH(4)
+  } else if (k <= 8) {
     CGS_LAUNCH(8)
   } else if (k <= 16) {
     CGS_LAUNCH(16)
