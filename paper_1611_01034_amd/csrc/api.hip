@@ -733,16 +733,17 @@ void net_forward(Ctx& c) {
 // `in` holds the input and is overwritten; returns the buffer with the output
 cx<float>* net_infer(Ctx& c, cx<float>* in, cx<float>* tmp) {
   NetState& n = c.net;
-  // matrix cores when the channel count and the lattice allow (FP32 products)
-  const bool mf = n.C % 8 == 0 && c.g.V % 64 == 0;
-  const long per = 9L * n.C * n.C * 16 * 2;
+  // matrix cores when the channel count and the lattice allow (FP32 accuracy
+  // from split BF16 products)
+  const bool mf = n.C % 8 == 0 && n.C <= 24 && c.g.V % 64 == 0;
+  const long per = net_packed_bytes(n.C) / (long)sizeof(bf16);
   if (mf) {
-    n.packed.ensure(sizeof(float) * per * n.L);
-    for (int l = 0; l < n.L; ++l) launch_net_pack(n.C, n.W(l), n.packed.as<float>() + l * per, c.st);
+    n.packed.ensure(sizeof(bf16) * per * n.L);
+    for (int l = 0; l < n.L; ++l) launch_net_pack(n.C, n.W(l), n.packed.as<bf16>() + l * per, c.st);
   }
   for (int l = 0; l < n.L; ++l) {
     if (mf)
-      launch_net_mix_mfma(c.g, n.C, c.U32.as<cx<float>>(), in, n.packed.as<float>() + l * per, tmp, c.st);
+      launch_net_mix_mfma(c.g, n.C, c.U32.as<cx<float>>(), in, n.packed.as<bf16>() + l * per, tmp, c.st);
     else
       launch_net_mix(c.g, n.C, c.U32.as<cx<float>>(), in, n.W(l), tmp, false, c.st);
     if (l < n.L - 1) launch_net_gate_inplace(c.g, n.C, n.ab(l), n.ab(l) + n.C, tmp, c.st);

@@ -144,9 +144,11 @@ void launch_net_mix(const Geom& g, int C, const cx<float>* U, const cx<float>* i
 void launch_net_gate(const Geom& g, int C, const cx<float>* z, const float* a, const float* b, cx<float>* y, float* sv,
                      hipStream_t st);
 // the forward mixing layer on the matrix cores (inference; C = 8, 16, 24): the
-// layer's weights packed once by launch_net_pack (9 * C * C * 16 * 2 floats)
-void launch_net_pack(int C, const cx<float>* W, float* P, hipStream_t st);
-void launch_net_mix_mfma(const Geom& g, int C, const cx<float>* U, const cx<float>* in, const float* P,
+// layer's weights split into three BF16 parts and packed once by
+// launch_net_pack (net_packed_bytes(C) bytes per layer)
+inline long net_packed_bytes(int C) { return 9L * C * C * 192; }
+void launch_net_pack(int C, const cx<float>* W, bf16* P, hipStream_t st);
+void launch_net_mix_mfma(const Geom& g, int C, const cx<float>* U, const cx<float>* in, const bf16* P,
                          cx<float>* out, hipStream_t st);
 void launch_net_gate_inplace(const Geom& g, int C, const float* a, const float* b, cx<float>* z, hipStream_t st);
 void launch_net_gate_bwd(const Geom& g, int C, const cx<float>* Gy, const cx<float>* z, const float* sv,

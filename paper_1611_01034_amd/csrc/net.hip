@@ -131,48 +131,69 @@ __global__ void __launch_bounds__(256) k_net_mix(Geom g, const cx<float>* __rest
 // The mixing layer on the matrix cores (inference).  Per site and colour k the
 // layer is z[(c,s)] = sum_{(d,c',t)} W[d][c][c'][s][t] (T_d x_{c'})[t][k]: a
 // complex matrix of 4C rows (c,s) and 9*4C columns (d,c',t) times one column
-// per (site, colour).  It runs as a real FP32 product with the embedding
+// per (site, colour).  It runs as a real product with the embedding
 //   A[i][(l,0)] = Re W_il, A[i][(l,1)] = Im W_il,
 //   B[(l,0)][(col,0)] = Re v, B[(l,1)][(col,0)] = -Im v, B[(l,0)][(col,1)] = Im v,
-//   B[(l,1)][(col,1)] = Re v,
-// on v_mfma_f32_16x16x4f32 (lane L: A[L%16][L/16], B[L/16][L%16], result
-// rows 4(L/16)+e, column L%16): FP32 products and sums, like the VALU kernel,
-// in another order.  A workgroup takes 64 sites, wavefront w sites 16w..16w+15
-// (96 real columns: 6 tiles); the transported inputs of 8 channels of one
-// offset are staged in LDS per step as in the VALU kernel.  The weights are
-// packed once per layer in fragment order (k_net_pack): one contiguous 256 B
-// load per A fragment.
+//   B[(l,1)][(col,1)] = Re v.
+// FP32 accuracy on the BF16 matrix cores: every FP32 operand x is split into
+// three BF16 parts x = x0 + x1 + x2 (x0 = bf16(x), x1 = bf16(x - x0),
+// x2 = bf16(x - x0 - x1), 24 significant bits together), and a*b is summed as
+// the six products a_i b_j with i + j <= 2; the dropped terms are below
+// 2^-24 |a b|, the products are exact in FP32 and the sums are FP32 (the
+// same rounding level as the FP32 VALU kernel, in another order).  That is
+// six v_mfma_f32_16x16x32_bf16 per 32 inner terms against eight
+// v_mfma_f32_16x16x4f32 for the same terms in FP32, at 16 times the rate.
+// Fragments (wave64): lane L holds A[L%16][8(L/16) + e] and B[8(L/16) + e][L%16]
+// (e < 8); the result D[4(L/16) + e][L%16] (e < 4).
+// A workgroup takes 64 sites, wavefront w sites 16w..16w+15 (96 real columns:
+// 6 tiles); the transported inputs of 8 channels of one offset are staged in
+// LDS per chunk as in the VALU kernel.  The weights are split and packed once
+// per layer in fragment order (k_net_pack): one 16 B load per A fragment part.
 typedef float v4f_n __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf_n __attribute__((ext_vector_type(8)));
 
-// packed[((chunk * 16 + step) * RT + t) * 64 + lane], chunk = d * (C/8) + k0/8
-__global__ void k_net_pack(int C, const cx<float>* __restrict__ W, float* __restrict__ P) {
+__device__ __forceinline__ void split3(float x, __bf16& x0, __bf16& x1, __bf16& x2) {
+  x0 = (__bf16)x;
+  const float r = x - (float)x0;
+  x1 = (__bf16)r;
+  x2 = (__bf16)(r - (float)x1);
+}
+
+// packed[(((chunk * 2 + ks) * RT + t) * 3 + part) * 64 + lane][e] (BF16),
+// chunk = d * (C/8) + k0/8; entry = part `part` of A[16t + lane%16][32 ks + 8 (lane/16) + e]
+__global__ void k_net_pack(int C, const cx<float>* __restrict__ W, __bf16* __restrict__ P) {
   const int RT = C / 4, nch = C / 8;
-  const long total = 9L * nch * 16 * RT * 64;
+  const long total = 9L * nch * 2 * RT * 3 * 64 * 8;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int lane = (int)(e & 63);
-    long r = e >> 6;
+    const int e8 = (int)(e & 7);
+    const int lane = (int)((e >> 3) & 63);
+    long r = e >> 9;
+    const int part = (int)(r % 3);
+    r /= 3;
     const int t = (int)(r % RT);
     r /= RT;
-    const int step = (int)(r & 15);
-    const int chunk = (int)(r >> 4);
+    const int ks = (int)(r & 1);
+    const int chunk = (int)(r >> 1);
     const int d = chunk / nch, k0 = (chunk % nch) * 8;
-    const int i = 16 * t + (lane & 15);           // row (c, s)
-    const int q = 4 * step + (lane >> 4);          // real inner index in the chunk
-    const int l = q >> 1, cp = q & 1;              // complex inner (c', t), part
+    const int i = 16 * t + (lane & 15);               // row (c, s)
+    const int q = 32 * ks + 8 * (lane >> 4) + e8;      // real inner index in the chunk
+    const int l = q >> 1, cp = q & 1;                  // complex inner (c', t), part
     const int ci = k0 + (l >> 2), tt = l & 3;
     const int co = i >> 2, sp = i & 3;
-    cx<float> w = W[((long)(d * C + co) * C + ci) * 16 + sp * 4 + tt];
-    P[e] = cp == 0 ? w.re : w.im;
+    const cx<float> w = W[((long)(d * C + co) * C + ci) * 16 + sp * 4 + tt];
+    __bf16 x[3];
+    split3(cp == 0 ? w.re : w.im, x[0], x[1], x[2]);
+    P[e] = x[part];
   }
 }
-void launch_net_pack(int C, const cx<float>* W, float* P, hipStream_t st) {
+void launch_net_pack(int C, const cx<float>* W, __bf16* P, hipStream_t st) {
   hipLaunchKernelGGL(k_net_pack, dim3(256), dim3(256), 0, st, C, W, P);
 }
 
 template <int RT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U,
-                                                      const cx<float>* __restrict__ in, const float* __restrict__ P,
-                                                      cx<float>* __restrict__ out) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U, const cx<float>* __restrict__ in,
+               const v8bf_n* __restrict__ P, cx<float>* __restrict__ out) {
   constexpr int C = 4 * RT, NCH = C / 8;
   __shared__ cx<float> txs[8][12][64];
   const int t = threadIdx.x, lane = t & 63;
@@ -189,6 +210,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   for (int chunk = 0; chunk < 9 * NCH; ++chunk) {
     const int d = chunk / NCH, k0 = (chunk % NCH) * 8;
     __syncthreads();
+#pragma unroll 1
     for (int p = t; p < 64 * 8; p += 256) {
       int i = p & 63, ch = p >> 6;
       long gs = (long)blockIdx.x * 64 + i;
@@ -199,25 +221,64 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
       for (int c = 0; c < 12; ++c) txs[ch][c][i] = v[c];
     }
     __syncthreads();
-    const float* Pc = P + (long)chunk * 16 * RT * 64 + lane;
-#pragma unroll 2
-    for (int step = 0; step < 16; ++step) {
-      const int q = 4 * step + kk;
-      const int l = q >> 1, cp = q & 1;
-      const int ch = l >> 2, tt = l & 3;
-      float bf[6];
+#pragma unroll 1
+    for (int ks = 0; ks < 2; ++ks) {
+      // B fragments: lane's inner terms 32 ks + 8 kk + e = (channel 4 ks + kk,
+      // spin e/2, part e%2)
+      const int ch = 4 * ks + kk;
+      const v8bf_n* Pc = P + (long)(chunk * 2 + ks) * RT * 3 * 64 + lane;
+      // three column tiles per pass; within a pass the A parts of row tile a+1
+      // are loaded while tile a multiplies, and the compiler barrier keeps the
+      // loads of later tiles from being hoisted (registers: 144 accumulators)
 #pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        const int j = 16 * u + (lane & 15);
-        const int c = j & 1, k = (j >> 1) % 3, site = (j >> 1) / 3;
-        cx<float> v = txs[ch][3 * tt + k][16 * w + site];
-        bf[u] = cp == 0 ? (c == 0 ? v.re : v.im) : (c == 0 ? -v.im : v.re);
-      }
+      for (int uh = 0; uh < 2; ++uh) {
+        v8bf_n b0[3], b1[3], b2[3];
 #pragma unroll
-      for (int a = 0; a < RT; ++a) {
-        const float af = Pc[(step * RT + a) * 64];
+        for (int uu = 0; uu < 3; ++uu) {
+          const int j = 16 * (3 * uh + uu) + (lane & 15);
+          const int c = j & 1, k = (j >> 1) % 3, site = (j >> 1) / 3;
 #pragma unroll
-        for (int u = 0; u < 6; ++u) acc[a][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[u], acc[a][u], 0, 0, 0);
+          for (int tt = 0; tt < 4; ++tt) {
+            const cx<float> v = txs[ch][3 * tt + k][16 * w + site];
+            __bf16 h, m, lo;
+            split3(c == 0 ? v.re : v.im, h, m, lo);
+            b0[uu][2 * tt] = h;
+            b1[uu][2 * tt] = m;
+            b2[uu][2 * tt] = lo;
+            split3(c == 0 ? -v.im : v.re, h, m, lo);
+            b0[uu][2 * tt + 1] = h;
+            b1[uu][2 * tt + 1] = m;
+            b2[uu][2 * tt + 1] = lo;
+          }
+        }
+        v8bf_n a0 = Pc[0], a1 = Pc[64], a2 = Pc[128];
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          v8bf_n n0 = a0, n1 = a1, n2 = a2;
+          if (a + 1 < RT) {
+            n0 = Pc[((a + 1) * 3 + 0) * 64];
+            n1 = Pc[((a + 1) * 3 + 1) * 64];
+            n2 = Pc[((a + 1) * 3 + 2) * 64];
+          }
+          v4f_n* ac = acc[a] + 3 * uh;
+          // smallest terms first; the column tiles interleave the dependent products
+#pragma unroll
+          for (int uu = 0; uu < 3; ++uu) ac[uu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0[uu], ac[uu], 0, 0, 0);
+#pragma unroll
+          for (int uu = 0; uu < 3; ++uu) ac[uu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[uu], ac[uu], 0, 0, 0);
+#pragma unroll
+          for (int uu = 0; uu < 3; ++uu) ac[uu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2[uu], ac[uu], 0, 0, 0);
+#pragma unroll
+          for (int uu = 0; uu < 3; ++uu) ac[uu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0[uu], ac[uu], 0, 0, 0);
+#pragma unroll
+          for (int uu = 0; uu < 3; ++uu) ac[uu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1[uu], ac[uu], 0, 0, 0);
+#pragma unroll
+          for (int uu = 0; uu < 3; ++uu) ac[uu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[uu], ac[uu], 0, 0, 0);
+          asm volatile("" ::: "memory");
+          a0 = n0;
+          a1 = n1;
+          a2 = n2;
+        }
       }
     }
   }
@@ -240,13 +301,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   }
 }
 
-void launch_net_mix_mfma(const Geom& g, int C, const cx<float>* U, const cx<float>* in, const float* P,
+void launch_net_mix_mfma(const Geom& g, int C, const cx<float>* U, const cx<float>* in, const __bf16* P,
                          cx<float>* out, hipStream_t st) {
   dim3 grid((unsigned)(g.V / 64));
+  const v8bf_n* Pv = reinterpret_cast<const v8bf_n*>(P);
   switch (C) {
-    case 8: hipLaunchKernelGGL((k_net_mix_mfma<2>), grid, dim3(256), 0, st, g, U, in, P, out); break;
-    case 16: hipLaunchKernelGGL((k_net_mix_mfma<4>), grid, dim3(256), 0, st, g, U, in, P, out); break;
-    case 24: hipLaunchKernelGGL((k_net_mix_mfma<6>), grid, dim3(256), 0, st, g, U, in, P, out); break;
+    case 8: hipLaunchKernelGGL((k_net_mix_mfma<2>), grid, dim3(256), 0, st, g, U, in, Pv, out); break;
+    case 16: hipLaunchKernelGGL((k_net_mix_mfma<4>), grid, dim3(256), 0, st, g, U, in, Pv, out); break;
+    case 24: hipLaunchKernelGGL((k_net_mix_mfma<6>), grid, dim3(256), 0, st, g, U, in, Pv, out); break;
     default: throw Error(INVALID_ARG, "matrix-core network layer needs 8, 16 or 24 channels");
   }
 }
