@@ -371,8 +371,10 @@ void launch_qr_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, co
 // Galerkin assembly of the next coarse operator from a coarse level, FP64.
 // One workgroup per (aggregate A, kind): kind 0 = self (site blocks + links
 // inside A), kind 1+mu = forward block (links across the upper mu face).
-// q = Q(c) staged per site; W = (operator block) * Q(y) per half of the
-// output columns.
+// q = Q(c) staged per site, Q(y) staged per piece; W = (operator block) * Q(y)
+// per half of the output columns, one thread per (component k, group of 8
+// vectors): each operator entry is loaded once (all loads in flight) and used
+// for the 8 vectors from LDS.
 template <class RQ>
 __global__ void __launch_bounds__(256) k_assemble_coarse(CGeom cg, int Nv, int a0, int a1, int a2, int a3,
                                                          const int* __restrict__ agg_sites,
@@ -386,12 +388,14 @@ __global__ void __launch_bounds__(256) k_assemble_coarse(CGeom cg, int Nv, int a
   extern __shared__ char smem_raw[];
   cx<double>* q = reinterpret_cast<cx<double>*>(smem_raw);  // q[i][k] = Q_i(c)[k]
   cx<double>* W = q + Nv * n;                                 // W[i][k] for output columns of one half
-  int A = blockIdx.x / 5, kind = blockIdx.x % 5;
+  cx<double>* qy = W + Nv * n;                                // qy[i][k] = Q_i(y)[k]
+  // workgroup = (aggregate, kind, half hc of the output columns)
+  const int A = blockIdx.x / 10, kind = (blockIdx.x % 10) >> 1, hc = blockIdx.x & 1;
   int t = threadIdx.x;
-  const int nent = np * np;
-  cx<double> accS[16], accX[16];
+  const int nent = np * np, nh = Nv * np;  // entries per column half: e = hc nh + t + 256 m
+  cx<double> accS[8], accX[8];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) accS[m] = accX[m] = mk(0.0, 0.0);
+  for (int m = 0; m < 8; ++m) accS[m] = accX[m] = mk(0.0, 0.0);
   for (int j = 0; j < asz; ++j) {
     int l[4];
     {
@@ -426,32 +430,43 @@ __global__ void __launch_bounds__(256) k_assemble_coarse(CGeom cg, int Nv, int a
         blk = ((long)c * 5 + 1 + piece) * nn;
       }
       bool toX = (kind == 0 && piece >= 0);
-      for (int hc = 0; hc < 2; ++hc) {
+      __syncthreads();
+      for (int e = t; e < Nv * n; e += 256) {
+        int i = e / n, k = e - i * n;
+        cx<RQ> v = Q[(long)i * qstride + (long)y * n + k];
+        qy[e] = mk<double>(v.re, v.im);
+      }
+      {
         __syncthreads();
         // W[i][k] = sum_{k2 in half hc} B[k][k2] Q_i(y)[k2]
-        for (int e = t; e < Nv * n; e += 256) {
-          int i = e / n, k = e - i * n;
-          cx<double> acc = mk(0.0, 0.0);
+        const int ng = (Nv + 7) / 8;
+        for (int task = t; task < n * ng; task += 256) {
+          const int k = task % n, i0 = 8 * (task / n);
+          cx<double> acc[8];
+#pragma unroll
+          for (int ii = 0; ii < 8; ++ii) acc[ii] = mk(0.0, 0.0);
+#pragma unroll 4
           for (int k2 = hc * hn; k2 < (hc + 1) * hn; ++k2) {
-            cx<RQ> qv = Q[(long)i * qstride + (long)y * n + k2];
-            cmac(acc, D[blk + (long)k2 * n + k], mk<double>(qv.re, qv.im));
+            const cx<double> d = D[blk + (long)k2 * n + k];
+#pragma unroll
+            for (int ii = 0; ii < 8; ++ii)
+              if (i0 + ii < Nv) cmac(acc[ii], d, qy[(i0 + ii) * n + k2]);
           }
-          W[e] = acc;
+#pragma unroll
+          for (int ii = 0; ii < 8; ++ii)
+            if (i0 + ii < Nv) W[(i0 + ii) * n + k] = acc[ii];
         }
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-          int e = t + 256 * m;
-          if (e < nent) {
-            int col = e / np, row = e - col * np;
-            if ((col >= Nv ? 1 : 0) == hc) {
-              int ic = col - hc * Nv;
-              int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
-              cx<double> acc = mk(0.0, 0.0);
-              for (int k = hr * hn; k < (hr + 1) * hn; ++k) cjmac(acc, q[ir * n + k], W[ic * n + k]);
-              if (toX) accX[m] += acc;
-              else accS[m] += acc;
-            }
+        for (int m = 0; m < 8; ++m) {
+          const int eh = t + 256 * m;
+          if (eh < nh) {
+            const int ic = eh / np, row = eh - ic * np;
+            const int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
+            cx<double> acc = mk(0.0, 0.0);
+            for (int k = hr * hn; k < (hr + 1) * hn; ++k) cjmac(acc, q[ir * n + k], W[ic * n + k]);
+            if (toX) accX[m] += acc;
+            else accS[m] += acc;
           }
         }
       }
@@ -459,9 +474,10 @@ __global__ void __launch_bounds__(256) k_assemble_coarse(CGeom cg, int Nv, int a
   }
   cx<double>* out = Dn + ((long)A * 5 + kind) * nent;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    int e = t + 256 * m;
-    if (e < nent) {
+  for (int m = 0; m < 8; ++m) {
+    const int eh = t + 256 * m;
+    if (eh < nh) {
+      const int e = hc * nh + eh;
       out[e] = accS[m] + accX[m];
       if (kind == 0) Xs[(long)A * nent + e] = accX[m];
     }
@@ -471,8 +487,9 @@ template <class RQ>
 void launch_assemble_coarse(const CGeom& cg, int Nv, int nagg, const int ab[4], const int* agg_sites,
                             const cx<double>* D, const cx<RQ>* Q, long qstride, cx<double>* Dn, cx<double>* Xs,
                             hipStream_t st) {
-  size_t sm = 2 * (size_t)Nv * cg.n * sizeof(cx<double>);
-  hipLaunchKernelGGL(k_assemble_coarse<RQ>, dim3(5 * nagg), dim3(256), sm, st, cg, Nv, ab[0], ab[1], ab[2], ab[3],
+  size_t sm = 3 * (size_t)Nv * cg.n * sizeof(cx<double>);
+  if (Nv > 32) throw Error(INVALID_ARG, "coarse assembly supports Nv <= 32");
+  hipLaunchKernelGGL(k_assemble_coarse<RQ>, dim3(10 * nagg), dim3(256), sm, st, cg, Nv, ab[0], ab[1], ab[2], ab[3],
                      agg_sites, D, Q, qstride, Dn, Xs);
 }
 
