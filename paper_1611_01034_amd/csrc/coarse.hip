@@ -386,8 +386,9 @@ __global__ void __launch_bounds__(256) k_assemble_coarse(CGeom cg, int Nv, int a
   const int asz = a0 * a1 * a2 * a3;
   const int ab[4] = {a0, a1, a2, a3};
   extern __shared__ char smem_raw[];
-  cx<double>* q = reinterpret_cast<cx<double>*>(smem_raw);  // q[i][k] = Q_i(c)[k]
-  cx<double>* W = q + Nv * n;                                 // W[i][k] for output columns of one half
+  // q rows padded to n + 1 entries: the output sums read 32 rows at one k
+  cx<double>* q = reinterpret_cast<cx<double>*>(smem_raw);  // q[i][k] = Q_i(c)[k] at i (n + 1) + k
+  cx<double>* W = q + Nv * (n + 1);                           // W[i][k] for output columns of one half
   cx<double>* qy = W + Nv * n;                                // qy[i][k] = Q_i(y)[k]
   // workgroup = (aggregate, kind, half hc of the output columns)
   const int A = blockIdx.x / 10, kind = (blockIdx.x % 10) >> 1, hc = blockIdx.x & 1;
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(256) k_assemble_coarse(CGeom cg, int Nv, int a
     for (int e = t; e < Nv * n; e += 256) {
       int i = e / n, k = e - i * n;
       cx<RQ> v = Q[(long)i * qstride + (long)c * n + k];
-      q[e] = mk<double>(v.re, v.im);
+      q[i * (n + 1) + k] = mk<double>(v.re, v.im);
     }
     // pieces: piece -1 = site block, piece mu = forward link in direction mu
     for (int piece = -1; piece < 4; ++piece) {
@@ -464,7 +465,7 @@ __global__ void __launch_bounds__(256) k_assemble_coarse(CGeom cg, int Nv, int a
             const int ic = eh / np, row = eh - ic * np;
             const int hr = row >= Nv ? 1 : 0, ir = row - hr * Nv;
             cx<double> acc = mk(0.0, 0.0);
-            for (int k = hr * hn; k < (hr + 1) * hn; ++k) cjmac(acc, q[ir * n + k], W[ic * n + k]);
+            for (int k = hr * hn; k < (hr + 1) * hn; ++k) cjmac(acc, q[ir * (n + 1) + k], W[ic * n + k]);
             if (toX) accX[m] += acc;
             else accS[m] += acc;
           }
@@ -487,7 +488,7 @@ template <class RQ>
 void launch_assemble_coarse(const CGeom& cg, int Nv, int nagg, const int ab[4], const int* agg_sites,
                             const cx<double>* D, const cx<RQ>* Q, long qstride, cx<double>* Dn, cx<double>* Xs,
                             hipStream_t st) {
-  size_t sm = 3 * (size_t)Nv * cg.n * sizeof(cx<double>);
+  size_t sm = (3 * (size_t)Nv * cg.n + Nv) * sizeof(cx<double>);
   if (Nv > 32) throw Error(INVALID_ARG, "coarse assembly supports Nv <= 32");
   hipLaunchKernelGGL(k_assemble_coarse<RQ>, dim3(10 * nagg), dim3(256), sm, st, cg, Nv, ab[0], ab[1], ab[2], ab[3],
                      agg_sites, D, Q, qstride, Dn, Xs);
