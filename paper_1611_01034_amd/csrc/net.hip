@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(256) k_net_mix(Geom g, const cx<float>* __rest
 // Fragments (wave64): lane L holds A[L%16][8(L/16) + e] and B[8(L/16) + e][L%16]
 // (e < 8); the result D[4(L/16) + e][L%16] (e < 4).
 // A workgroup takes 64 sites, wavefront w sites 16w..16w+15 (96 real columns:
-// 6 tiles); the transported inputs of 8 channels of one offset are staged in
-// LDS per chunk as in the VALU kernel.  The weights are split and packed once
+// 6 tiles, each one colour and 8 consecutive sites); the transported inputs of
+// 8 channels of one offset are staged in LDS per chunk as in the VALU kernel.  The weights are split and packed once
 // per layer in fragment order (k_net_pack): one 16 B load per A fragment part.
 typedef float v4f_n __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf_n __attribute__((ext_vector_type(8)));
@@ -195,7 +195,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U, const cx<float>* __restrict__ in,
                const v8bf_n* __restrict__ P, cx<float>* __restrict__ out) {
   constexpr int C = 4 * RT, NCH = C / 8;
-  __shared__ cx<float> txs[8][12][64];
+  // transported inputs [channel][component][site]; the channel stride is padded
+  // by 8 entries so that the four channel groups of a wavefront read disjoint banks
+  constexpr int TXC = 12 * 64 + 8;
+  __shared__ cx<float> txs[8 * TXC];
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const long fl = g.V * 12;
@@ -204,7 +207,8 @@ k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U, const cx<float>* __restr
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int u = 0; u < 6; ++u) acc[a][u] = v4f_n{0.f, 0.f, 0.f, 0.f};
-  // this lane's B columns: j = 16u + lane%16 = c + 2 (k + 3 site), site in 0..15 of the wave
+  // this lane's B column in tile u: colour k = u/2, site 8 (u%2) + (lane%16)/2 of
+  // the wave's 16, part c = lane%2 (8 consecutive sites per tile and colour)
   const int kk = lane >> 4;
 #pragma unroll 1
   for (int chunk = 0; chunk < 9 * NCH; ++chunk) {
@@ -218,7 +222,7 @@ k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U, const cx<float>* __restr
       cx<float> v[12];
       transport_site(g, U, in + (long)(k0 + ch) * fl, d, Bi, si, v);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) txs[ch][c][i] = v[c];
+      for (int c = 0; c < 12; ++c) txs[ch * TXC + c * 64 + i] = v[c];
     }
     __syncthreads();
 #pragma unroll 1
@@ -235,11 +239,11 @@ k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U, const cx<float>* __restr
         v8bf_n b0[3], b1[3], b2[3];
 #pragma unroll
         for (int uu = 0; uu < 3; ++uu) {
-          const int j = 16 * (3 * uh + uu) + (lane & 15);
-          const int c = j & 1, k = (j >> 1) % 3, site = (j >> 1) / 3;
+          const int u = 3 * uh + uu;
+          const int c = lane & 1, k = u >> 1, site = 8 * (u & 1) + ((lane & 15) >> 1);
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt) {
-            const cx<float> v = txs[ch][3 * tt + k][16 * w + site];
+            const cx<float> v = txs[ch * TXC + (3 * tt + k) * 64 + 16 * w + site];
             __bf16 h, m, lo;
             split3(c == 0 ? v.re : v.im, h, m, lo);
             b0[uu][2 * tt] = h;
@@ -282,11 +286,10 @@ k_net_mix_mfma(Geom g, const cx<float>* __restrict__ U, const cx<float>* __restr
       }
     }
   }
-  // rows 16a + 4 kk + e = (c, s) = (i/4, i%4); column j -> (site, colour, part)
+  // rows 16a + 4 kk + e = (c, s) = (i/4, i%4); column -> (site, colour, part) as above
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
-    const int j = 16 * u + (lane & 15);
-    const int c = j & 1, k = (j >> 1) % 3, site = (j >> 1) / 3;
+    const int c = lane & 1, k = u >> 1, site = 8 * (u & 1) + ((lane & 15) >> 1);
     const long gs = (long)blockIdx.x * 64 + 16 * w + site;
     const int Bs = (int)(gs / g.bs), ss = (int)(gs - (long)Bs * g.bs);
     const long base = fidx(g, Bs, ss, 12);
