@@ -246,9 +246,10 @@ __global__ void __launch_bounds__(256) k_coarse_schur_even_mrhs(CGeom cg,
 // ([n][K] complex) to the FP32 products with Minv, which all threads of the
 // workgroup share: thread -> row i = tid % n and a quarter g = tid / n of the
 // inner index (16 terms, all loads in flight), the four partial sums added in
-// LDS ([4][n][K]) in fixed order.  The LDS is sized by K at launch: at K = 2
-// the kernel holds 6 wavefronts per SIMD instead of 4 (13 % faster odd-even
-// operator at 48^3x96).
+// LDS ([4][n][K]) in fixed order.  For K > 8 a thread takes row i and every
+// fourth column instead, with all n inner terms, and the partial sums go
+// away.  The LDS is sized by K at launch: at K = 2 the kernel holds 6
+// wavefronts per SIMD instead of 4 (13 % faster odd-even operator at 48^3x96).
 template <class S, int NT, int RT>
 __global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
                                                                  const typename store_traits<S>::elem* __restrict__ D,
@@ -284,6 +285,35 @@ __global__ void __launch_bounds__(256) k_coarse_hop_inv_odd_mrhs(CGeom cg,
     }
   }
   __syncthreads();
+  if constexpr (NT == 2) {
+    // K > 8: thread (row i, column group gq) sums all n inner terms for the
+    // columns gq, gq + 4, ... (no partial sums in LDS; the four column groups
+    // read the same inverse entries, which the L1 shares)
+    const cx<float>* M = Minv + (long)io * n * n;
+    cx<float> o[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = mk<float>(0, 0);
+#pragma unroll 1
+    for (int l0 = 0; l0 < n; l0 += 16) {
+      cx<float> mm[16];
+#pragma unroll
+      for (int l = 0; l < 16; ++l) mm[l] = M[(long)(l0 + l) * n + i];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = gq + 4 * q;
+        if (r < K) {
+#pragma unroll
+          for (int l = 0; l < 16; ++l) cmac(o[q], mm[l], us[(l0 + l) * K + r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = gq + 4 * q;
+      if (r < K) y[(long)r * ldv + (long)site * n + i] = o[q];
+    }
+    return;
+  }
   {
     const cx<float>* M = Minv + (long)io * n * n;
 #pragma unroll
@@ -520,7 +550,8 @@ void launch_coarse_hop_inv_odd_mrhs(const CGeom& cg, const void* D, const cx<flo
   int nodd = cg.nsites - cg.neven;
   if (K < 1 || K > 16) throw Error(INVALID_ARG, "K-column coarse operator: 1 <= K <= 16");
   dim3 grid(nodd), blk(4 * cg.n);
-  const size_t sm = (size_t)5 * cg.n * K * sizeof(cx<float>);
+  // hop result [n][K], and for K <= 8 the four partial sums [4][n][K]
+  const size_t sm = (size_t)(nt_of(K) == 2 ? 1 : 5) * cg.n * K * sizeof(cx<float>);
   auto Dp = (const typename store_traits<S>::elem*)D;
   MRHS_DISPATCH(k_coarse_hop_inv_odd_mrhs, grid, blk, sm, st, cg, Dp, Minv, K, ldv, x, base, y);
 }
