@@ -1019,10 +1019,12 @@ void launch_cvt_real(long n, const double* in, float* out, hipStream_t st) {
 // triangular with a real positive diagonal; that factor is unique, so it is the
 // one Gram-Schmidt in the order v_1..v_Nv produces.  It is computed as a
 // Cholesky QR in FP64: G = V^H V on the matrix cores, G = R^H R in LDS, then
-// Q = V R^{-1} on the matrix cores.  An FP64 output takes a second pass on Q,
-// which brings its orthogonality to working precision; for an FP32 output the
-// one FP64 pass is already below FP32 rounding.  A pivot at or below 1e-24 of
-// the vector's squared norm (linearly dependent test vectors) sets *fail.
+// Q = V R^{-1} on the matrix cores.  The loss of orthogonality of one pass
+// grows like eps64 cond(V)^2: an FP64 output always takes a second pass on Q,
+// an FP32 output when the aggregate's smallest pivot ratio R_kk^2 / |v_k|^2 is
+// below 1e-6.  A pivot ratio at or below 1e-14 (|R_kk| <= 1e-7 |v_k|, where
+// the FP64 Gram matrix no longer resolves the column: linearly dependent test
+// vectors) sets *fail.
 //
 // One workgroup (4 wavefronts) per (block, half); rows r of the aggregate are
 // (tile of 8 slots, component of the half, slot in the tile), so 8 consecutive
@@ -1044,9 +1046,9 @@ __device__ __forceinline__ cx<double> qr_ld(const cx<T>* p, long stride, int j, 
 
 // one Cholesky QR pass: src (rows of this aggregate) -> dst; Gr/Gi/Xr/Xi/d0 in LDS
 template <class TS, class TD>
-__device__ void cholqr_pass(const Geom& g, int B, int h, int Nv, const cx<TS>* src, long sstride, cx<TD>* dst,
+__device__ __forceinline__ void cholqr_pass(const Geom& g, int B, int h, int Nv, const cx<TS>* src, long sstride, cx<TD>* dst,
                             long dstride, double (*Gr)[33], double (*Gi)[33], double (*Xr)[33], double (*Xi)[33],
-                            double* d0, int* fail) {
+                            double* d0, int* fail, double* ratio) {
   using MF = mfma_k4<double>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rows = 6 * g.bs;
@@ -1092,12 +1094,15 @@ __device__ void cholqr_pass(const Geom& g, int B, int h, int Nv, const cx<TS>* s
   if (t < Nv) d0[t] = Gr[t][t];
   __syncthreads();
   // ---- G = R^H R in place on the upper triangle (R[k][k] real)
+  double rmin = 1.0;  // smallest pivot ratio (thread 0)
   for (int k = 0; k < Nv; ++k) {
     const double dk = Gr[k][k];
     const double rkk = dk > 0 ? sqrt(dk) : 0.0, rinv = rkk > 0 ? 1.0 / rkk : 0.0;
     __syncthreads();
     if (t == 0) {
-      if (fail && !(dk > 1e-24 * d0[k])) atomicOr(fail, 1);
+      const double rk = d0[k] > 0 ? dk / d0[k] : 0.0;
+      rmin = rk < rmin ? rk : rmin;
+      if (fail && !(rk > 1e-14)) atomicOr(fail, 1);
       Gr[k][k] = rkk;
       Gi[k][k] = 0.0;
     } else if (t > k && t < Nv) {
@@ -1116,6 +1121,7 @@ __device__ void cholqr_pass(const Geom& g, int B, int h, int Nv, const cx<TS>* s
     }
     __syncthreads();
   }
+  if (t == 0) *ratio = rmin;
   // ---- X = R^{-1} (upper), one thread per column; zero elsewhere (padding)
   for (int q = t; q < 32 * 32; q += QR_NT) {
     Xr[q >> 5][q & 31] = 0.0;
@@ -1170,13 +1176,21 @@ __device__ void cholqr_pass(const Geom& g, int B, int h, int Nv, const cx<TS>* s
 }  // namespace
 
 template <class RI, class RO>
-__global__ void __launch_bounds__(QR_NT) k_qr_fine(Geom g, int Nv, const cx<RI>* V, long vstride, RO* Qout_raw,
+__global__ void __launch_bounds__(QR_NT) __attribute__((amdgpu_waves_per_eu(3, 8))) k_qr_fine(Geom g, int Nv, const cx<RI>* V, long vstride, RO* Qout_raw,
                                                    long qstride, int* __restrict__ fail) {
-  __shared__ double Gr[32][33], Gi[32][33], Xr[32][33], Xi[32][33], d0[32];
+  __shared__ double Gr[32][33], Gi[32][33], Xr[32][33], Xi[32][33], d0[32], ratio;
   cx<RO>* Q = reinterpret_cast<cx<RO>*>(Qout_raw);
   const int B = blockIdx.x >> 1, h = blockIdx.x & 1;
-  cholqr_pass<RI, RO>(g, B, h, Nv, V, vstride, Q, qstride, Gr, Gi, Xr, Xi, d0, fail);
-  if constexpr (sizeof(RO) == 8) cholqr_pass<RO, RO>(g, B, h, Nv, Q, qstride, Q, qstride, Gr, Gi, Xr, Xi, d0, nullptr);
+  static_assert(std::is_same<RI, RO>::value, "both passes share one body");
+  // pass 0 on V; pass 1 on Q for an FP64 output or an ill-conditioned aggregate
+  // (ratio is an LDS value after a barrier: uniform over the workgroup)
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    cholqr_pass<RI, RO>(g, B, h, Nv, pass == 0 ? V : reinterpret_cast<const cx<RI>*>(Q),
+                        pass == 0 ? vstride : qstride, Q, qstride, Gr, Gi, Xr, Xi, d0, pass == 0 ? fail : nullptr,
+                        &ratio);
+    if (!(sizeof(RO) == 8 || ratio < 1e-6)) break;
+  }
 }
 template <class RI, class RO>
 void launch_qr_fine(const Geom& g, int Nv, const cx<RI>* V, long vstride, cx<RO>* Q, long qstride, int* fail,

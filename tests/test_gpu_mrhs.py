@@ -193,3 +193,15 @@ def test_lockstep_outer_solve(dd, prec):
         assert res[1] == res[2]
     else:
         assert abs(res[1] - res[2]) <= max(3, 0.15 * res[1])
+
+
+def test_coarse_solve_multi_restart_above_32(dd):
+    # restart 40: Arnoldi steps past 32 basis vectors take the unfused
+    # Gram-Schmidt path and the general batched back substitution
+    ctx, op, h = two_level(dd, (8, 8, 8, 16), (4, 4, 4, 4), 8, delta=3.0, fixed_iters=1, coarse_max_iter=45,
+                           coarse_restart=40)
+    Dc = h.levels[1].op
+    bs = synth.gaussian((2,) + Dc.dims + (Dc.n,), 84)
+    got = ctx.coarse_solve_multi(1, bs)
+    for k in range(2):
+        assert rel(got[k], h.coarse_solve(1, bs[k])) < 1e-10

@@ -229,3 +229,20 @@ def test_three_level_vcycle_fixed(dd):
     got = ctx.vcycle(v.reshape(op.dims + (4, 3))).reshape(op.dims + (12,))
     want = h.vcycle(0, v)
     assert rel(got, want) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rank_deficient_test_vectors_rejected(dd, prec):
+    # one test vector is i times another (exact in both precisions): every
+    # aggregate half is rank-deficient and the block orthonormalisation must
+    # refuse the set, as the oracle's does
+    dims, block, nv = (4, 4, 4, 8), (2, 2, 2, 2), 6
+    ctx, op, U = make(dd, dims, block)
+    V = synth.gaussian((nv,) + dims + (12,), 1601)
+    V[3] = 1j * V[1]
+    with pytest.raises(ValueError):
+        agg.orthonormalise(V, block)
+    p = dd.default_params(levels=2, block=[block], nvec=[nv], precision=prec)
+    with pytest.raises(dd.DDAMGError) as e:
+        ctx.set_test_vectors(p, [V.reshape((nv,) + dims + (4, 3))])
+    assert e.value.status == dd.NUMERICAL
