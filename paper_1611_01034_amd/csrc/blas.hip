@@ -804,11 +804,12 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
                      H, ldh, m, cs, sn, g, j, resid, resid_host, act);
 }
 
-// FP32 vectors: 1024-thread workgroups with FP32 per-thread sums (at most 128
-// registers); FP64 vectors: 256-thread workgroups
+// FP32 vectors: 512-thread workgroups with FP32 per-thread sums (at most 128
+// registers; with up to 256 workgroups a coarsest column of 82,944 entries
+// spreads over all 256 CUs); FP64 vectors: 256-thread workgroups
 template <class R>
 int cgs_block_size() {
-  return sizeof(R) == 4 ? 1024 : 256;
+  return sizeof(R) == 4 ? 512 : 256;
 }
 template <class R>
 void launch_cgs_step(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, cx<double>* pa,
@@ -818,7 +819,7 @@ void launch_cgs_step(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long c
   double* a = reinterpret_cast<double*>(pa);
   double* b = reinterpret_cast<double*>(pb);
   if constexpr (sizeof(R) == 4)
-    cgs_step_bs<R, 1024>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, resid_host, K, act, st);
+    cgs_step_bs<R, 512>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, resid_host, K, act, st);
   else
     cgs_step_bs<R, 256>(V, ldv, csV, k, w, csw, N, a, b, pcs, nwg, hcol, hcs, H, ldh, m, cs, sn, g, j, resid, resid_host, K, act, st);
 }

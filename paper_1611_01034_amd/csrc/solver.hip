@@ -289,7 +289,7 @@ KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(co
 template <class R>
 static int cgs_nwg(long N) {
   const long per = sizeof(R) == 4 ? cgs_block_size<R>() : 4L * cgs_block_size<R>();
-  const long cap = sizeof(R) == 4 ? 128 : 1024;
+  const long cap = sizeof(R) == 4 ? 256 : 1024;
   return (int)std::min<long>(cap, std::max<long>(1, (N + per - 1) / per));
 }
 
