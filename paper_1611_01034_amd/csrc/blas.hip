@@ -778,7 +778,7 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
     constexpr int BA = (BS == 1024 && KM >= 16) ? 512 : BS;                                                            \
     hipLaunchKernelGGL((k_cgs_dot<R, KM, BS>), grid, blk, 0, st, V, ldv, csV, k, (const cx<R>*)w, csw, N, a, pcs,     \
                        act);                                                                                           \
-    if (two_pass) {                                                                                                    \
+    if constexpr (two_pass) {                                                                                          \
       hipLaunchKernelGGL((k_cgs_axpy_dot<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,               \
                          (const double*)a, b, pcs, hcol, hcs, act);                                                    \
       hipLaunchKernelGGL((k_cgs_axpy_norm<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,              \
