@@ -27,7 +27,7 @@ namespace ddamg {
 
 // ---------------------------------------------------------------------------
 // SAP: one colour sweep.  One workgroup per block of the colour, one thread per
-// (even slot i, odd slot half+i).  r = b - D x on the block, then n_mr MR steps
+// slot (even slots first).  r = b - D x on the block, then n_mr MR steps
 // on the block-local even-site Schur complement S = T_ee - D_eo T_oo^{-1} D_oe
 // (hops leaving the block dropped), odd reconstruction, x += e.
 template <class R, class S, bool SUB = false>
