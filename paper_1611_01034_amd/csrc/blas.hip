@@ -556,6 +556,8 @@ void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int 
 // buffers, pa and pb, each [K][ldh][nwg] complex.  Basis V_0..V_{k-1} at
 // stride ldv, k <= KM <= 32.
 namespace {
+// smallest power of two >= km (the transposing wavefront sum needs one)
+constexpr int cgs_pow2(int km) { return km <= 2 ? 2 : km <= 4 ? 4 : km <= 8 ? 8 : km <= 16 ? 16 : 32; }
 // this workgroup's sums of acc[0..nval) -> partd[(v/2) * nwg + wg] (as doubles;
 // NW wavefronts, the wavefront totals added in FP64 in wavefront order)
 template <int KM, int NW, class A>
@@ -615,9 +617,11 @@ __global__ void __launch_bounds__(BS) k_cgs_dot(const cx<R>* __restrict__ V, lon
   if (act && !act[r]) return;
   V += r * csV;
   w += r * csw;
-  R acc[2 * KM];
+  // sums for KM vectors, padded to a power of two for the wavefront reduction
+  constexpr int KP = cgs_pow2(KM);
+  R acc[2 * KP];
 #pragma unroll
-  for (int q = 0; q < 2 * KM; ++q) acc[q] = R(0);
+  for (int q = 0; q < 2 * KP; ++q) acc[q] = R(0);
   const long stride = (long)gridDim.x * BS;
   for (long e = (long)blockIdx.x * BS + threadIdx.x; e < N; e += stride) {
     const cx<R> x = w[e];
@@ -628,7 +632,7 @@ __global__ void __launch_bounds__(BS) k_cgs_dot(const cx<R>* __restrict__ V, lon
       acc[2 * i + 1] += v.re * x.im - v.im * x.re;
     }
   }
-  store_partials<KM, BS / 64>(acc, 2 * k, pa + 2 * r * pcs);
+  store_partials<KP, BS / 64>(acc, 2 * k, pa + 2 * r * pcs);
 }
 
 // h_r = sum of pa_r (workgroup 0 stores it in hcol_r);  w_r -= sum_i h_r[i] V_{r,i};
@@ -647,9 +651,11 @@ __global__ void __launch_bounds__(BS) k_cgs_axpy_dot(const cx<R>* __restrict__ V
   if (blockIdx.x == 0 && threadIdx.x < 2 * k) reinterpret_cast<double*>(hcol + r * hcs)[threadIdx.x] = cf[threadIdx.x];
   if (threadIdx.x < KM) cfr[threadIdx.x] = mk<R>((R)cf[2 * threadIdx.x], (R)cf[2 * threadIdx.x + 1]);
   __syncthreads();
-  R acc[2 * KM];
+  // sums for KM vectors, padded to a power of two for the wavefront reduction
+  constexpr int KP = cgs_pow2(KM);
+  R acc[2 * KP];
 #pragma unroll
-  for (int q = 0; q < 2 * KM; ++q) acc[q] = R(0);
+  for (int q = 0; q < 2 * KP; ++q) acc[q] = R(0);
   const long stride = (long)gridDim.x * BS;
   for (long e = (long)blockIdx.x * BS + threadIdx.x; e < N; e += stride) {
     const cx<R> x0 = w[e];
@@ -670,7 +676,7 @@ __global__ void __launch_bounds__(BS) k_cgs_axpy_dot(const cx<R>* __restrict__ V
       acc[2 * i + 1] += v.re * x.im - v.im * x.re;
     }
   }
-  store_partials<KM, BS / 64>(acc, 2 * k, pb + 2 * r * pcs);
+  store_partials<KP, BS / 64>(acc, 2 * k, pb + 2 * r * pcs);
 }
 
 // c_r = sum of pb_r (workgroup 0: hcol_r += c_r, or hcol_r = c_r when this is
@@ -796,6 +802,8 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
     CGS_LAUNCH(8)
   } else if (k <= 16) {
     CGS_LAUNCH(16)
+  } else if (k <= 24) {
+    CGS_LAUNCH(24)
   } else {
     CGS_LAUNCH(32)
   }
