@@ -800,6 +800,8 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
     CGS_LAUNCH(4)
   } else if (k <= 8) {
     CGS_LAUNCH(8)
+  } else if (k <= 12) {
+    CGS_LAUNCH(12)
   } else if (k <= 16) {
     CGS_LAUNCH(16)
   } else if (k <= 24) {
