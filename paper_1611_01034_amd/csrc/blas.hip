@@ -794,18 +794,25 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
                          (const double*)a, b, pcs, hcol, hcs, act);                                                    \
     }                                                                                                                  \
   }
+  // buckets of basis sizes: at most three clamped loads past k per element
   if (k <= 2) {
     CGS_LAUNCH(2)
   } else if (k <= 4) {
     CGS_LAUNCH(4)
+  } else if (k <= 6) {
+    CGS_LAUNCH(6)
   } else if (k <= 8) {
     CGS_LAUNCH(8)
   } else if (k <= 12) {
     CGS_LAUNCH(12)
   } else if (k <= 16) {
     CGS_LAUNCH(16)
+  } else if (k <= 20) {
+    CGS_LAUNCH(20)
   } else if (k <= 24) {
     CGS_LAUNCH(24)
+  } else if (k <= 28) {
+    CGS_LAUNCH(28)
   } else {
     CGS_LAUNCH(32)
   }
