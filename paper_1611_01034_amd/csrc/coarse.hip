@@ -197,60 +197,44 @@ void launch_coarse_sap_multi(const CGeom& cg, const void* D, double tw, int nblk
 
 // ---------------------------------------------------------------------------
 // restriction to the next level: r_c[A][s*Nv+i] = sum_{j in A, k in half s}
-// conj(Q_i[site_j][k]) r[site_j][k].  One workgroup (256) per aggregate.
+// conj(Q_i[site_j][k]) r[site_j][k].  One workgroup (256) per aggregate;
+// wavefront w takes the vectors 8w..8w+7 (then +32, ...) over all entries of
+// the aggregate (lanes on consecutive entries) and sums its 32 values
+// (8 vectors x 2 halves x re/im) with one transposing wavefront sum: no LDS,
+// no barriers, the four wavefronts independent.
 template <class R>
 __global__ void __launch_bounds__(256) k_restrict_coarse(int n, int Nv, int asz, const int* __restrict__ agg_sites,
                                                          const cx<R>* __restrict__ Q, long qstride,
                                                          const cx<R>* __restrict__ r, cx<R>* __restrict__ rc) {
-  __shared__ double red[16][4][2];
-  int A = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int tot = asz * n;
-  for (int i0 = 0; i0 < Nv; i0 += 8) {
-    double acc[8][2][2];
+  const int A = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tot = asz * n, hn = n >> 1;
+  for (int i0 = 8 * w; i0 < Nv; i0 += 32) {
+    double acc[32];  // [4 ii + 2 h + p]
 #pragma unroll
-    for (int ii = 0; ii < 8; ++ii) acc[ii][0][0] = acc[ii][0][1] = acc[ii][1][0] = acc[ii][1][1] = 0.0;
-    for (int e = t; e < tot; e += 256) {
-      int j = e / n, k = e - j * n;
-      long idx = (long)agg_sites[A * asz + j] * n + k;
-      cx<R> rv = r[idx];
-      int h = k >= (n >> 1) ? 1 : 0;
+    for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+#pragma unroll 2
+    for (int e = lane; e < tot; e += 64) {
+      const int j = e / n, k = e - j * n;
+      const long idx = (long)agg_sites[A * asz + j] * n + k;
+      const cx<R> rv = r[idx];
+      const bool up = k >= hn;
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii) {
-        if (i0 + ii < Nv) {
-          cx<R> qv = Q[(long)(i0 + ii) * qstride + idx];
-          double re = (double)qv.re * rv.re + (double)qv.im * rv.im;
-          double im = (double)qv.re * rv.im - (double)qv.im * rv.re;
-          if (h) {
-            acc[ii][1][0] += re;
-            acc[ii][1][1] += im;
-          } else {
-            acc[ii][0][0] += re;
-            acc[ii][0][1] += im;
-          }
-        }
+        const int iv = i0 + ii < Nv ? i0 + ii : Nv - 1;  // clamped: every load in flight
+        const cx<R> qv = Q[(long)iv * qstride + idx];
+        const double re = (double)qv.re * rv.re + (double)qv.im * rv.im;
+        const double im = (double)qv.re * rv.im - (double)qv.im * rv.re;
+        acc[4 * ii + 0] += up ? 0.0 : re;
+        acc[4 * ii + 1] += up ? 0.0 : im;
+        acc[4 * ii + 2] += up ? re : 0.0;
+        acc[4 * ii + 3] += up ? im : 0.0;
       }
     }
-#pragma unroll
-    for (int ii = 0; ii < 8; ++ii)
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-          double v = wave_sum_n(acc[ii][hh][p], 64);
-          if (lane == 0) red[2 * ii + hh][wv][p] = v;
-        }
-    __syncthreads();
-    int ni = min(8, Nv - i0);
-    if (t < 2 * ni) {
-      int ii = t >> 1, hh = t & 1;
-      double re = 0, im = 0;
-      for (int v = 0; v < 4; ++v) {
-        re += red[t][v][0];
-        im += red[t][v][1];
-      }
-      rc[(long)A * 2 * Nv + hh * Nv + i0 + ii] = mk<R>((R)re, (R)im);
+    const double v = wave_transpose_sum<32>(acc, lane);  // lane l: total of value l % 32
+    if (lane < 32) {
+      const int ii = lane >> 2, hh = (lane >> 1) & 1, p = lane & 1;
+      if (i0 + ii < Nv) reinterpret_cast<R*>(rc + (long)A * 2 * Nv + hh * Nv + i0 + ii)[p] = (R)v;
     }
-    __syncthreads();
   }
 }
 template <class R>
