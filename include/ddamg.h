@@ -98,6 +98,9 @@ typedef struct ddamg_params {
                                   outer FGMRES whose V-cycles and coarse solves serve all of them
                                   (default 1, at most 16).  Each holds its own FP64 Krylov basis of
                                   2 * restart + 1 fine fields. */
+  int keep_test_vectors;       /* 1: the setup keeps its test vectors (nvec[l] fields per level
+                                  transition) for ddamg_update_gauge; 0: they are freed when the
+                                  setup ends (default) */
 } ddamg_params;
 
 typedef struct ddamg_stats {
@@ -162,6 +165,22 @@ int ddamg_set_test_vectors(ddamg_ctx* ctx, const ddamg_params* p, const void* co
  * ignored. */
 int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise, int noise_precision,
                         int on_device, const void* coarse_init);
+/* Setup update for a changed gauge field (the HMC use of Sec. 3.1: during a
+ * trajectory the setup is refreshed by one fine-level and three
+ * first-coarse-level iterations instead of being rebuilt).  links: the
+ * new field, as for ddamg_set_gauge.  The test vectors of the current
+ * setup (kept when it ran with keep_test_vectors = 1; else the columns of its
+ * interpolation bases P_l, which span the same space on every aggregate but
+ * are not smooth across aggregates) become those of the new one: the library
+ * moves them (no copy), then runs ddamg_setup's steps on them with p
+ * (p->init_sap_iters smoothing sweeps, usually 0; p->setup_iters fine and
+ * p->coarse_setup_iters level-1 iterations, 1 and 3 in the paper's use).
+ * With both iteration counts 0 the new D_c is the Galerkin operator of the old
+ * P on the new field.  p must keep the levels, precision, nvec and aggregation
+ * blocks of the current setup (INVALID_ARG otherwise).  BAD_STATE without a
+ * setup; a field with NaN or Inf returns NUMERICAL with the old field and
+ * setup intact; any later error leaves the new field and no setup. */
+int ddamg_update_gauge(ddamg_ctx* ctx, const void* links, int on_device, const ddamg_params* p);
 
 /* Solve D(mu) x_r = b_r for nrhs right-hand sides (spinor layout, nrhs
  * contiguous fields) with FGMRES preconditioned by Eq. (1), stopping at a

@@ -117,6 +117,28 @@ void check_params(const ddamg_params* p) {
   if (p->rhs_batch < 1 || p->rhs_batch > 16) throw Error(INVALID_ARG, "rhs_batch must be in [1, 16]");
 }
 
+// links (lexicographic FP64, host or device) -> block layout, clover term and
+// the fine odd-site inverses; throws before any change for a non-finite field
+void load_links(Ctx& c, const void* links, int on_device) {
+  if (!links) throw Error(INVALID_ARG, "links is NULL");
+  size_t bytes = sizeof(cx<double>) * (size_t)c.g.V * 36;
+  const cx<double>* src = (const cx<double>*)links;
+  DevBuf stage;
+  if (!on_device) {
+    stage.alloc(bytes);
+    HIP_CHECK(hipMemcpyAsync(stage.p, links, bytes, hipMemcpyHostToDevice, c.st));
+    src = stage.as<cx<double>>();
+  }
+  check_finite(c, (const double*)src, (long)c.g.V * 72);
+  launch_links_from_lex(c.g, src, c.U64.as<cx<double>>(), c.st);
+  launch_clover(c.g, c.U64.as<cx<double>>(), c.csw, c.m0 + 4.0, c.H64.as<double>(), c.st);
+  c.have_32 = false;
+  c.u16_kind = -1;
+  c.rebuild_odd_inverse();
+  c.sync();
+  c.have_gauge = true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -225,25 +247,38 @@ int ddamg_set_gauge(ddamg_ctx* ctx, const void* links, int on_device) {
   if (!ctx) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {
     Ctx& c = ctx->c;
-    if (!links) throw Error(INVALID_ARG, "links is NULL");
-    size_t bytes = sizeof(cx<double>) * (size_t)c.g.V * 36;
-    const cx<double>* src = (const cx<double>*)links;
-    DevBuf stage;
-    if (!on_device) {
-      stage.alloc(bytes);
-      HIP_CHECK(hipMemcpyAsync(stage.p, links, bytes, hipMemcpyHostToDevice, c.st));
-      src = stage.as<cx<double>>();
-    }
-    check_finite(c, (const double*)src, (long)c.g.V * 72);
-    launch_links_from_lex(c.g, src, c.U64.as<cx<double>>(), c.st);
-    launch_clover(c.g, c.U64.as<cx<double>>(), c.csw, c.m0 + 4.0, c.H64.as<double>(), c.st);
-    c.have_32 = false;
-    c.u16_kind = -1;
-    c.rebuild_odd_inverse();
-    c.sync();
-    c.have_gauge = true;
+    load_links(c, links, on_device);
     c.have_setup = false;
     c.mg.reset();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_update_gauge(ddamg_ctx* ctx, const void* links, int on_device, const ddamg_params* p) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_setup(c);
+    check_params(p);
+    if (p->levels != c.p.levels || p->precision != c.p.precision)
+      throw Error(INVALID_ARG, "levels and precision must equal those of the current setup");
+    for (int l = 0; l < p->levels - 1; ++l) {
+      if (p->nvec[l] != c.p.nvec[l]) throw Error(INVALID_ARG, "nvec must equal that of the current setup");
+      for (int d = 0; d < 4; ++d)
+        if (p->block[l][d] != c.p.block[l][d])
+          throw Error(INVALID_ARG, "aggregation blocks must equal those of the current setup");
+    }
+    // a field with NaN or Inf is rejected here with the old state intact
+    load_links(c, links, on_device);
+    std::unique_ptr<MGBase> prev = std::move(c.mg);
+    c.have_setup = false;
+    c.p = *p;
+    c.mg = make_mg(c);
+    c.mg->adopt_vectors(*prev);
+    prev.reset();
+    const void* none[3] = {nullptr, nullptr, nullptr};
+    c.mg->build(none, 1, true);
+    c.have_setup = true;
     return DDAMG_OK;
   });
 }

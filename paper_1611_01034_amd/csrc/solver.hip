@@ -1125,7 +1125,18 @@ struct MG : MGBase {
     for (int i = 0; i < Nv[0]; ++i)
       launch_copy_cvt<float, R>(v + (long)i * len, Vraw[0].template as<cx<R>>() + (long)i * len, len, c.st);
     c.sync();
-    fine_loaded = true;
+    loaded[0] = true;
+  }
+  void adopt_vectors(MGBase& prev_) override {
+    auto* prev = dynamic_cast<MG<R, S>*>(&prev_);
+    if (!prev || prev->L != L) throw Error(INVALID_ARG, "the previous hierarchy has another precision or depth");
+    for (int l = 0; l < L - 1; ++l)
+      if (prev->Nv[l] != Nv[l] || prev->Q[l].bytes != Vraw[l].bytes || !prev->Q[l].p)
+        throw Error(INVALID_ARG, "the previous hierarchy has other test vector counts or aggregates");
+    for (int l = 0; l < L - 1; ++l) {
+      Vraw[l].swap(prev->Vraw[l].p ? prev->Vraw[l] : prev->Q[l]);
+      loaded[l] = true;
+    }
   }
   DevBuf fbm;
   void precond_multi(const cx<double>* v, cx<double>* z, int K) override {
@@ -1326,8 +1337,8 @@ struct MG : MGBase {
       const bool batched = smooth && p.batch > 1;
       for (int i = 0; i < Nv[l]; ++i) {
         cx<R>* vi = Vraw[l].template as<cx<R>>() + (long)i * len;
-        if (l == 0 && fine_loaded) {
-          // already in place (load_fine_init)
+        if (loaded[l]) {
+          // already in place (load_fine_init, adopt_vectors)
         } else {
           const char* src = (const char*)vecs[l] + sizeof(cx<double>) * (size_t)len * i;
           upload_vec(l, src, on_device, vi);
@@ -1367,8 +1378,10 @@ struct MG : MGBase {
     }
     c.sync();
     // the raw test vectors and the setup's fine K-column buffer are not needed
-    // by the solver: give the memory back (the largest items of the setup)
-    for (int l = 0; l < L - 1; ++l) Vraw[l].release();
+    // by the solver: give the memory back (the largest items of the setup),
+    // unless the vectors are kept for a later setup update
+    if (!p.keep_test_vectors)
+      for (int l = 0; l < L - 1; ++l) Vraw[l].release();
     fxm.release();
   }
 

@@ -5,6 +5,7 @@
 #include <functional>
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kernels.hpp"
@@ -40,6 +41,10 @@ struct DevBuf {
     bytes = 0;
   }
   ~DevBuf() { release(); }
+  void swap(DevBuf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 
@@ -181,7 +186,11 @@ struct MGBase {
   // level-0 initial vectors from the device (block layout, FP32, stride = fine
   // length), copied into the hierarchy; build() then skips vecs[0]
   virtual void load_fine_init(const cx<float>* v) = 0;
-  bool fine_loaded = false;
+  // the test vectors of a previous hierarchy of the same precision, levels
+  // and N_v (the kept raw vectors, else its interpolation bases Q_l) become
+  // this one's (moved, not copied); build() then skips vecs for those levels
+  virtual void adopt_vectors(MGBase& prev) = 0;
+  bool loaded[3] = {false, false, false};  // test vectors of level l already in place
 };
 
 // learned-setup network: parameters (real view, FP32), Adam moments, activations

@@ -58,6 +58,7 @@ class Params(ctypes.Structure):
         ("fixed_iters", ctypes.c_int),
         ("batch", ctypes.c_int),
         ("rhs_batch", ctypes.c_int),
+        ("keep_test_vectors", ctypes.c_int),
     ]
 
 
@@ -85,6 +86,7 @@ _SIGS = {
     "ddamg_destroy": (None, [_vp]),
     "ddamg_last_error": (ctypes.c_char_p, [_vp]),
     "ddamg_set_gauge": (_i, [_vp, _vp, _i]),
+    "ddamg_update_gauge": (_i, [_vp, _vp, _i, ctypes.POINTER(Params)]),
     "ddamg_set_clover": (_i, [_vp, _vp, _i]),
     "ddamg_get_clover": (_i, [_vp, _vp]),
     "ddamg_set_mu": (_i, [_vp, _d]),
@@ -243,6 +245,15 @@ class DDAMG:
         p, dev = _ptr(U)
         self._check(_lib.ddamg_set_gauge(self._h, p, dev))
         self._keep = U
+
+    def update_gauge(self, U, params: Params):
+        """New gauge field, keeping the hierarchy's interpolation as the test
+        vectors of a refreshed setup (ddamg_update_gauge)."""
+        U = _c128(U)
+        p, dev = _ptr(U)
+        self._check(_lib.ddamg_update_gauge(self._h, p, dev, ctypes.byref(params)))
+        self._keep = U
+        self.params = params
 
     def set_clover(self, A=None):
         if A is None:

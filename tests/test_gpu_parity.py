@@ -187,6 +187,79 @@ def test_minus_mu_reuses_setup(dd):
     assert abs(s1["iters"] - s2["iters"]) <= max(2, 0.2 * s1["iters"])
 
 
+# ------------------------------------------------------------------ setup update (Sec. 3.1)
+
+def _perturbed(U, eta, seed):
+    """exp(i eta H') U on every link: a small random step of the field."""
+    W = synth.gauge_field(U.shape[:4], eta, seed)
+    return np.einsum("...ab,...bc->...ac", W, U)
+
+
+def test_update_gauge_without_iterations_is_galerkin_of_old_interpolation(dd):
+    dims, block, nv = (8, 8, 8, 16), (4, 4, 4, 4), 12
+    ctx, op, U = make(dd, dims, block)
+    p = dd.default_params(levels=2, block=[block], nvec=[nv], setup_iters=1, coarse_mu_factor=3.0)
+    ctx.setup(p, [synth.spinor(dims, 2601, nvec=nv)])
+    Q = ctx.get_interpolation(0).reshape((nv,) + dims + (12,))
+    U2 = _perturbed(U, 0.05, 2602)
+    ctx.update_gauge(U2, dd.default_params(levels=2, block=[block], nvec=[nv], setup_iters=0, init_sap_iters=0,
+                                           coarse_mu_factor=3.0))
+    op2 = dirac.WilsonClover(U2, KAPPA, CSW, MU)
+    psi = synth.spinor(dims, 2603)
+    assert rel(ctx.apply_dirac(psi), op2.apply(psi)) < 1e-12
+    h = mg.Hierarchy(op2, mg.Params(levels=2, blocks=[block], nvec=[nv], delta=3.0)).set_test_vectors([Q])
+    # the old basis is already orthonormal per aggregate half: QR keeps it
+    assert rel(h.levels[0].Q, Q) < 1e-13
+    assert rel(ctx.get_interpolation(0).reshape(Q.shape), Q) < 1e-12
+    S, F = ctx.get_coarse_op(1)
+    assert rel(S, h.levels[1].op.S) < 1e-12
+    assert rel(F, h.levels[1].op.F) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_update_gauge_iteration_counts(dd, prec):
+    # after small changes of the field, one fine setup iteration on the kept
+    # test vectors gives the outer iteration count of a new full setup
+    dims, block, nv = (8, 8, 8, 16), (4, 4, 4, 4), 12
+    ctx, op, U = make(dd, dims, block)
+    kw = dict(levels=2, block=[block], nvec=[nv], coarse_mu_factor=3.0, precision=prec, keep_test_vectors=1)
+    V0 = synth.spinor(dims, 2701, nvec=nv)
+    ctx.setup(dd.default_params(setup_iters=3, **kw), [V0])
+    b = synth.spinor(dims, 2702)
+    U2 = U
+    for step in range(3):
+        U2 = _perturbed(U2, 0.02, 2710 + step)
+        ctx.update_gauge(U2, dd.default_params(setup_iters=1, init_sap_iters=0, **kw))
+        x, s = ctx.solve(b, tol=1e-10)
+        op2 = dirac.WilsonClover(U2, KAPPA, CSW, MU)
+        assert s["converged"] and rel(op2.apply(x), b) <= 1e-10
+        fresh = dd.DDAMG(dims, block, KAPPA, CSW, MU)
+        fresh.set_gauge(U2)
+        fresh.setup(dd.default_params(setup_iters=3, **kw), [V0])
+        _, sf = fresh.solve(b, tol=1e-10)
+        fresh.close()
+        assert s["iters"] <= sf["iters"] + max(2, 0.2 * sf["iters"]), (step, s["iters"], sf["iters"])
+
+
+def test_update_gauge_rejects_other_shapes(dd):
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, op, U = make(dd, dims, block)
+    with pytest.raises(dd.DDAMGError):
+        ctx.update_gauge(U, dd.default_params(levels=2, block=[block], nvec=[8]))  # no setup yet
+    ctx.setup(dd.default_params(levels=2, block=[block], nvec=[8], setup_iters=0),
+              [synth.spinor(dims, 2801, nvec=8)])
+    with pytest.raises(dd.DDAMGError):
+        ctx.update_gauge(U, dd.default_params(levels=2, block=[block], nvec=[10], setup_iters=0))
+    bad = U.copy()
+    bad[0, 0, 0, 0, 0, 0, 0] = np.nan
+    with pytest.raises(dd.DDAMGError):
+        ctx.update_gauge(bad, dd.default_params(levels=2, block=[block], nvec=[8], setup_iters=0))
+    # the failed calls left the setup in place
+    b = synth.spinor(dims, 2802)
+    x, st = ctx.solve(b, tol=1e-10)
+    assert rel(op.apply(x), b) <= 1e-10
+
+
 # ------------------------------------------------------------------ 3 levels
 
 def _three_level(dd, **kw):
