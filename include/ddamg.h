@@ -131,6 +131,16 @@ const char* ddamg_last_error(const ddamg_ctx* ctx);
  * links with the csw of ddamg_create (Sec. 1: Wilson clover operator).
  * Returns NUMERICAL if a link is not finite. */
 int ddamg_set_gauge(ddamg_ctx* ctx, const void* links, int on_device);
+/* Twisted boundary conditions (Sec. 2, the features the library adds):
+ * psi(x + L_mu e_mu) = e^{i theta_mu} psi(x) in direction mu = 0:T 1:Z 2:Y
+ * 3:X; theta = {pi, 0, 0, 0} is antiperiodic in time, all zero (the default)
+ * periodic.  The library carries the phase on the links that cross the
+ * boundary (U_mu(x) with x_mu = L_mu - 1), so every level and kernel sees the
+ * same operator; the clover term does not change.  theta: 4 doubles, host,
+ * read during the call.  Applies to the field in place (any setup is dropped)
+ * and to every field uploaded later.  INVALID_ARG for NULL or non-finite
+ * theta. */
+int ddamg_set_boundary_phases(ddamg_ctx* ctx, const double theta[4]);
 /* Replace the clover term by a caller-supplied one (clover layout above);
  * clover = NULL rebuilds it from the links.  Invalidates any setup. */
 int ddamg_set_clover(ddamg_ctx* ctx, const void* clover, int on_device);

@@ -144,17 +144,34 @@ def clover_from_blocks(Ab):
 # operator
 # ----------------------------------------------------------------------------
 
+def boundary_phase_links(U, theta):
+    """Links that carry twisted boundary conditions psi(x + L_mu e_mu) =
+    exp(i theta_mu) psi(x) (Sec. 2) on the periodic lattice: the forward hop
+    from x_mu = L_mu - 1 reads psi(0) and must see exp(i theta_mu) psi(0), so
+    U_mu(x) at x_mu = L_mu - 1 takes that factor (and the backward hop from
+    x_mu = 0, through U^dag, its inverse)."""
+    U = np.array(U, dtype=np.complex128, copy=True)
+    for mu in range(4):
+        idx = [slice(None)] * 4
+        idx[mu] = -1
+        U[tuple(idx) + (mu,)] *= np.exp(1j * theta[mu])
+    return U
+
+
 class WilsonClover:
-    """D(mu) = D_W + i mu Gamma5 on a periodic lattice.
+    """D(mu) = D_W + i mu Gamma5 on a periodic lattice, or with twisted
+    boundary conditions (theta, per direction T,Z,Y,X).
 
     U      links [T,Z,Y,X,4,3,3]
     kappa  hopping parameter (m0 = 1/(2 kappa) - 4)
     csw    clover coefficient (ignored if `clover` is given)
     mu     twisted mass (mass normalisation)
     clover optional clover term [T,Z,Y,X,2,6,6] (A only, without m0+4)
+    theta  optional boundary phases; the clover term is built from the
+           unphased links (closed loops do not see the phases)
     """
 
-    def __init__(self, U, kappa: float, csw: float, mu: float, clover=None):
+    def __init__(self, U, kappa: float, csw: float, mu: float, clover=None, theta=None):
         self.U = np.asarray(U, dtype=np.complex128)
         self.dims = self.U.shape[:4]
         self.m0 = m0_from_kappa(kappa)
@@ -163,6 +180,8 @@ class WilsonClover:
             self.A = clover_matrix(self.U, csw)
         else:
             self.A = clover_from_blocks(np.asarray(clover, dtype=np.complex128))
+        if theta is not None:
+            self.U = boundary_phase_links(self.U, theta)
 
     # --- pieces -------------------------------------------------------------
     def hop(self, psi):

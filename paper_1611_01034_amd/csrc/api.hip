@@ -130,7 +130,12 @@ void load_links(Ctx& c, const void* links, int on_device) {
     src = stage.as<cx<double>>();
   }
   check_finite(c, (const double*)src, (long)c.g.V * 72);
-  launch_links_from_lex(c.g, src, c.U64.as<cx<double>>(), c.st);
+  LinkPhases ph;
+  for (int d = 0; d < 4; ++d) {
+    ph.re[d] = std::cos(c.theta[d]);
+    ph.im[d] = std::sin(c.theta[d]);
+  }
+  launch_links_from_lex(c.g, src, c.U64.as<cx<double>>(), ph, c.st);
   launch_clover(c.g, c.U64.as<cx<double>>(), c.csw, c.m0 + 4.0, c.H64.as<double>(), c.st);
   c.have_32 = false;
   c.u16_kind = -1;
@@ -250,6 +255,32 @@ int ddamg_set_gauge(ddamg_ctx* ctx, const void* links, int on_device) {
     load_links(c, links, on_device);
     c.have_setup = false;
     c.mg.reset();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_set_boundary_phases(ddamg_ctx* ctx, const double theta[4]) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (!theta) throw Error(INVALID_ARG, "theta is NULL");
+    for (int d = 0; d < 4; ++d)
+      if (!std::isfinite(theta[d])) throw Error(INVALID_ARG, "theta must be finite");
+    if (c.have_gauge) {
+      // the links in place carry the old phases: multiply by the difference
+      LinkPhases ph;
+      for (int d = 0; d < 4; ++d) {
+        ph.re[d] = std::cos(theta[d] - c.theta[d]);
+        ph.im[d] = std::sin(theta[d] - c.theta[d]);
+      }
+      launch_link_phase(c.g, c.U64.as<cx<double>>(), ph, c.st);
+      c.have_32 = false;
+      c.u16_kind = -1;
+      c.sync();
+      c.have_setup = false;
+      c.mg.reset();
+    }
+    for (int d = 0; d < 4; ++d) c.theta[d] = theta[d];
     return DDAMG_OK;
   });
 }

@@ -447,18 +447,48 @@ void launch_clover_to_lex(const Geom& g, const double* H, double diag, cx<double
 }
 
 // links [V][4][3][3] lexicographic -> block layout FP64
-__global__ void k_links_from_lex(Geom g, const cx<double>* __restrict__ lex, cx<double>* __restrict__ U) {
+__global__ void k_links_from_lex(Geom g, const cx<double>* __restrict__ lex, cx<double>* __restrict__ U,
+                                 LinkPhases ph) {
   long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= g.V) return;
   int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
   int x[4];
   site_coords(g, B, s, x);
   long li = lex_index(g, x);
-  for (int mu = 0; mu < 4; ++mu)
-    for (int k = 0; k < 9; ++k) U[fidx(g, B, s, 36) + (long)(mu * 9 + k) * TILE] = lex[(li * 4 + mu) * 9 + k];
+  for (int mu = 0; mu < 4; ++mu) {
+    const bool edge = x[mu] == g.L[mu] - 1;
+    const cx<double> f = edge ? mk(ph.re[mu], ph.im[mu]) : mk(1.0, 0.0);
+    for (int k = 0; k < 9; ++k) {
+      const cx<double> v = lex[(li * 4 + mu) * 9 + k];
+      U[fidx(g, B, s, 36) + (long)(mu * 9 + k) * TILE] = edge ? f * v : v;
+    }
+  }
 }
-void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, hipStream_t st) {
-  hipLaunchKernelGGL(k_links_from_lex, dim3((g.V + 255) / 256), dim3(256), 0, st, g, lex, U);
+void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, const LinkPhases& ph,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_links_from_lex, dim3((g.V + 255) / 256), dim3(256), 0, st, g, lex, U, ph);
+}
+
+// twisted boundary conditions psi(x + L_mu e_mu) = e^{i theta_mu} psi(x) as a
+// phase on the links that cross the boundary (forward hop from x_mu = L_mu - 1
+// and, through U^dag, the backward hop from x_mu = 0)
+__global__ void k_link_phase(Geom g, cx<double>* __restrict__ U, LinkPhases ph) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.V) return;
+  int B = (int)(gid / g.bs), s = (int)(gid - (long)B * g.bs);
+  int x[4];
+  site_coords(g, B, s, x);
+  for (int mu = 0; mu < 4; ++mu) {
+    if (x[mu] != g.L[mu] - 1) continue;
+    const cx<double> f = mk(ph.re[mu], ph.im[mu]);
+    for (int k = 0; k < 9; ++k) {
+      cx<double>& v = U[fidx(g, B, s, 36) + (long)(mu * 9 + k) * TILE];
+      v = f * v;
+    }
+  }
+}
+void launch_link_phase(const Geom& g, cx<double>* U, const LinkPhases& ph, hipStream_t st) {
+  hipLaunchKernelGGL(k_link_phase, dim3((g.V + 255) / 256), dim3(256), 0, st, g, U, ph);
 }
 
 // ---------------------------------------------------------------------------

@@ -67,7 +67,15 @@ void set_sigma_table(const double* tab);
 void launch_clover(const Geom& g, const cx<double>* U, double csw, double diag, double* H, hipStream_t st);
 void launch_clover_from_lex(const Geom& g, const cx<double>* lex, double diag, double* H, hipStream_t st);
 void launch_clover_to_lex(const Geom& g, const double* H, double diag, cx<double>* lex, hipStream_t st);
-void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, hipStream_t st);
+// boundary phases e^{i theta_mu} of twisted boundary conditions: the link
+// U_mu(x) with x_mu = L_mu - 1 carries the phase (periodic: 1)
+struct LinkPhases {
+  double re[4], im[4];
+};
+void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, const LinkPhases& ph,
+                           hipStream_t st);
+// multiply the boundary links of U (block layout) by ph in place
+void launch_link_phase(const Geom& g, cx<double>* U, const LinkPhases& ph, hipStream_t st);
 void launch_odd_inverse(const Geom& g, const double* H, double tw, double* M, hipStream_t st);
 // K-column forms (column k at in + k*ld_in, out + k*ld_out): Q is read once
 // per group of columns

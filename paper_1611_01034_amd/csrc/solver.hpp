@@ -213,6 +213,7 @@ struct Ctx {
   hipStream_t st = nullptr;
   Geom g{};
   double kappa = 0, csw = 0, mu = 0, m0 = 0;
+  double theta[4] = {0, 0, 0, 0};  // twisted boundary conditions (0: periodic)
   bool have_gauge = false, have_setup = false;
   DevBuf U64, H64, M64;        // fine operator, FP64
   DevBuf U32, H32, M32;        // FP32 copies

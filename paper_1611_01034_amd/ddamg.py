@@ -87,6 +87,7 @@ _SIGS = {
     "ddamg_last_error": (ctypes.c_char_p, [_vp]),
     "ddamg_set_gauge": (_i, [_vp, _vp, _i]),
     "ddamg_update_gauge": (_i, [_vp, _vp, _i, ctypes.POINTER(Params)]),
+    "ddamg_set_boundary_phases": (_i, [_vp, ctypes.POINTER(_d)]),
     "ddamg_set_clover": (_i, [_vp, _vp, _i]),
     "ddamg_get_clover": (_i, [_vp, _vp]),
     "ddamg_set_mu": (_i, [_vp, _d]),
@@ -245,6 +246,11 @@ class DDAMG:
         p, dev = _ptr(U)
         self._check(_lib.ddamg_set_gauge(self._h, p, dev))
         self._keep = U
+
+    def set_boundary_phases(self, theta):
+        """Twisted boundary conditions psi(x + L_mu) = exp(i theta_mu) psi(x)."""
+        th = (_d * 4)(*[float(t) for t in theta])
+        self._check(_lib.ddamg_set_boundary_phases(self._h, th))
 
     def update_gauge(self, U, params: Params):
         """New gauge field, keeping the hierarchy's interpolation as the test

@@ -187,6 +187,70 @@ def test_minus_mu_reuses_setup(dd):
     assert abs(s1["iters"] - s2["iters"]) <= max(2, 0.2 * s1["iters"])
 
 
+# ------------------------------------------------------------------ twisted boundary conditions (Sec. 2)
+
+THETA = (np.pi, 0.4, -1.3, 2.0)
+
+
+@pytest.mark.parametrize("dims,block", CASES[2:])
+def test_dirac_and_sap_twisted_boundary(dd, dims, block):
+    U = synth.gauge_field(dims, 0.3, 1001)
+    op = dirac.WilsonClover(U, KAPPA, CSW, 0.05, theta=THETA)
+    psi = synth.spinor(dims, 8)
+    ctx = dd.DDAMG(dims, block, KAPPA, CSW, 0.05)
+    ctx.set_boundary_phases(THETA)
+    ctx.set_gauge(U)
+    assert rel(ctx.apply_dirac(psi), op.apply(psi)) < 1e-12
+    assert rel(ctx.apply_dirac(psi, sign=-1), op.apply(psi, -op.mu)) < 1e-12
+    assert np.abs(ctx.get_clover() - dirac.clover_blocks(op.A)).max() < 1e-13
+    x0 = np.zeros_like(psi)
+    got = ctx.sap(psi, x0, iters=2, mr_steps=4, precision="fp64")
+    want = sap.sap(stencil.FineLevel(op), psi.reshape(dims + (12,)), x0.reshape(dims + (12,)), block, 4, 2)
+    assert rel(got.reshape(dims + (12,)), want) < 1e-11
+    # phases changed with the field in place
+    ctx.set_boundary_phases((0.3, 0.0, 0.0, 0.0))
+    ctx.set_boundary_phases(THETA)
+    assert rel(ctx.apply_dirac(psi), op.apply(psi)) < 1e-12
+    ctx.set_boundary_phases((0.0, 0.0, 0.0, 0.0))
+    assert rel(ctx.apply_dirac(psi), dirac.WilsonClover(U, KAPPA, CSW, 0.05).apply(psi)) < 1e-12
+    with pytest.raises(dd.DDAMGError):
+        ctx.set_boundary_phases((np.nan, 0.0, 0.0, 0.0))
+    ctx.close()
+
+
+def test_coarse_operator_twisted_boundary(dd):
+    dims, block, nv = (8, 4, 8, 8), (4, 2, 4, 2), 8
+    U = synth.gauge_field(dims, 0.3, 1001)
+    op = dirac.WilsonClover(U, KAPPA, CSW, MU, theta=THETA)
+    ctx = dd.DDAMG(dims, block, KAPPA, CSW, MU)
+    ctx.set_boundary_phases(THETA)
+    ctx.set_gauge(U)
+    V = synth.gaussian((nv,) + dims + (12,), 2903)
+    ctx.set_test_vectors(dd.default_params(levels=2, block=[block], nvec=[nv], coarse_mu_factor=5.0),
+                         [V.reshape((nv,) + dims + (4, 3))])
+    h = mg.Hierarchy(op, mg.Params(levels=2, blocks=[block], nvec=[nv], delta=5.0)).set_test_vectors([V])
+    S, F = ctx.get_coarse_op(1)
+    assert rel(S, h.levels[1].op.S) < 1e-12
+    assert rel(F, h.levels[1].op.F) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_solve_twisted_boundary(dd, prec):
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1001)
+    op = dirac.WilsonClover(U, KAPPA, CSW, MU, theta=THETA)
+    ctx = dd.DDAMG(dims, block, KAPPA, CSW, MU)
+    ctx.set_boundary_phases(THETA)
+    ctx.set_gauge(U)
+    ctx.setup(dd.default_params(levels=2, block=[block], nvec=[12], setup_iters=2, precision=prec,
+                                coarse_mu_factor=3.0), [synth.spinor(dims, 2901, nvec=12)])
+    b = synth.spinor(dims, 2902)
+    x, st = ctx.solve(b, tol=1e-10)
+    assert st["converged"] and rel(op.apply(x), b) <= 1e-10
+    ctx.close()
+
+
 # ------------------------------------------------------------------ setup update (Sec. 3.1)
 
 def _perturbed(U, eta, seed):

@@ -53,6 +53,40 @@ def test_free_field_plane_wave(mu):
         assert np.abs(got - want).max() < 1e-13
 
 
+@pytest.mark.parametrize("theta", [(np.pi, 0.0, 0.0, 0.0), (0.7, -1.9, 2.6, np.pi)])
+def test_free_field_plane_wave_twisted_boundary(theta):
+    # psi(x + L_mu) = exp(i theta_mu) psi(x) admits the momenta
+    # p_mu = (2 pi n_mu + theta_mu) / L_mu, with the free-field symbol
+    dims = (4, 6, 2, 8)
+    op = dirac.WilsonClover(_free_links(dims), KAPPA, CSW, MU, theta=theta)
+    rng = np.random.default_rng(4)
+    x = np.indices(dims)
+    for n in [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 1, 3), (3, 5, 1, 7)]:
+        p = [(2 * np.pi * n[d] + theta[d]) / dims[d] for d in range(4)]
+        phase = np.exp(1j * sum(p[d] * x[d] for d in range(4)))
+        u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        got = op.apply(phase[..., None, None] * u)
+        want = phase[..., None, None] * (dirac.plane_wave_symbol(p, op.m0, MU) @ u)
+        assert np.abs(got - want).max() < 1e-13
+
+
+def test_twisted_boundary_equals_uniform_abelian_phase():
+    # Omega(x) = exp(-i sum_mu theta_mu x_mu / L_mu) maps the twisted operator
+    # to the periodic one on links exp(i theta_mu / L_mu) U_mu(x):
+    # D_theta = Omega^-1 D_per[U'] Omega
+    dims = (4, 2, 6, 4)
+    theta = (np.pi, 0.4, -1.3, 2.0)
+    U = synth.gauge_field(dims, 0.4, 17)
+    op = dirac.WilsonClover(U, KAPPA, CSW, MU, theta=theta)
+    U1 = U * np.exp(1j * np.array([theta[d] / dims[d] for d in range(4)]))[:, None, None]
+    per = dirac.WilsonClover(U1, KAPPA, CSW, MU)
+    x = np.indices(dims)
+    om = np.exp(-1j * sum(theta[d] * x[d] / dims[d] for d in range(4)))[..., None, None]
+    psi = synth.spinor(dims, 18)
+    assert np.abs(op.apply(psi) - per.apply(om * psi) / om).max() < 1e-13
+    assert np.abs(op.A - per.A).max() < 1e-13
+
+
 def test_constant_diagonal_links_shift_momentum_per_colour():
     dims = (4, 4, 6, 2)
     alpha = np.array([[0.3, -0.1, -0.2], [0.05, 0.4, -0.45], [-0.7, 0.2, 0.5], [0.11, 0.13, -0.24]])
