@@ -187,6 +187,27 @@ def test_minus_mu_reuses_setup(dd):
     assert abs(s1["iters"] - s2["iters"]) <= max(2, 0.2 * s1["iters"])
 
 
+def test_squared_operator_as_two_solves(dd):
+    # D^dag D x = b as x = D(mu)^-1 G5 D(-mu)^-1 G5 b with one setup for both
+    # signs (Sec. 3: the squared operator is inverted by two solves of D;
+    # D(mu)^dag = G5 D(-mu) G5)
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, op, _ = make(dd, dims, block)
+    ctx.setup(dd.default_params(levels=2, block=[block], nvec=[12], setup_iters=2, coarse_mu_factor=3.0),
+              [synth.spinor(dims, 2511, nvec=12)])
+    g5 = np.array([-1.0, -1.0, 1.0, 1.0])[:, None]
+    b = synth.spinor(dims, 2512)
+    ctx.set_mu(-MU)
+    y, s1 = ctx.solve(g5 * b, tol=1e-11)
+    ctx.set_mu(MU)
+    x, s2 = ctx.solve(g5 * y, tol=1e-11)
+    assert s1["converged"] and s2["converged"]
+    r = b - g5 * op.apply(g5 * op.apply(x, MU), -MU)
+    # r = G5 e1 + D^dag e2 with |e1| <= 1e-11 |b|, |e2| <= 1e-11 |y| and
+    # |y| <= |b| / mu (D^dag D = D_W^dag D_W + mu^2); |D| < 16
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-11 * (1 + 16.0 / MU)
+
+
 # ------------------------------------------------------------------ twisted boundary conditions (Sec. 2)
 
 THETA = (np.pi, 0.4, -1.3, 2.0)
