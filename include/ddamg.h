@@ -187,7 +187,8 @@ int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise
  * p->coarse_setup_iters level-1 iterations, 1 and 3 in the paper's use).
  * With both iteration counts 0 the new D_c is the Galerkin operator of the old
  * P on the new field.  p must keep the levels, precision, nvec and aggregation
- * blocks of the current setup (INVALID_ARG otherwise).  BAD_STATE without a
+ * blocks of the current setup (INVALID_ARG otherwise).  The old and the new
+ * hierarchy are both held while the new one is allocated.  BAD_STATE without a
  * setup; a field with NaN or Inf returns NUMERICAL with the old field and
  * setup intact; any later error leaves the new field and no setup. */
 int ddamg_update_gauge(ddamg_ctx* ctx, const void* links, int on_device, const ddamg_params* p);
