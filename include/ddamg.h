@@ -202,6 +202,22 @@ int ddamg_update_gauge(ddamg_ctx* ctx, const void* links, int on_device, const d
 int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, ddamg_stats* st, int on_device);
 
 /* ---- single operators, for parity checks (host or device FP64 arrays) ---- */
+/* Hasenbusch-shifted odd-even reduced system (Sec. 3.1): with the odd-site
+ * reduced operator Dhat(mu) = D_oo - D_oe D_ee^-1 D_eo and Gamma5hat = Gamma5
+ * on the odd sites, solves (Dhat(mu) + i rho Gamma5hat) x_o = b_o as the
+ * full-lattice system D(mu; rho) x = (0, b_o), where D(mu; rho) is D(mu) with
+ * the odd-site twist raised to mu + rho (the full operator is what the
+ * multigrid cycle inverts, as the paper does for odd-even systems).  The
+ * outer FGMRES runs on D(mu; rho) in FP64 and is preconditioned by the cycle
+ * of the current setup (built for mu on all sites).  b: one fine spinor
+ * field; its even sites are ignored.  x receives the full solution: its odd
+ * sites are x_o, its even sites -D_ee^-1 D_eo x_o.  The second operator of the
+ * pair, Gamma5hat Dhat(-mu) Gamma5hat - i rho Gamma5hat, is this solve after
+ * ddamg_set_mu(-mu) with -rho and Gamma5 b, followed by Gamma5 on x.  Stops
+ * at a true relative residual <= tol of the full system; NOT_CONVERGED, the
+ * other errors and st as for ddamg_solve. */
+int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, double tol, ddamg_stats* st,
+                            int on_device);
 /* out = D(sign*mu) in, full lattice (Sec. 1); precision FP64 or FP32 (and
  * FP16/BF16 links with FP32 arithmetic). */
 int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int precision, int on_device);

@@ -240,6 +240,32 @@ def gamma5_field(psi):
     return spin_mul(GAMMA5, psi)
 
 
+def odd_mask(dims):
+    """1.0 on the odd sites (sum of the coordinates odd), 0.0 on the even ones."""
+    return (np.indices(tuple(dims)).sum(axis=0) % 2).astype(np.float64)
+
+
+def apply_odd_shifted(op, psi, rho: float, mu=None):
+    """D(mu; rho) psi: D(mu) with the twist of the odd sites raised by rho
+    (Sec. 3.1: the Hasenbusch-shifted operators carry an extra i rho Gamma5
+    on one parity)."""
+    m = odd_mask(op.dims)[..., None, None]
+    return op.apply(psi, mu) + 1j * rho * m * spin_mul(GAMMA5, psi)
+
+
+def schur_odd(op, psi, rho: float = 0.0, mu=None):
+    """(Dhat(mu) + i rho Gamma5hat) psi_o with Dhat = D_oo - D_oe D_ee^-1 D_eo,
+    the odd-site reduced operator (Sec. 3.1).  psi is a full-lattice field whose
+    even sites are ignored; the result is zero on the even sites.  Hops link
+    opposite parities only, so D_ee and D_oo are the site terms."""
+    m = odd_mask(op.dims)[..., None, None]
+    xo = m * psi
+    t = (1.0 - m) * op.hop(xo)              # D_eo x_o
+    u = (1.0 - m) * op.site_inv(t, mu)      # D_ee^-1 D_eo x_o
+    w = m * op.hop(u)                       # D_oe D_ee^-1 D_eo x_o
+    return m * op.site(xo, mu) + 1j * rho * m * spin_mul(GAMMA5, xo) - w
+
+
 def plane_wave_symbol(p, m0: float, mu: float):
     """Closed form of D(mu) on psi(x) = exp(i p.x) u in the free field (U = 1):
     m0 + sum_mu (1 - cos p_mu) + i sum_mu gamma_mu sin p_mu + i mu gamma5.

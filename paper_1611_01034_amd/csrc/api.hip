@@ -485,6 +485,56 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
   });
 }
 
+int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, double tol, ddamg_stats* stats,
+                            int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_setup(c);
+    if (!b || !x) throw Error(INVALID_ARG, "bad right-hand side arguments");
+    if (!(tol > 0) || !std::isfinite(tol)) throw Error(INVALID_ARG, "tol must be > 0");
+    if (!std::isfinite(rho)) throw Error(INVALID_ARG, "rho must be finite");
+    auto t0 = std::chrono::steady_clock::now();
+    const long N = c.fine_len();
+    c.f64c.ensure(sizeof(cx<double>) * N);
+    // D(mu) with the odd-site twist raised by rho, preconditioned by the
+    // cycle of the setup (built for mu on every site)
+    std::function<void(const cx<double>*, cx<double>*)> A = [&c, rho](const cx<double>* in, cx<double>* out) {
+      c.dirac64(in, out, c.mu);
+      launch_odd_twist_add(c.g, in, out, rho, c.st);
+    };
+    std::function<void(const cx<double>*, cx<double>*)> M = [&c](const cx<double>* in, cx<double>* out) {
+      c.mg->precond(in, out);
+    };
+    for (int l = 0; l < 4; ++l) c.mg->coarse_iters[l] = 0;
+    c.mg->vcycles = 0;
+    c.outer.init(c.p.restart, N, N, true);
+    c.upload_fine(b, on_device, c.f64a.as<cx<double>>());
+    check_finite(c, (const double*)c.f64a.p, 2 * N);
+    launch_zero_even(c.g, c.f64a.as<cx<double>>(), c.st);
+    KrylovResult kr = fgmres<double>(c, c.outer, N, A, &M, c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>(), tol,
+                                     c.p.max_iter, false, true);
+    c.download_fine(c.f64b.as<cx<double>>(), x, on_device);
+    c.sync();
+    c.outer.V.release();
+    c.outer.Z.release();
+    c.outer.tmp.release();
+    if (stats) {
+      stats->iters = kr.iters;
+      stats->converged = kr.converged ? 1 : 0;
+      stats->resid = kr.resid;
+      for (int l = 0; l < 4; ++l) stats->coarse_iters[l] = c.mg->coarse_iters[l];
+      stats->vcycles = c.mg->vcycles;
+      stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!kr.converged) {
+      c.err = "FGMRES reached max_iter before the tolerance";
+      return DDAMG_NOT_CONVERGED;
+    }
+    return DDAMG_OK;
+  });
+}
+
 int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int precision, int on_device) {
   if (!ctx) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {

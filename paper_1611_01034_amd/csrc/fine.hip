@@ -491,6 +491,40 @@ void launch_link_phase(const Geom& g, cx<double>* U, const LinkPhases& ph, hipSt
   hipLaunchKernelGGL(k_link_phase, dim3((g.V + 255) / 256), dim3(256), 0, st, g, U, ph);
 }
 
+// out += i rho Gamma5 in on the odd sites: the twist of the odd sites raised
+// by rho over that of the even sites (FP64 fine fields)
+__global__ void k_odd_twist_add(Geom g, const cx<double>* __restrict__ in, cx<double>* __restrict__ out, double rho) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)g.nblocks * g.half) return;
+  int B = (int)(gid / g.half), s = g.half + (int)(gid - (long)B * g.half);
+  const long o = fidx(g, B, s, 12);
+  for (int c = 0; c < 12; ++c) {
+    const double t = c < 6 ? -rho : rho;  // Gamma5 = diag(-1, -1, 1, 1) in spin
+    const cx<double> v = in[o + (long)c * TILE];
+    cx<double> w = out[o + (long)c * TILE];
+    w.re -= t * v.im;
+    w.im += t * v.re;
+    out[o + (long)c * TILE] = w;
+  }
+}
+void launch_odd_twist_add(const Geom& g, const cx<double>* in, cx<double>* out, double rho, hipStream_t st) {
+  const long n = (long)g.nblocks * g.half;
+  hipLaunchKernelGGL(k_odd_twist_add, dim3((n + 255) / 256), dim3(256), 0, st, g, in, out, rho);
+}
+
+// x = 0 on the even sites (FP64 fine field)
+__global__ void k_zero_even(Geom g, cx<double>* __restrict__ x) {
+  long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)g.nblocks * g.half) return;
+  int B = (int)(gid / g.half), s = (int)(gid - (long)B * g.half);
+  const long o = fidx(g, B, s, 12);
+  for (int c = 0; c < 12; ++c) x[o + (long)c * TILE] = mk(0.0, 0.0);
+}
+void launch_zero_even(const Geom& g, cx<double>* x, hipStream_t st) {
+  const long n = (long)g.nblocks * g.half;
+  hipLaunchKernelGGL(k_zero_even, dim3((n + 255) / 256), dim3(256), 0, st, g, x);
+}
+
 // ---------------------------------------------------------------------------
 // odd-site inverse factor M_chi = (H_chi^2 + tw^2)^{-1} (Hermitian positive
 // definite), by Cholesky; stored packed like H.

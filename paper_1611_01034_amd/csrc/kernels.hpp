@@ -74,6 +74,9 @@ struct LinkPhases {
 };
 void launch_links_from_lex(const Geom& g, const cx<double>* lex, cx<double>* U, const LinkPhases& ph,
                            hipStream_t st);
+// out += i rho Gamma5 in on the odd sites; x = 0 on the even sites (FP64)
+void launch_odd_twist_add(const Geom& g, const cx<double>* in, cx<double>* out, double rho, hipStream_t st);
+void launch_zero_even(const Geom& g, cx<double>* x, hipStream_t st);
 // multiply the boundary links of U (block layout) by ph in place
 void launch_link_phase(const Geom& g, cx<double>* U, const LinkPhases& ph, hipStream_t st);
 void launch_odd_inverse(const Geom& g, const double* H, double tw, double* M, hipStream_t st);

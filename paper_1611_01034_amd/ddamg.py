@@ -94,6 +94,7 @@ _SIGS = {
     "ddamg_setup": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
     "ddamg_set_test_vectors": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
     "ddamg_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(Stats), _i]),
+    "ddamg_solve_odd_shifted": (_i, [_vp, _vp, _vp, _d, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_apply_dirac": (_i, [_vp, _vp, _vp, _i, _i, _i]),
     "ddamg_sap": (_i, [_vp, _vp, _vp, _i, _i, _i, _i]),
     "ddamg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -335,6 +336,22 @@ class DDAMG:
         st = Stats()
         allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
         self._check(_lib.ddamg_solve(self._h, pb, px, nrhs, float(tol), ctypes.byref(st), dev), allow)
+        return x, st.as_dict()
+
+    def solve_odd_shifted(self, b, rho, tol=1e-10, x=None):
+        """Full solution of D(mu; rho) x = (0, b_odd) (ddamg_solve_odd_shifted):
+        its odd sites solve (Dhat(mu) + i rho Gamma5hat) x_o = b_o."""
+        b = _c128(b)
+        if x is None:
+            if _is_torch(b):
+                import torch
+                x = torch.empty_like(b)
+            else:
+                x = np.empty_like(b)
+        pb, dev = _ptr(b)
+        px, _ = _ptr(x)
+        st = Stats()
+        self._check(_lib.ddamg_solve_odd_shifted(self._h, pb, px, float(rho), float(tol), ctypes.byref(st), dev))
         return x, st.as_dict()
 
     # ---- single operators ---------------------------------------------------

@@ -208,6 +208,32 @@ def test_squared_operator_as_two_solves(dd):
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-11 * (1 + 16.0 / MU)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_hasenbusch_shifted_odd_even_systems(dd, prec):
+    # (Dhat(mu) + i rho G5hat) x_o = b_o and (G5hat Dhat(-mu) G5hat - i rho G5hat) x_o = b_o
+    # through the full operator with the odd-site twist raised by rho (Sec. 3.1)
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, op, _ = make(dd, dims, block)
+    ctx.setup(dd.default_params(levels=2, block=[block], nvec=[12], setup_iters=2, precision=prec,
+                                coarse_mu_factor=3.0), [synth.spinor(dims, 2521, nvec=12)])
+    g5 = np.array([-1.0, -1.0, 1.0, 1.0])[:, None]
+    odd = dirac.odd_mask(dims)[..., None, None]
+    b = synth.spinor(dims, 2522)
+    for rho in (0.0, 0.01, 0.1):
+        x, st = ctx.solve_odd_shifted(b, rho, tol=1e-10)
+        assert st["converged"]
+        assert rel(dirac.apply_odd_shifted(op, x, rho), odd * b) <= 1e-10
+        assert rel(dirac.schur_odd(op, x, rho), odd * b) <= 1e-9
+    rho = 0.01
+    ctx.set_mu(-MU)
+    y, st = ctx.solve_odd_shifted(g5 * b, -rho, tol=1e-10)
+    ctx.set_mu(MU)
+    assert st["converged"]
+    x = g5 * y
+    # G5hat (Dhat(-mu) - i rho G5hat) G5hat x_o = b_o
+    assert rel(g5 * dirac.schur_odd(op, g5 * x, -rho, -MU), odd * b) <= 1e-9
+
+
 # ------------------------------------------------------------------ twisted boundary conditions (Sec. 2)
 
 THETA = (np.pi, 0.4, -1.3, 2.0)

@@ -87,6 +87,30 @@ def test_twisted_boundary_equals_uniform_abelian_phase():
     assert np.abs(op.A - per.A).max() < 1e-13
 
 
+def test_odd_shifted_operator_and_schur_complement_dense():
+    # D(mu; rho) = D(mu) + i rho Gamma5 on the odd sites; its odd-site Schur
+    # complement from the dense blocks equals schur_odd, and the odd part of
+    # the full solve of D(mu; rho) x = (0, b_o) solves the reduced system
+    dims = (4, 2, 2, 4)
+    rho = 0.07
+    op = dirac.WilsonClover(synth.gauge_field(dims, 0.4, 19), KAPPA, CSW, 0.05)
+    D = op.dense()
+    odd = np.repeat(dirac.odd_mask(dims).reshape(-1) > 0.5, 12)
+    g5 = np.tile(np.repeat([-1.0, -1.0, 1.0, 1.0], 3), int(np.prod(dims)))
+    Ds = D + np.diag(1j * rho * g5 * odd)
+    e = synth.spinor(dims, 20)
+    assert np.abs(dirac.apply_odd_shifted(op, e, rho).reshape(-1) - Ds @ e.reshape(-1)).max() < 1e-13
+    o, ev = np.where(odd)[0], np.where(~odd)[0]
+    S = Ds[np.ix_(o, o)] - Ds[np.ix_(o, ev)] @ np.linalg.solve(Ds[np.ix_(ev, ev)], Ds[np.ix_(ev, o)])
+    got = dirac.schur_odd(op, e, rho).reshape(-1)
+    assert np.abs(got[o] - S @ e.reshape(-1)[o]).max() < 1e-12
+    assert np.abs(got[ev]).max() == 0.0
+    b = np.where(odd, e.reshape(-1), 0.0)
+    x = np.linalg.solve(Ds, b)
+    r = dirac.schur_odd(op, x.reshape(e.shape), rho).reshape(-1)[o] - e.reshape(-1)[o]
+    assert np.abs(r).max() < 1e-12
+
+
 def test_constant_diagonal_links_shift_momentum_per_colour():
     dims = (4, 4, 6, 2)
     alpha = np.array([[0.3, -0.1, -0.2], [0.05, 0.4, -0.45], [-0.7, 0.2, 0.5], [0.11, 0.13, -0.24]])
