@@ -209,7 +209,8 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
  * the odd-site twist raised to mu + rho (the full operator is what the
  * multigrid cycle inverts, as the paper does for odd-even systems).  The
  * outer FGMRES runs on D(mu; rho) in FP64 and is preconditioned by the cycle
- * of the current setup (built for mu on all sites).  b: one fine spinor
+ * of the current setup run with the mean twist mu + rho/2 on every site and
+ * level (the setup's twist is restored on return).  b: one fine spinor
  * field; its even sites are ignored.  x receives the full solution: its odd
  * sites are x_o, its even sites -D_ee^-1 D_eo x_o.  The second operator of the
  * pair, Gamma5hat Dhat(-mu) Gamma5hat - i rho Gamma5hat, is this solve after

@@ -498,11 +498,33 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
     const long N = c.fine_len();
     c.f64c.ensure(sizeof(cx<double>) * N);
     // D(mu) with the odd-site twist raised by rho, preconditioned by the
-    // cycle of the setup (built for mu on every site)
-    std::function<void(const cx<double>*, cx<double>*)> A = [&c, rho](const cx<double>* in, cx<double>* out) {
-      c.dirac64(in, out, c.mu);
+    // cycle of the setup with the mean twist mu + rho/2 on every site of every
+    // level (restored on return)
+    const double mu0 = c.mu;
+    std::function<void(const cx<double>*, cx<double>*)> A = [&c, mu0, rho](const cx<double>* in, cx<double>* out) {
+      c.dirac64(in, out, mu0);
       launch_odd_twist_add(c.g, in, out, rho, c.st);
     };
+    struct TwistScope {
+      Ctx& c;
+      double mu0;
+      bool on;
+      ~TwistScope() {
+        if (!on) return;
+        c.mu = mu0;
+        try {
+          c.rebuild_odd_inverse();
+          c.mg->set_mu(mu0);
+          c.sync();
+        } catch (...) {
+        }
+      }
+    } scope{c, mu0, rho != 0.0};
+    if (rho != 0.0) {
+      c.mu = mu0 + 0.5 * rho;
+      c.rebuild_odd_inverse();
+      c.mg->set_mu(c.mu);
+    }
     std::function<void(const cx<double>*, cx<double>*)> M = [&c](const cx<double>* in, cx<double>* out) {
       c.mg->precond(in, out);
     };

@@ -338,7 +338,7 @@ class DDAMG:
         self._check(_lib.ddamg_solve(self._h, pb, px, nrhs, float(tol), ctypes.byref(st), dev), allow)
         return x, st.as_dict()
 
-    def solve_odd_shifted(self, b, rho, tol=1e-10, x=None):
+    def solve_odd_shifted(self, b, rho, tol=1e-10, x=None, allow_not_converged=False):
         """Full solution of D(mu; rho) x = (0, b_odd) (ddamg_solve_odd_shifted):
         its odd sites solve (Dhat(mu) + i rho Gamma5hat) x_o = b_o."""
         b = _c128(b)
@@ -351,7 +351,9 @@ class DDAMG:
         pb, dev = _ptr(b)
         px, _ = _ptr(x)
         st = Stats()
-        self._check(_lib.ddamg_solve_odd_shifted(self._h, pb, px, float(rho), float(tol), ctypes.byref(st), dev))
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        self._check(_lib.ddamg_solve_odd_shifted(self._h, pb, px, float(rho), float(tol), ctypes.byref(st), dev),
+                    allow)
         return x, st.as_dict()
 
     # ---- single operators ---------------------------------------------------
