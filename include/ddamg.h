@@ -186,7 +186,9 @@ int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise
  * (p->init_sap_iters smoothing sweeps, usually 0; p->setup_iters fine and
  * p->coarse_setup_iters level-1 iterations, 1 and 3 in the paper's use).
  * With both iteration counts 0 the new D_c is the Galerkin operator of the old
- * P on the new field.  p must keep the levels, precision, nvec and aggregation
+ * P on the new field.  On three levels give p->coarse_setup_iters > 0 with
+ * p->setup_iters > 0: the level-1 test vectors are coefficients in the fine
+ * basis, which a fine iteration changes.  p must keep the levels, precision, nvec and aggregation
  * blocks of the current setup (INVALID_ARG otherwise).  The old and the new
  * hierarchy are both held while the new one is allocated.  BAD_STATE without a
  * setup; a field with NaN or Inf returns NUMERICAL with the old field and
