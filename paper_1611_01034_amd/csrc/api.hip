@@ -512,6 +512,8 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
       ~TwistScope() {
         if (!on) return;
         c.mu = mu0;
+        // a failure here can only follow a failure of the solve itself, whose
+        // error is the one the call reports
         try {
           c.rebuild_odd_inverse();
           c.mg->set_mu(mu0);
