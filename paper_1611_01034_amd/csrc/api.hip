@@ -509,15 +509,18 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
       Ctx& c;
       double mu0;
       bool on;
+      void restore() {
+        on = false;
+        c.mu = mu0;
+        c.rebuild_odd_inverse();
+        c.mg->set_mu(mu0);
+        c.sync();
+      }
+      // on an error path the solve's own error is the one reported
       ~TwistScope() {
         if (!on) return;
-        c.mu = mu0;
-        // a failure here can only follow a failure of the solve itself, whose
-        // error is the one the call reports
         try {
-          c.rebuild_odd_inverse();
-          c.mg->set_mu(mu0);
-          c.sync();
+          restore();
         } catch (...) {
         }
       }
@@ -539,6 +542,7 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
     KrylovResult kr = fgmres<double>(c, c.outer, N, A, &M, c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>(), tol,
                                      c.p.max_iter, false, true);
     c.download_fine(c.f64b.as<cx<double>>(), x, on_device);
+    if (scope.on) scope.restore();
     c.sync();
     c.outer.V.release();
     c.outer.Z.release();
