@@ -219,11 +219,15 @@ def test_hasenbusch_shifted_odd_even_systems(dd, prec):
     g5 = np.array([-1.0, -1.0, 1.0, 1.0])[:, None]
     odd = dirac.odd_mask(dims)[..., None, None]
     b = synth.spinor(dims, 2522)
+    _, s0 = ctx.solve(b, tol=1e-10)
     for rho in (0.0, 0.01, 0.1):
         x, st = ctx.solve_odd_shifted(b, rho, tol=1e-10)
         assert st["converged"]
         assert rel(dirac.apply_odd_shifted(op, x, rho), odd * b) <= 1e-10
         assert rel(dirac.schur_odd(op, x, rho), odd * b) <= 1e-9
+    # the setup's own twist is back: the plain solve repeats itself
+    x, s1 = ctx.solve(b, tol=1e-10)
+    assert s1["iters"] == s0["iters"] and rel(op.apply(x), b) <= 1e-10
     rho = 0.01
     ctx.set_mu(-MU)
     y, st = ctx.solve_odd_shifted(g5 * b, -rho, tol=1e-10)
