@@ -39,6 +39,10 @@ def test_default_params_follow_listing_1_names():
                              coarse_setup_iters=int(gold["MGCoarseSetupIter"]),
                              coarse_mu_factor=float(gold["MGCoarseMuFactor"]))
     assert (q.levels, q.setup_iters, q.coarse_setup_iters, q.coarse_mu_factor) == (3, 5, 3, 5.0)
+    # the setup frees its test vectors unless asked to keep them for an update
+    assert p.keep_test_vectors == 0
+    # the tail of the struct, as the library fills it (a layout mismatch shifts these)
+    assert (p.precision, p.batch, p.rhs_batch) == (ddamg.FP64, 16, 1)
 
 
 @pytest.mark.parametrize("dims,block", [((4, 4, 4, 6), (2, 2, 2, 2)),   # odd number of blocks in X
@@ -57,4 +61,7 @@ def test_null_context_calls_fail_cleanly():
     lib = ddamg._lib
     assert lib.ddamg_set_gauge(None, None, 0) == ddamg.INVALID_ARG
     assert lib.ddamg_solve(None, None, None, 1, 1e-10, None, 0) == ddamg.INVALID_ARG
+    assert lib.ddamg_update_gauge(None, None, 0, None) == ddamg.INVALID_ARG
+    assert lib.ddamg_set_boundary_phases(None, None) == ddamg.INVALID_ARG
+    assert lib.ddamg_solve_odd_shifted(None, None, None, 0.0, 1e-10, None, 0) == ddamg.INVALID_ARG
     assert lib.ddamg_last_error(None) == b"null context"
