@@ -224,8 +224,20 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
 /* out = D(sign*mu) in, full lattice (Sec. 1); precision FP64 or FP32 (and
  * FP16/BF16 links with FP32 arithmetic). */
 int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int precision, int on_device);
-/* iters SAP iterations on D x = b starting from x (updated in place). */
+/* iters SAP iterations on D x = b starting from x (updated in place): the
+ * smoother M of Eq. (1) (Sec. 1), red then black 4^4 blocks, each block solved
+ * by mr_steps MR steps on its even-site Schur complement (odd-even in the
+ * smoother, Sec. 3).  precision: DDAMG_FP64 or DDAMG_FP32 arithmetic, or
+ * DDAMG_FP16 / DDAMG_BF16 link storage with FP32 arithmetic (the links
+ * rounded to nearest even once, the clover term and odd-site inverses in
+ * FP32).  b, x: spinor layout, host or device. */
 int ddamg_sap(ddamg_ctx* ctx, const void* b, void* x, int iters, int mr_steps, int precision, int on_device);
+/* The same on nfields (1..16) independent systems D x_k = b_k at once, each
+ * colour sweep one launch for all fields (the form the setup and the
+ * preconditioner of several right-hand sides use); every field takes the
+ * arithmetic of a one-field sweep.  b, x: nfields contiguous spinor fields. */
+int ddamg_sap_multi(ddamg_ctx* ctx, int nfields, const void* b, void* x, int iters, int mr_steps, int precision,
+                    int on_device);
 /* level l >= 0: lattice dims of level l and components per site. */
 int ddamg_level_info(ddamg_ctx* ctx, int level, int dims[4], int* ncomp);
 /* orthonormalised test vectors spanning P from level l to l+1, level-l layout */
@@ -253,6 +265,22 @@ int ddamg_vcycle(ddamg_ctx* ctx, const void* in, void* out);
  * inputs rounded to the storage format (FP32 accumulation, twist in FP32);
  * otherwise the single-field kernel runs once per field. */
 int ddamg_apply_coarse_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out);
+/* The odd-even reduced operator of the coarsest level (Sec. 3: odd-even
+ * preconditioning on the coarsest level), S = D_ee - D_eo D_oo^-1 D_oe with the
+ * coarsest twist delta*mu in D_ee and D_oo, on nrhs (1..16) fields at once in
+ * the form the coarsest GMRES uses (matrix cores for FP16/BF16 storage and
+ * 2 N_v a multiple of 16, the inputs of every product rounded to the storage
+ * format, FP32 accumulation).  in, out: host complex128 [nrhs][len_l], layout
+ * of ddamg_apply_coarse; the odd-site entries of in are not read, those of out
+ * are zero.  level must be the coarsest. */
+int ddamg_apply_coarse_schur_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out);
+/* iters SAP iterations of an intermediate coarse level (the coarse-level
+ * smoother of the cycle; SAP blocks coarse_sap_block, coarse_mr_steps MR steps
+ * on each block operator) on nrhs (1..16) systems D_c x_k = b_k at once, with
+ * the block operator read once per MR step for all of them (matrix cores for
+ * FP16/BF16 storage).  b, x: host complex128 [nrhs][len_l], x updated in
+ * place. */
+int ddamg_coarse_sap_multi(ddamg_ctx* ctx, int level, int nrhs, const void* b, void* x, int iters);
 /* Coarse solves of nrhs right-hand sides in lock step (one operator launch
  * per step for all of them; each keeps its own Krylov space and stopping
  * test).  Same solver and layout as ddamg_coarse_solve; 1 <= nrhs <= 16. */

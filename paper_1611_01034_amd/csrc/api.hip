@@ -72,8 +72,16 @@ void sigma_table(double* tab) {
     }
 }
 
+// every buffer a call allocates comes from the context's pool
+struct PoolScope {
+  MemPool* prev;
+  explicit PoolScope(ddamg_ctx* ctx) : prev(current_pool()) { current_pool() = ctx ? &ctx->c.pool : nullptr; }
+  ~PoolScope() { current_pool() = prev; }
+};
+
 template <class F>
 int guard(ddamg_ctx* ctx, F&& f) {
+  PoolScope scope(ctx);
   try {
     if (ctx) ctx->c.err.clear();
     return f();
@@ -201,6 +209,8 @@ int ddamg_create(const int dims[4], const int block[4], double kappa, double csw
   int st = guard(ctx, [&]() {
     Ctx& c = ctx->c;
     c.st = (hipStream_t)stream;
+    HIP_CHECK(hipGetDevice(&c.dev));
+    c.pool.st = c.st;
     c.timer.st = c.st;
     Geom& g = c.g;
     g.V = 1;
@@ -423,7 +433,7 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
     if (Kb > 1) {
       // right-hand sides in groups of Kb through one lock-step outer FGMRES
       // (the one-column workspace is not allocated on this path)
-      KrylovWSm<double> ws;
+      KrylovWSm<double>& ws = c.outer_m;
       ws.init(c.p.restart, Kb, N, N, true);
       DevBuf bK, xK;
       bK.alloc(sizeof(cx<double>) * N * Kb);
@@ -465,10 +475,14 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
       c.download_fine(c.f64b.as<cx<double>>(), xs, on_device);
     }
     c.sync();
-    // the outer Krylov basis is the largest allocation; give it back between solves
+    // the outer Krylov basis is the largest allocation: its ranges go back to
+    // the context's pool between solves, for the setup's buffers to reuse
     c.outer.V.release();
     c.outer.Z.release();
     c.outer.tmp.release();
+    c.outer_m.V.release();
+    c.outer_m.Z.release();
+    c.outer_m.r.release();
     if (stats) {
       stats->iters = total_it;
       stats->converged = all_conv ? 1 : 0;
@@ -600,37 +614,65 @@ int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int p
   });
 }
 
-int ddamg_sap(ddamg_ctx* ctx, const void* b, void* x, int iters, int mr_steps, int precision, int on_device) {
+int ddamg_sap_multi(ddamg_ctx* ctx, int nfields, const void* b, void* x, int iters, int mr_steps, int precision,
+                    int on_device) {
   if (!ctx) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {
     Ctx& c = ctx->c;
     need_gauge(c);
     if (!b || !x || iters < 0 || mr_steps < 0) throw Error(INVALID_ARG, "bad SAP arguments");
-    long N = c.fine_len();
-    c.upload_fine(b, on_device, c.f64a.as<cx<double>>());
-    c.upload_fine(x, on_device, c.f64b.as<cx<double>>());
+    if (nfields < 1 || nfields > 16) throw Error(INVALID_ARG, "nfields must be in [1, 16]");
+    if (precision < DDAMG_FP64 || precision > DDAMG_BF16) throw Error(INVALID_ARG, "unknown precision");
+    const long N = c.fine_len();
+    const int K = nfields;
+    const size_t fb = sizeof(cx<double>) * (size_t)N;
+    // K fields in block layout, stride N: FP64 staging, then the working precision
+    DevBuf b64, x64;
+    b64.alloc(fb * K);
+    x64.alloc(fb * K);
+    for (int k = 0; k < K; ++k) {
+      c.upload_fine((const char*)b + fb * k, on_device, b64.as<cx<double>>() + (long)k * N);
+      c.upload_fine((const char*)x + fb * k, on_device, x64.as<cx<double>>() + (long)k * N);
+    }
     if (precision == DDAMG_FP64) {
       for (int it = 0; it < iters; ++it)
         for (int col = 0; col < 2; ++col)
-          launch_sap<double, double>(c.g, col, c.U64.p, c.H64.as<double>(), c.M64.as<double>(), c.mu,
-                                     c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>(), mr_steps, c.st);
-    } else if (precision == DDAMG_FP32) {
+          launch_sap_multi<double, double>(c.g, col, c.U64.p, c.H64.as<double>(), c.M64.as<double>(), c.mu,
+                                           b64.as<cx<double>>(), x64.as<cx<double>>(), mr_steps, K, N, c.st);
+    } else {
       c.ensure_32();
-      c.f32a.ensure(sizeof(cx<float>) * N);
-      c.f32b.ensure(sizeof(cx<float>) * N);
-      launch_copy_cvt<double, float>(c.f64a.as<cx<double>>(), c.f32a.as<cx<float>>(), N, c.st);
-      launch_copy_cvt<double, float>(c.f64b.as<cx<double>>(), c.f32b.as<cx<float>>(), N, c.st);
+      const void* U = c.U32.p;
+      if (precision != DDAMG_FP32) {
+        c.ensure_16(precision);
+        U = c.U16.p;
+      }
+      DevBuf b32, x32;
+      b32.alloc(sizeof(cx<float>) * (size_t)N * K);
+      x32.alloc(sizeof(cx<float>) * (size_t)N * K);
+      launch_copy_cvt<double, float>(b64.as<cx<double>>(), b32.as<cx<float>>(), N * K, c.st);
+      launch_copy_cvt<double, float>(x64.as<cx<double>>(), x32.as<cx<float>>(), N * K, c.st);
       for (int it = 0; it < iters; ++it)
-        for (int col = 0; col < 2; ++col)
-          launch_sap<float, float>(c.g, col, c.U32.p, c.H32.as<float>(), c.M32.as<float>(), c.mu,
-                                   c.f32a.as<cx<float>>(), c.f32b.as<cx<float>>(), mr_steps, c.st);
-      launch_copy_cvt<float, double>(c.f32b.as<cx<float>>(), c.f64b.as<cx<double>>(), N, c.st);
-    } else
-      throw Error(INVALID_ARG, "SAP parity entry supports FP64 and FP32");
-    c.download_fine(c.f64b.as<cx<double>>(), x, on_device);
+        for (int col = 0; col < 2; ++col) {
+          if (precision == DDAMG_FP32)
+            launch_sap_multi<float, float>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.mu,
+                                           b32.as<cx<float>>(), x32.as<cx<float>>(), mr_steps, K, N, c.st);
+          else if (precision == DDAMG_FP16)
+            launch_sap_multi<float, f16>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.mu,
+                                         b32.as<cx<float>>(), x32.as<cx<float>>(), mr_steps, K, N, c.st);
+          else
+            launch_sap_multi<float, bf16>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.mu,
+                                          b32.as<cx<float>>(), x32.as<cx<float>>(), mr_steps, K, N, c.st);
+        }
+      launch_copy_cvt<float, double>(x32.as<cx<float>>(), x64.as<cx<double>>(), N * K, c.st);
+    }
+    for (int k = 0; k < K; ++k) c.download_fine(x64.as<cx<double>>() + (long)k * N, (char*)x + fb * k, on_device);
     c.sync();
     return DDAMG_OK;
   });
+}
+
+int ddamg_sap(ddamg_ctx* ctx, const void* b, void* x, int iters, int mr_steps, int precision, int on_device) {
+  return ddamg_sap_multi(ctx, 1, b, x, iters, mr_steps, precision, on_device);
 }
 
 int ddamg_level_info(ddamg_ctx* ctx, int level, int dims[4], int* ncomp) {
@@ -735,6 +777,27 @@ int ddamg_coarse_solve_multi(ddamg_ctx* ctx, int level, int nrhs, const void* b,
     LEVEL_CHECK(1, 0);
     if (nrhs < 1 || nrhs > 16 || !b || !x) throw Error(INVALID_ARG, "nrhs must be in [1, 16]");
     c.mg->coarse_solve_multi_host(level, nrhs, (const cx<double>*)b, (cx<double>*)x);
+    return DDAMG_OK;
+  });
+}
+int ddamg_apply_coarse_schur_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 0);
+    if (level != c.mg->nlev() - 1) throw Error(INVALID_ARG, "level must be the coarsest");
+    if (nrhs < 1 || nrhs > 16 || !in || !out) throw Error(INVALID_ARG, "nrhs must be in [1, 16]");
+    c.mg->schur_multi_host(level, nrhs, (const cx<double>*)in, (cx<double>*)out);
+    return DDAMG_OK;
+  });
+}
+int ddamg_coarse_sap_multi(ddamg_ctx* ctx, int level, int nrhs, const void* b, void* x, int iters) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    LEVEL_CHECK(1, 1);
+    if (nrhs < 1 || nrhs > 16 || !b || !x || iters < 0) throw Error(INVALID_ARG, "nrhs must be in [1, 16]");
+    c.mg->coarse_sap_multi_host(level, nrhs, (const cx<double>*)b, (cx<double>*)x, iters);
     return DDAMG_OK;
   });
 }

@@ -67,6 +67,113 @@ __global__ void k_all_finite(long n, const double* __restrict__ a, int* __restri
 }
 
 // ---------------------------------------------------------------------------
+MemPool*& current_pool() {
+  static thread_local MemPool* p = nullptr;
+  return p;
+}
+
+namespace {
+constexpr size_t kGranule = 256;
+constexpr size_t kMinSlab = size_t(64) << 20;  // small buffers share 64 MiB slabs
+constexpr size_t kSlabRound = size_t(2) << 20;
+}  // namespace
+
+void* MemPool::get(size_t b) {
+  b = (b + kGranule - 1) / kGranule * kGranule;
+  // best fit over the free ranges of every slab
+  Slab* best = nullptr;
+  size_t best_off = 0, best_len = ~size_t(0);
+  for (auto& s : slabs)
+    for (auto& fr : s.free)
+      if (fr.second >= b && fr.second < best_len) {
+        best = &s;
+        best_off = fr.first;
+        best_len = fr.second;
+      }
+  if (best) {
+    if (dirty) {
+      HIP_CHECK(hipStreamSynchronize(st));
+      dirty = false;
+    }
+    best->free.erase(best_off);
+    if (best_len > b) best->free[best_off + b] = best_len - b;
+    best->used += b;
+    return best->base + best_off;
+  }
+  size_t sb = std::max(b, kMinSlab);
+  sb = (sb + kSlabRound - 1) / kSlabRound * kSlabRound;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sb);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    trim();
+    e = hipMalloc(&p, sb);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+      (void)hipGetLastError();
+      throw Error(OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed (" +
+                                     std::to_string(reserved()) + " bytes held by the context)");
+    }
+  }
+  HIP_CHECK(e);
+  Slab s;
+  s.base = (char*)p;
+  s.bytes = sb;
+  s.used = b;
+  if (sb > b) s.free[b] = sb - b;
+  slabs.push_back(std::move(s));
+  return p;
+}
+
+void MemPool::put(void* p, size_t b) {
+  b = (b + kGranule - 1) / kGranule * kGranule;
+  char* c = (char*)p;
+  for (auto& s : slabs) {
+    if (c < s.base || c >= s.base + s.bytes) continue;
+    size_t off = (size_t)(c - s.base), len = b;
+    auto next = s.free.find(off + len);
+    if (next != s.free.end()) {
+      len += next->second;
+      s.free.erase(next);
+    }
+    auto it = s.free.lower_bound(off);
+    if (it != s.free.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == off) {
+        off = prev->first;
+        len += prev->second;
+        s.free.erase(prev);
+      }
+    }
+    s.free[off] = len;
+    s.used -= b;
+    dirty = true;
+    return;
+  }
+}
+
+void MemPool::trim() {
+  (void)hipStreamSynchronize(st);
+  std::vector<Slab> keep;
+  for (auto& s : slabs) {
+    if (s.used == 0) (void)hipFree(s.base);
+    else keep.push_back(std::move(s));
+  }
+  slabs.swap(keep);
+  dirty = false;
+}
+
+size_t MemPool::reserved() const {
+  size_t t = 0;
+  for (auto& s : slabs) t += s.bytes;
+  return t;
+}
+
+MemPool::~MemPool() {
+  if (!slabs.empty()) (void)hipStreamSynchronize(st);
+  for (auto& s : slabs) (void)hipFree(s.base);
+}
+
+// ---------------------------------------------------------------------------
 hipEvent_t KernelTimer::get() {
   if (!pool.empty()) {
     hipEvent_t e = pool.back();
@@ -1501,6 +1608,44 @@ struct MG : MGBase {
       launch_copy_cvt<double, R>(a.as<cx<double>>(), bb + k * len, len, c.st);
     }
     coarse_solve_m(l, bb, xx, K);
+    for (int k = 0; k < K; ++k) {
+      launch_copy_cvt<R, double>(xx + k * len, a.as<cx<double>>(), len, c.st);
+      download_level(l, a.as<cx<double>>(), x + k * len);
+    }
+  }
+  void schur_multi_host(int l, int K, const cx<double>* in, cx<double>* out) override {
+    if (l != L - 1) throw Error(INVALID_ARG, "the odd-even reduced operator is formed on the coarsest level only");
+    ensure_multi(K);
+    const long len = level_len(l);
+    DevBuf a;
+    a.alloc(sizeof(cx<double>) * len);
+    cx<R>* x = rcm[l].template as<cx<R>>();
+    cx<R>* y = ecm[l].template as<cx<R>>();
+    for (int k = 0; k < K; ++k) {
+      upload_level(l, in + k * len, 0, a.as<cx<double>>());
+      launch_copy_cvt<double, R>(a.as<cx<double>>(), x + k * len, len, c.st);
+    }
+    launch_zero<R>(len * K, y, c.st);
+    AopM[l](x, y, K);
+    for (int k = 0; k < K; ++k) {
+      launch_copy_cvt<R, double>(y + k * len, a.as<cx<double>>(), len, c.st);
+      download_level(l, a.as<cx<double>>(), out + k * len);
+    }
+  }
+  void coarse_sap_multi_host(int l, int K, const cx<double>* b, cx<double>* x, int iters) override {
+    ensure_multi(K);
+    const long len = level_len(l);
+    DevBuf a;
+    a.alloc(sizeof(cx<double>) * len);
+    cx<R>* bb = rcm[l].template as<cx<R>>();
+    cx<R>* xx = ecm[l].template as<cx<R>>();
+    for (int k = 0; k < K; ++k) {
+      upload_level(l, b + k * len, 0, a.as<cx<double>>());
+      launch_copy_cvt<double, R>(a.as<cx<double>>(), bb + k * len, len, c.st);
+      upload_level(l, x + k * len, 0, a.as<cx<double>>());
+      launch_copy_cvt<double, R>(a.as<cx<double>>(), xx + k * len, len, c.st);
+    }
+    coarse_sap_m(l, bb, xx, K, iters);
     for (int k = 0; k < K; ++k) {
       launch_copy_cvt<R, double>(xx + k * len, a.as<cx<double>>(), len, c.st);
       download_level(l, a.as<cx<double>>(), x + k * len);

@@ -3,6 +3,7 @@
 #pragma once
 #include <chrono>
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
 #include <utility>
@@ -13,15 +14,57 @@
 
 namespace ddamg {
 
+// Device memory of one context.  Slabs obtained with hipMalloc stay with the
+// context until it is destroyed: on this device a hipMalloc of memory that
+// the process freed earlier costs up to a second per few GB (a 7.6 GB block:
+// 1.26 s), while a first-time allocation costs microseconds, so a setup or
+// solve that gives its buffers back and takes them again would pay that on
+// every call.  Buffers take best-fit ranges out of the slabs (256-byte
+// granules); released ranges merge with free neighbours.  Every kernel of a
+// context runs on its one stream, so a range released and handed out again is
+// reused in stream order; the first reuse after any release synchronises that
+// stream once, which covers synchronous host copies into a reused range
+// (hipFree synchronised the device for the same reason).  When hipMalloc
+// fails, slabs with nothing in use are freed and the allocation retried.
+struct MemPool {
+  struct Slab {
+    char* base = nullptr;
+    size_t bytes = 0, used = 0;
+    std::map<size_t, size_t> free;  // offset -> length of the free ranges
+  };
+  std::vector<Slab> slabs;
+  hipStream_t st = nullptr;         // the owning context's stream
+  bool dirty = false;               // a range was released since the last synchronisation
+  void* get(size_t b);
+  void put(void* p, size_t b);
+  void trim();                      // hipFree every slab with nothing in use
+  size_t reserved() const;
+  MemPool() = default;
+  MemPool(const MemPool&) = delete;
+  MemPool& operator=(const MemPool&) = delete;
+  ~MemPool();
+};
+
+// the pool of the context whose entry point is running on this thread (set by
+// the C interface for the duration of a call); without one, DevBuf uses
+// hipMalloc/hipFree directly
+MemPool*& current_pool();
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  MemPool* pool = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   void alloc(size_t b) {
     release();
-    if (b) {
+    if (!b) return;
+    MemPool* mp = current_pool();
+    if (mp) {
+      p = mp->get(b);
+      pool = mp;
+    } else {
       hipError_t e = hipMalloc(&p, b);
       if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
         (void)hipGetLastError();
@@ -29,21 +72,26 @@ struct DevBuf {
         throw Error(OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
       }
       HIP_CHECK(e);
-      bytes = b;
     }
+    bytes = b;
   }
   void ensure(size_t b) {
     if (bytes < b) alloc(b);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (pool) pool->put(p, bytes);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
+    pool = nullptr;
   }
   ~DevBuf() { release(); }
   void swap(DevBuf& o) {
     std::swap(p, o.p);
     std::swap(bytes, o.bytes);
+    std::swap(pool, o.pool);
   }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
@@ -178,6 +226,10 @@ struct MGBase {
   // K columns of a level-l field, host FP64 [K][len] in the level layout
   virtual void apply_coarse_multi_host(int l, int K, const cx<double>* in, cx<double>* out) = 0;
   virtual void coarse_solve_multi_host(int l, int K, const cx<double>* b, cx<double>* x) = 0;
+  // K columns of the coarsest level's odd-even reduced operator (even-site
+  // parts of in; out zero on odd sites), and K-field SAP on an intermediate level
+  virtual void schur_multi_host(int l, int K, const cx<double>* in, cx<double>* out) = 0;
+  virtual void coarse_sap_multi_host(int l, int K, const cx<double>* b, cx<double>* x, int iters) = 0;
   // napply launches of the K-column coarse operator of level l on device-resident
   // work vectors (which = 0: full stencil, 1: odd-even reduced operator, coarsest level)
   virtual void bench_coarse_multi(int l, int K, int napply, int which) = 0;
@@ -210,7 +262,9 @@ struct NetState {
 };
 
 struct Ctx {
+  MemPool pool;  // first member: destroyed after every buffer that returns to it
   hipStream_t st = nullptr;
+  int dev = 0;                 // HIP device current at ddamg_create
   Geom g{};
   double kappa = 0, csw = 0, mu = 0, m0 = 0;
   double theta[4] = {0, 0, 0, 0};  // twisted boundary conditions (0: periodic)
@@ -227,6 +281,7 @@ struct Ctx {
   ddamg_params p{};
   std::unique_ptr<MGBase> mg;
   KrylovWS<double> outer;
+  KrylovWSm<double> outer_m;   // lock-step outer solves (basis released to the pool between solves)
   NetState net;
   KernelTimer timer;
   std::string err;

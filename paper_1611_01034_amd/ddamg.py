@@ -97,6 +97,9 @@ _SIGS = {
     "ddamg_solve_odd_shifted": (_i, [_vp, _vp, _vp, _d, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_apply_dirac": (_i, [_vp, _vp, _vp, _i, _i, _i]),
     "ddamg_sap": (_i, [_vp, _vp, _vp, _i, _i, _i, _i]),
+    "ddamg_sap_multi": (_i, [_vp, _i, _vp, _vp, _i, _i, _i, _i]),
+    "ddamg_apply_coarse_schur_multi": (_i, [_vp, _i, _i, _vp, _vp]),
+    "ddamg_coarse_sap_multi": (_i, [_vp, _i, _i, _vp, _vp, _i]),
     "ddamg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "ddamg_get_interpolation": (_i, [_vp, _i, _vp]),
     "ddamg_restrict": (_i, [_vp, _i, _vp, _vp]),
@@ -371,6 +374,14 @@ class DDAMG:
                                    PRECISIONS[precision], 0))
         return x
 
+    def sap_multi(self, bs, xs0, iters, mr_steps=4, precision="fp64"):
+        """bs, xs0: [K, T, Z, Y, X, 4, 3] (host); K fields through one launch per colour."""
+        bs = _c128(bs)
+        xs = np.array(xs0, dtype=np.complex128, copy=True)
+        self._check(_lib.ddamg_sap_multi(self._h, int(bs.shape[0]), _ptr(bs)[0], _ptr(xs)[0], int(iters),
+                                         int(mr_steps), PRECISIONS[precision], 0))
+        return xs
+
     def level_info(self, level):
         d = (ctypes.c_int * 4)()
         n = ctypes.c_int()
@@ -436,6 +447,22 @@ class DDAMG:
         x = np.empty_like(bs)
         self._check(_lib.ddamg_coarse_solve_multi(self._h, int(level), int(bs.shape[0]), _ptr(bs)[0], _ptr(x)[0]))
         return x
+
+    def apply_coarse_schur_multi(self, level, ys):
+        """Odd-even reduced operator of the coarsest level on [nrhs, ...] fields
+        (odd-site entries of the input ignored, zero in the output)."""
+        ys = _c128(ys)
+        out = np.empty_like(ys)
+        self._check(_lib.ddamg_apply_coarse_schur_multi(self._h, int(level), int(ys.shape[0]), _ptr(ys)[0],
+                                                        _ptr(out)[0]))
+        return out
+
+    def coarse_sap_multi(self, level, bs, xs0, iters):
+        bs = _c128(bs)
+        xs = np.array(xs0, dtype=np.complex128, copy=True)
+        self._check(_lib.ddamg_coarse_sap_multi(self._h, int(level), int(bs.shape[0]), _ptr(bs)[0], _ptr(xs)[0],
+                                                int(iters)))
+        return xs
 
     def bench_coarse(self, level, nrhs, napply, which=0):
         self._check(_lib.ddamg_bench_coarse(self._h, int(level), int(nrhs), int(napply), int(which)))
