@@ -224,6 +224,21 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
 /* out = D(sign*mu) in, full lattice (Sec. 1); precision FP64 or FP32 (and
  * FP16/BF16 links with FP32 arithmetic). */
 int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int precision, int on_device);
+/* out = D(sign*mu) in in FP64, allocating nothing: for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same operator and kernels as
+ * ddamg_apply_dirac with precision DDAMG_FP64; in and out are device arrays
+ * (spinor layout above, complex128, caller-owned, may not alias).  The two
+ * block-layout fields it needs live in a scratch array of the library that
+ * every device it runs on holds for the life of the process (48 MiB: two
+ * fields of at most 131072 sites); lattices with more sites return
+ * INVALID_ARG.  The call only enqueues its kernels on the context's stream and
+ * returns: out is ready when that stream reaches them.  Every call on one
+ * device shares the one scratch array, so calls that can overlap on one GPU
+ * (contexts on different streams) race; the array needs no clearing, since
+ * each call writes every entry it reads.  sign must be +1 or -1; BAD_STATE
+ * without a gauge field. */
+int ddamg_apply_dirac_noalloc(ddamg_ctx* ctx, const void* in, void* out, int sign);
 /* iters SAP iterations on D x = b starting from x (updated in place): the
  * smoother M of Eq. (1) (Sec. 1), red then black 4^4 blocks, each block solved
  * by mr_steps MR steps on its even-site Schur complement (odd-even in the

@@ -210,6 +210,7 @@ int ddamg_create(const int dims[4], const int block[4], double kappa, double csw
     Ctx& c = ctx->c;
     c.st = (hipStream_t)stream;
     HIP_CHECK(hipGetDevice(&c.dev));
+    noalloc_scratch_init(c.dev);
     c.pool.st = c.st;
     c.timer.st = c.st;
     Geom& g = c.g;

@@ -300,4 +300,8 @@ struct Ctx {
 
 std::unique_ptr<MGBase> make_mg(Ctx& c);
 
+// records the device address of ddamg_apply_dirac_noalloc's scratch array on
+// device dev (the current device), once per device
+void noalloc_scratch_init(int dev);
+
 }  // namespace ddamg

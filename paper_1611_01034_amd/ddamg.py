@@ -96,6 +96,7 @@ _SIGS = {
     "ddamg_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_solve_odd_shifted": (_i, [_vp, _vp, _vp, _d, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_apply_dirac": (_i, [_vp, _vp, _vp, _i, _i, _i]),
+    "ddamg_apply_dirac_noalloc": (_i, [_vp, _vp, _vp, _i]),
     "ddamg_sap": (_i, [_vp, _vp, _vp, _i, _i, _i, _i]),
     "ddamg_sap_multi": (_i, [_vp, _i, _vp, _vp, _i, _i, _i, _i]),
     "ddamg_apply_coarse_schur_multi": (_i, [_vp, _i, _i, _vp, _vp]),
@@ -365,6 +366,19 @@ class DDAMG:
         out = np.empty_like(psi) if not _is_torch(psi) else psi.new_empty(psi.shape)
         pi, dev = _ptr(psi)
         self._check(_lib.ddamg_apply_dirac(self._h, pi, _ptr(out)[0], int(sign), PRECISIONS[precision], dev))
+        return out
+
+    def apply_dirac_noalloc(self, psi, out, sign=+1):
+        """D(sign*mu) psi into out, both complex128 CUDA tensors of the
+        spinor shape, without any allocation by the library; enqueued on the
+        context stream (synchronise before reading out)."""
+        if not (_is_torch(psi) and _is_torch(out)) or not (psi.is_cuda and out.is_cuda):
+            raise TypeError("apply_dirac_noalloc takes CUDA tensors")
+        if psi.dtype != out.dtype or str(psi.dtype) != "torch.complex128" or psi.shape != out.shape:
+            raise TypeError("psi and out must be complex128 tensors of one shape")
+        if not (psi.is_contiguous() and out.is_contiguous()):
+            raise ValueError("psi and out must be contiguous")
+        self._check(_lib.ddamg_apply_dirac_noalloc(self._h, psi.data_ptr(), out.data_ptr(), int(sign)))
         return out
 
     def sap(self, b, x0, iters, mr_steps=4, precision="fp64"):
