@@ -85,21 +85,25 @@ __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::el
   }
 }
 
-// SAP colour sweep.  One workgroup per block of the colour, one thread per
-// site: threads [0, half) own the even slots, [half, bs) the odd slots.
-//   r = b - D x on the block;  rho = r_e - D_eo T_oo^{-1} r_o;
-//   n_mr MR steps on S = T_ee - D_eo T_oo^{-1} D_oe (block-local hops only);
-//   e_o = T_oo^{-1} (r_o - D_oe e_e);  x += e.
+// SAP colour sweep.  One workgroup per block of the colour (and field), one
+// thread per pair of slots: thread i owns even slot i and odd slot half + i,
+// so both wavefronts of a block have work in the even-site and in the
+// odd-site half of every MR step.
+//   r = b - D x on the block;  t_o = T_oo^{-1} r_o,  x_o += t_o;
+//   rho = r_e - D_eo t_o;  n_mr MR steps on S = T_ee - D_eo T_oo^{-1} D_oe
+//   (block-local hops only) accumulate e_e;  x_e += e_e,
+//   x_o -= T_oo^{-1} D_oe e_e  (together: x_o += T_oo^{-1} (r_o - D_oe e_e)).
+// x of a block is read and written by its own workgroup only: the residual
+// reads the other colour's blocks, which this sweep leaves unchanged.
 template <class R, class S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 1 : 3, 8)))
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 1 : 2, 8)))
 k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H,
       const R* __restrict__ Minv, R tw, const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr, int K,
       long ld) {
   extern __shared__ char smem_raw[];
   cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x half, even slots
   cx<R>* od = ev + 12 * g.half;                     // 12 x half, odd slots
-  cx<R>* epsb = od + 12 * g.half;                   // 12 x half, accumulated correction (even)
-  __shared__ double red[3][16];
+  __shared__ double red[2][3][2];                    // per-wavefront sums, by MR step parity
   int B;
   {
     // K right-hand sides interleaved: consecutive workgroups (same XCD) take
@@ -115,108 +119,120 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
     int par = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
     B = B0 + ((par ^ colour) & 1);
   }
-  const int t = threadIdx.x;
-  const bool even = t < g.half;
-  const int i = even ? t : t - g.half;  // index within the parity
-  const int lane = t & 63, wv = t >> 6, nw = (g.bs + 63) >> 6;
-  SiteNbr me;
-  me_of(g, B, t, me);
-  cx<R> r[12], tmp[12];
+  const int i = threadIdx.x;
+  const int se = i, so = g.half + i;
+  const int lane = i & 63, wv = i >> 6, nw = (g.half + 63) >> 6;
+  SiteNbr me_e, me_o;
+  me_of(g, B, se, me_e);
+  me_of(g, B, so, me_o);
+  cx<R> rho[12], ee[12], tmp[12];
   {
-    // r = b - D x, with x of this block staged in ev/od (free until the
-    // odd-site solve below)
-    cx<R> psi[12];
-    load_spinor(x, g, B, t, psi);
+    // r = b - D x with x of this block staged in ev/od
+    cx<R> psi[12], ro[12];
+    load_spinor(x, g, B, se, psi);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) *lds_site(ev, g, t, c) = psi[c];
-    site_term(H, g, B, t, tw, psi, tmp);
+    for (int c = 0; c < 12; ++c) *lds_site(ev, g, se, c) = psi[c];
+    site_term(H, g, B, se, tw, psi, rho);
+    __asm__ volatile("" ::: "memory");
+    load_spinor(x, g, B, so, psi);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) *lds_site(ev, g, so, c) = psi[c];
+    site_term(H, g, B, so, tw, psi, ro);
     __syncthreads();
-    hop_staged<R, S>(U, x, ev, g, B, t, me, tmp);
-    load_spinor(b, g, B, t, r);
+    hop_staged<R, S>(U, x, ev, g, B, se, me_e, rho);
+    __asm__ volatile("" ::: "memory");
+    hop_staged<R, S>(U, x, ev, g, B, so, me_o, ro);
+    load_spinor(b, g, B, se, psi);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r[c] -= tmp[c];
+    for (int c = 0; c < 12; ++c) rho[c] = psi[c] - rho[c];
+    load_spinor(b, g, B, so, psi);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ro[c] = psi[c] - ro[c];
     __syncthreads();
-    if (!even) {
-      site_inv(H, Minv, g, B, t, tw, r, tmp);
+    __asm__ volatile("" ::: "memory");
+    site_inv(H, Minv, g, B, so, tw, ro, tmp);
+    load_spinor(x, g, B, so, psi);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) od[c * g.half + i] = tmp[c];
+    for (int c = 0; c < 12; ++c) {
+      od[c * g.half + i] = tmp[c];
+      psi[c] += tmp[c];
     }
+    store_spinor(x, g, B, so, psi);
   }
   __syncthreads();
-  if (even) {
-    hop_block_lds<R, S, true>(U, g, B, t, me, od, g.half, r);  // r now holds rho
+  hop_block_lds<R, S, true>(U, g, B, se, me_e, od, g.half, rho);  // rho = r_e - D_eo t_o
 #pragma unroll
-    for (int c = 0; c < 12; ++c) epsb[c * g.half + i] = mk<R>(0, 0);
-  }
+  for (int c = 0; c < 12; ++c) ee[c] = mk<R>(0, 0);
+  const int nact = min(64, g.half - wv * 64);
   for (int k = 0; k < n_mr; ++k) {
-    if (even) {
+    // the block operator is re-read in every step: keeping the loop-invariant
+    // links, clover and inverses in registers would exceed the register file
+    __asm__ volatile("" ::: "memory");
 #pragma unroll
-      for (int c = 0; c < 12; ++c) ev[c * g.half + i] = r[c];
-    }
+    for (int c = 0; c < 12; ++c) ev[c * g.half + i] = rho[c];
     __syncthreads();
-    if (!even) {  // w = T_oo^{-1} D_oe rho
+    {  // w = T_oo^{-1} D_oe rho
       cx<R> u[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) u[c] = mk<R>(0, 0);
-      hop_block_lds<R, S>(U, g, B, t, me, ev, 0, u);
-      site_inv(H, Minv, g, B, t, tw, u, tmp);
+      hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, u);
+      site_inv(H, Minv, g, B, so, tw, u, tmp);
 #pragma unroll
       for (int c = 0; c < 12; ++c) od[c * g.half + i] = tmp[c];
     }
     __syncthreads();
+    __asm__ volatile("" ::: "memory");
+    // q = T_ee rho - D_eo w
+    site_term(H, g, B, se, tw, rho, tmp);
+    hop_block_lds<R, S, true>(U, g, B, se, me_e, od, g.half, tmp);
     double qr_re = 0, qr_im = 0, qq = 0;
-    if (even) {  // q = T_ee rho - D_eo w
-      site_term(H, g, B, t, tw, r, tmp);
-      hop_block_lds<R, S, true>(U, g, B, t, me, od, g.half, tmp);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        qr_re += (double)tmp[c].re * r[c].re + (double)tmp[c].im * r[c].im;
-        qr_im += (double)tmp[c].re * r[c].im - (double)tmp[c].im * r[c].re;
-        qq += (double)tmp[c].re * tmp[c].re + (double)tmp[c].im * tmp[c].im;
-      }
+    for (int c = 0; c < 12; ++c) {
+      qr_re += (double)tmp[c].re * rho[c].re + (double)tmp[c].im * rho[c].im;
+      qr_im += (double)tmp[c].re * rho[c].im - (double)tmp[c].im * rho[c].re;
+      qq += (double)tmp[c].re * tmp[c].re + (double)tmp[c].im * tmp[c].im;
     }
-    {
-      int nact = min(64, (int)blockDim.x - wv * 64);
-      qr_re = wave_sum_n(qr_re, nact);
-      qr_im = wave_sum_n(qr_im, nact);
-      qq = wave_sum_n(qq, nact);
-    }
+    qr_re = wave_sum_n(qr_re, nact);
+    qr_im = wave_sum_n(qr_im, nact);
+    qq = wave_sum_n(qq, nact);
     if (lane == 0) {
-      red[0][wv] = qr_re;
-      red[1][wv] = qr_im;
-      red[2][wv] = qq;
+      red[k & 1][0][wv] = qr_re;
+      red[k & 1][1][wv] = qr_im;
+      red[k & 1][2][wv] = qq;
     }
     __syncthreads();
-    if (even) {
-      double sr = 0, si = 0, sq = 0;
-      for (int v = 0; v < nw; ++v) {
-        sr += red[0][v];
-        si += red[1][v];
-        sq += red[2][v];
-      }
-      cx<R> alpha = mk<R>(0, 0);
-      if (sq > 0) alpha = mk<R>((R)(sr / sq), (R)(si / sq));
+    double sr = 0, si = 0, sq = 0;
+    for (int v = 0; v < nw; ++v) {
+      sr += red[k & 1][0][v];
+      si += red[k & 1][1][v];
+      sq += red[k & 1][2][v];
+    }
+    cx<R> alpha = mk<R>(0, 0);
+    if (sq > 0) alpha = mk<R>((R)(sr / sq), (R)(si / sq));
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        epsb[c * g.half + i] += alpha * r[c];
-        r[c] -= alpha * tmp[c];
-      }
+    for (int c = 0; c < 12; ++c) {
+      ee[c] += alpha * rho[c];
+      rho[c] -= alpha * tmp[c];
     }
-    __syncthreads();
   }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) ev[c * g.half + i] = ee[c];
   __syncthreads();
-  cx<R> xv[12];
-  load_spinor(x, g, B, t, xv);
-  if (even) {
+  {  // x_o -= T_oo^{-1} D_oe e_e
+    cx<R> u[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) xv[c] += epsb[c * g.half + i];
-  } else {  // e_o = T_oo^{-1} (r_o - D_oe e_e)
-    hop_block_lds<R, S, true>(U, g, B, t, me, epsb, 0, r);
-    site_inv(H, Minv, g, B, t, tw, r, tmp);
+    for (int c = 0; c < 12; ++c) u[c] = mk<R>(0, 0);
+    hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, u);
+    site_inv(H, Minv, g, B, so, tw, u, tmp);
+    load_spinor(x, g, B, so, u);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) xv[c] += tmp[c];
+    for (int c = 0; c < 12; ++c) u[c] -= tmp[c];
+    store_spinor(x, g, B, so, u);
   }
-  store_spinor(x, g, B, t, xv);
+  load_spinor(x, g, B, se, tmp);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tmp[c] += ee[c];
+  store_spinor(x, g, B, se, tmp);
 }
 
 template <class R, class S>
@@ -227,8 +243,8 @@ void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* M
 template <class R, class S>
 void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
                       cx<R>* x, int n_mr, int K, long ld, hipStream_t st) {
-  size_t sm = 3 * 12 * (size_t)g.half * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_sap<R, S>), dim3((g.nblocks / 2) * K), dim3(g.bs), sm, st, g, colour,
+  size_t sm = 2 * 12 * (size_t)g.half * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_sap<R, S>), dim3((g.nblocks / 2) * K), dim3(g.half), sm, st, g, colour,
                      (const typename store_traits<S>::elem*)U, H, Minv, (R)tw, b, x, n_mr, K, ld);
 }
 template void launch_sap_multi<double, double>(const Geom&, int, const void*, const double*, const double*, double,
@@ -1037,14 +1053,17 @@ template <class RQ>
 void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, const cx<RQ>* Q, long qstride,
                           const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st) {
   if (Nv < 1 || Nv > 32) throw Error(INVALID_ARG, "assembly: nvec must be in [1, 32]");
-  // sites per stage: LDS of two workgroups per CU
-  constexpr int CS = 4, CS4 = sizeof(RQ) == 8 ? 3 : 4;
+  // The Galerkin products are formed and summed in FP64 on the FP64 matrix
+  // cores for both storage formats of the test vectors (FP32 vectors are
+  // widened as they are staged).  Sites per stage: LDS of two workgroups per CU.
+  using T = double;
+  constexpr int CS = 4, CS4 = 3;
   const dim3 grid(6 * g.nblocks), blk(256);
   switch ((2 * Nv + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS, 1>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
-    case 2: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS, 2>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
-    case 3: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS, 3>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
-    default: hipLaunchKernelGGL((k_assemble_fine<RQ, RQ, CS4, 4>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    case 1: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 1>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    case 2: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 2>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    case 3: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 3>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    default: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS4, 4>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
   }
 }
 template void launch_assemble_fine<double>(const Geom&, int, const cx<double>*, const double*, const cx<double>*,
