@@ -296,3 +296,21 @@ def apply_at_sites(U, psi, kappa, csw, mu, sites):
         op = WilsonClover(Up, kappa, csw, mu)
         out.append(op.apply(pp)[1, 1, 1, 1])
     return np.stack(out)
+
+
+def apply_t_slab(U, psi, kappa, csw, mu, t0, nt):
+    """(D(mu) psi)(x) for the time slices t0 .. t0+nt-1 of a lattice of any size.
+
+    The slices t0-1 .. t0+nt (periodic in T) of the links and the spinor are
+    gathered and the operator is applied on that slab with its own periodic
+    T extent nt+2; on the nt inner slices every term of D (the site term with
+    its clover leaves, which reach one slice either way, and the eight hops)
+    only touches slices of the slab, so they are the exact values.  Returns
+    [nt, Z, Y, X, 4, 3].  U and psi may be any arrays indexable by a list of
+    time slices (numpy arrays, memory maps)."""
+    T = U.shape[0]
+    rows = [(t0 + k) % T for k in range(-1, nt + 1)]
+    Us = np.asarray(U[rows])
+    ps = np.asarray(psi[rows])
+    return WilsonClover(Us, kappa, csw, mu).apply(ps)[1:nt + 1]
+

@@ -66,6 +66,17 @@ def test_apply_at_sites_matches_full_apply():
     assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("t0,nt", [(0, 2), (3, 3), (6, 2), (1, 1)])
+def test_apply_t_slab_matches_full_apply(t0, nt):
+    dims = (8, 4, 2, 6)
+    U = synth.gauge_field(dims, 0.3, 3315)
+    psi = synth.gaussian(dims + (4, 3), 3316)
+    full = dirac.WilsonClover(U, KAPPA, CSW, 0.05).apply(psi)
+    got = dirac.apply_t_slab(U, psi, KAPPA, CSW, 0.05, t0, nt)
+    want = full[[(t0 + k) % dims[0] for k in range(nt)]]
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
 @pytest.mark.parametrize("delta", [1.0, 3.0])
 def test_level1_cycle_is_exact_coarse_correction(delta):
     # no level-1 smoothing, coarsest solved to 1e-14: cycle_1(w) = P_1 D_c,2^{-1} P_1^dag w,
