@@ -1,20 +1,28 @@
-"""Benchmark: DD-alpha-AMG time to a 1e-10 true residual at 48^3 x 96, mixed
-precision vs FP64, with the fine operator's D(mu) bandwidth against the HBM
-roofline.
+"""Benchmark: DD-alpha-AMG time to a 1e-10 true residual at 48^3 x 96 with 12
+right-hand sides, mixed precision vs FP64, with the fine operator's D(mu) and
+the SAP smoother's bandwidth against the HBM roofline.
 
-One step = the whole hot path on one batch of synthetic input: adaptive setup
-(test vectors, block QR, Galerkin coarse operators on every level) followed by
-the preconditioned FGMRES solve of every right-hand side to a true relative
-residual <= 1e-10.  Inputs (SU(3) links exp(i 0.3 H), Gaussian sources and
-initial test vectors, all seeded) are generated on the device before the
-timed region.
+One step = the whole hot path on one batch of synthetic input: the adaptive
+setup (learned initial test vectors, one refinement iteration, block QR,
+Galerkin coarse operators on every level) followed by the preconditioned
+FGMRES solve of every right-hand side to a true relative residual <= 1e-10
+(lock-step groups of --rhs-batch).  Inputs (SU(3) links exp(i 0.3 H),
+Gaussian sources, network noise and level-1 test vectors, all seeded) are
+generated on the device before the timed region.
 
-    python bench.py [--gpus 1] [--steps 1] [--warmup 0] [--nrhs 2]
-                    [--dims 96,48,48,48] [--fp64-compare 1]
+    python bench.py [--gpus 1] [--steps 1] [--warmup 0] [--nrhs 12]
+                    [--rhs-batch 3] [--fp64-compare 1] [--cpu-baseline 1]
 
 Prints one JSON line.  `value` is the mixed-precision step time in seconds
-(lower is better); the plain FP64 form is run once after the timed steps on
-the same inputs and reported as fp64_step_s.
+(lower is better).  After the timed steps:
+  * the plain FP64 form (random start, 5-iteration setup) runs once on the
+    same right-hand sides when it fits --time-budget (seconds since start),
+    else the line says it was skipped;
+  * the oracle leg (cpu_baseline): the FP64 CPU oracle applies D(mu) to the
+    solution of the first right-hand side over the whole 48^3 x 96 lattice in
+    time slabs on the host's cores, which times the oracle (GB/s with the
+    same algorithmic bytes as the device kernel) and gives the oracle's own
+    true residual of that solution and its agreement with the library's D(mu).
 """
 import argparse
 import hashlib
@@ -26,6 +34,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+T_START = time.time()
 METRIC = "D(μ) GB/s; DD-αAMG time to 1e-10 residual at 48^3×96, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 KAPPA, CSW, MU = 0.13729, 1.57551, 0.0009
@@ -39,16 +48,21 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--nrhs", type=int, default=2)
+    ap.add_argument("--nrhs", type=int, default=12)
     ap.add_argument("--dims", type=str, default="96,48,48,48")
     ap.add_argument("--precision", type=str, default="bf16")
     ap.add_argument("--setup-iters", type=int, default=1)
     ap.add_argument("--fp64-compare", type=int, default=1)
     ap.add_argument("--fp64-setup-iters", type=int, default=5)
+    ap.add_argument("--fp64-rhs-batch", type=int, default=2)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--rhs-batch", type=int, default=2)
+    ap.add_argument("--rhs-batch", type=int, default=3)
     ap.add_argument("--learned", type=int, default=1)
     ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="seconds since start beyond which the FP64 leg is skipped")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="override a solver parameter of the mixed form (ddamg_params field)")
     return ap.parse_args()
 
 
@@ -56,36 +70,72 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(nrhs, V_target):
-    """The oracle timed on a bounded sample: one 2-level setup + solve of the
-    4^4 configuration (Nv 8, 2^4 aggregates, 3 setup iterations, tol 1e-10),
-    scaled linearly by volume and by the number of right-hand sides."""
+def oracle_leg(U, x0, b0, y_lib, budget_s=25.0):
+    """The FP64 oracle on the host: D(mu) x0 over the whole lattice in time
+    slabs of two slices (one halo slice each side), on as many threads as the
+    host offers (at most 16).  Returns the cpu_baseline record and the
+    oracle's check of the device result (true residual of x0, agreement of
+    the library's D(mu) x0 with the oracle's)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
         threadpool_limits = None
-    import numpy as np
+    from oracle import dirac
 
-    from oracle import dirac, mg
-    from paper_1611_01034_amd import synth
+    T = U.shape[0]
+    nt = 2
+    slabs = list(range(0, T, nt))
+    sites_slab = nt * int(np.prod(U.shape[1:4]))
+    cores = max(1, min(16, os.cpu_count() or 1))
 
-    dims = (4, 4, 4, 4)
-    U = synth.gauge_field(dims, 0.3, 1001)
-    V0 = synth.gaussian((8,) + dims + (12,), 1501)
-    b = synth.spinor(dims, 1101).reshape(dims + (12,))
+    def work(t0):
+        t = time.time()
+        Dx = dirac.apply_t_slab(U, x0, KAPPA, CSW, MU, t0, nt)
+        dt = time.time() - t
+        rows = list(range(t0, t0 + nt))
+        r = b0[rows] - Dx
+        d = Dx - y_lib[rows]
+        return (dt, float(np.vdot(r, r).real), float(np.vdot(b0[rows], b0[rows]).real),
+                float(np.abs(d).max()), float(np.abs(Dx).max()))
+
     ctx = threadpool_limits(1) if threadpool_limits else None
-    t = time.time()
-    op = dirac.WilsonClover(U, KAPPA, CSW, MU)
-    h = mg.Hierarchy(op, mg.Params(levels=2, blocks=[(2, 2, 2, 2)], nvec=[8], setup_iters=3)).setup([V0])
-    x, info = h.solve(b, tol=1e-10)
-    dt = time.time() - t
-    if ctx is not None:
-        ctx.unregister() if hasattr(ctx, "unregister") else None
-    V = int(np.prod(dims))
-    return {"value": dt * (V_target / V) * nrhs, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"numpy FP64 oracle, 2-level setup (3 iterations) + 1 solve to 1e-10 on 4^4 "
-                      f"({dt:.2f} s measured, {info['iters']} FGMRES iterations), scaled by volume "
-                      f"x{V_target // V} and by {nrhs} right-hand sides"}
+    # one core: slabs one after another until the bounded sample is used
+    t1 = time.time()
+    one = []
+    for t0 in slabs:
+        one.append(work(t0))
+        if time.time() - t1 > budget_s / 2:
+            break
+    t1 = time.time() - t1
+    # all cores: the whole lattice (the slabs done above are not repeated)
+    rest = slabs[len(one):]
+    tp = time.time()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        many = list(ex.map(work, rest))
+    tp = time.time() - tp
+    if ctx is not None and hasattr(ctx, "unregister"):
+        ctx.unregister()
+    allr = one + many
+    r2 = sum(v[1] for v in allr)
+    b2 = sum(v[2] for v in allr)
+    dmax = max(v[3] for v in allr)
+    ymax = max(v[4] for v in allr)
+    gbs1 = len(one) * sites_slab * DIRAC_FP64_BYTES_PER_SITE / t1 / 1e9
+    gbsp = len(rest) * sites_slab * DIRAC_FP64_BYTES_PER_SITE / tp / 1e9 if rest else None
+    cpu = {"value": round(gbsp if gbsp else gbs1, 3), "unit": "GB/s", "cores": cores if gbsp else 1,
+           "kind": "oracle",
+           "sample": f"numpy FP64 oracle D(mu) on the 48^3x96 solution of the first right-hand side, time slabs "
+                     f"of {nt} slices with one halo slice each side: {len(rest)} slabs on {cores} threads in "
+                     f"{tp:.1f} s (whole lattice with the {len(one)} slabs timed on one thread in {t1:.1f} s, "
+                     f"{gbs1:.3f} GB/s); bytes counted as the device kernel's {DIRAC_FP64_BYTES_PER_SITE} B/site",
+           "one_core_gbs": round(gbs1, 4)}
+    check = {"oracle_true_residual_rhs0": float(np.sqrt(r2 / b2)),
+             "dirac_max_abs_diff_over_max": dmax / ymax,
+             "sites_checked": len(allr) * sites_slab}
+    return cpu, check
 
 
 DIRAC_SOURCES = ["dirac.hip", "finedev.hpp", "common.hpp"]
@@ -132,6 +182,7 @@ def main():
     cd = tuple(d // 4 for d in dims)
     nv = [24, 32]
     levels = 3
+    kb = min(args.rhs_batch, args.nrhs)
 
     log("generating inputs on the device")
     U = synth.gauge_field_device(dims, 0.3, 5001)
@@ -149,9 +200,9 @@ def main():
         V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
     torch.cuda.synchronize()
 
-    def make_ctx(net=False):
+    def make_ctx(Ug, net=False):
         c = ddamg.DDAMG(dims, block, KAPPA, CSW, MU, stream=stream.cuda_stream)
-        c.set_gauge(U)
+        c.set_gauge(Ug)
         if net:
             c.net_create(L, C)
             c.net_set_params(wts)
@@ -162,8 +213,17 @@ def main():
                                     coarse_setup_iters=3, precision=prec, coarse_mu_factor=5.0, batch=batch,
                                     rhs_batch=rhs_batch)
 
-    ctx = make_ctx(net=bool(args.learned))
-    p_mixed = params(args.precision, args.setup_iters, min(args.rhs_batch, args.nrhs), args.batch)
+    ctx = make_ctx(U, net=bool(args.learned))
+    # the device copy of the links is the library's from here on; the host
+    # oracle leg regenerates the same seeded field
+    del U
+    torch.cuda.empty_cache()
+    p_mixed = params(args.precision, args.setup_iters, kb, args.batch)
+    overrides = {}
+    for kv in args.set:
+        k, v = kv.split("=", 1)
+        overrides[k] = float(v) if "." in v or "e" in v else int(v)
+        setattr(p_mixed, k, overrides[k])
 
     def step(c, tag):
         t = time.time()
@@ -173,7 +233,8 @@ def main():
             c.setup(p_mixed, [V0, V1])
         log(f"{tag}: setup issued ({time.time() - t:.1f} s)")
         _, st = c.solve(b, tol=1e-10, x=x)
-        log(f"{tag}: solve done ({time.time() - t:.1f} s, {st['iters']} iterations)")
+        log(f"{tag}: solve done ({time.time() - t:.1f} s, {st['iters']} iterations over {st['nrhs']} rhs, "
+            f"{st['iters_min']}-{st['iters_max']} per rhs)")
         return st
 
     for i in range(args.warmup):
@@ -189,49 +250,80 @@ def main():
     n_d, ms_d = ctx.timing_query(0)
     kinds = {k: ctx.timing_query(i) for i, k in enumerate(["dirac_fp64", "fine_sap", "coarse_apply",
                                                             "transfer", "dirac_reduced", "coarsest_schur"])}
-    # the D(mu) FP64 launches of the residual check below are not in the timed region
+    # the D(mu) FP64 launches of the checks below are not in the timed region
     ctx.timing(False)
     log(f"mixed step {dt:.2f} s, stats {stats}")
 
-    # true residual of the last solve, checked in FP64 on the device
+    # true residuals of the last solve, checked in FP64 on the device
     resid = 0.0
     for i in range(args.nrhs):
         r = ctx.apply_dirac(x[i])
         resid = max(resid, float(torch.linalg.vector_norm(b[i] - r) / torch.linalg.vector_norm(b[i])))
+    y0 = ctx.apply_dirac(x[0]).cpu().numpy() if args.cpu_baseline else None
 
     # D(mu) FP64 bandwidth inside the timed steps (HIP events around every launch)
     avg_ms = ms_d / max(n_d, 1)
     bytes_launch = DIRAC_FP64_BYTES_PER_SITE * V
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if n_d else None
     src_hash = dirac_sources_sha256()
+    # fine SAP colour sweeps inside the timed steps: every launch sweeps the
+    # blocks of one colour for K fields (K = the setup's batch or the rhs
+    # group); the library adds up each launch's algorithmic bytes
+    n_s, ms_s = kinds["fine_sap"]
+    bytes_s = ctx.timing_bytes(1)
+    sap = None
+    if n_s and ms_s > 0:
+        a = bytes_s / (ms_s * 1e-3) / 1e9
+        sap = {"bound": "hbm", "kernel": f"fine SAP colour sweep ({args.precision} links, FP32 arithmetic, "
+                                          f"4 MR steps), K fields per launch",
+               "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4),
+               "traffic": None, "algorithmic_bytes": bytes_s, "launches": n_s,
+               "avg_launch_ms": round(ms_s / n_s, 4)}
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
 
     fp64_s = None
     fp64_stats = None
+    fp64_note = None
     if args.fp64_compare:
-        if V0 is None:
-            del noise
-            torch.cuda.empty_cache()
+        elapsed = time.time() - T_START
+        # the FP64 form has run ~20x the mixed step on this lattice
+        projected = 20.0 * dt * max(1.0, args.nrhs / 12.0)
+        if elapsed + projected > args.time_budget:
+            fp64_note = (f"skipped: {elapsed:.0f} s elapsed + about {projected:.0f} s projected exceeds the "
+                         f"{args.time_budget:.0f} s budget of this run")
+            log("fp64:", fp64_note)
+        else:
+            if args.learned:
+                del noise
+                torch.cuda.empty_cache()
             V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
-        c64 = make_ctx()
-        # FP64 fine fields are twice the size: 4 test vectors per setup batch
-        p64 = params("fp64", args.fp64_setup_iters, 1, min(args.batch, 4))
-        torch.cuda.synchronize()
-        t1 = time.time()
-        c64.setup(p64, [V0, V1])
-        log(f"fp64: setup issued ({time.time() - t1:.1f} s)")
-        _, fp64_stats = c64.solve(b, tol=1e-10, x=x)
-        torch.cuda.synchronize()
-        fp64_s = time.time() - t1
-        c64.close()
-        log(f"fp64 step {fp64_s:.2f} s, stats {fp64_stats}")
+            U = synth.gauge_field_device(dims, 0.3, 5001)
+            c64 = make_ctx(U)
+            del U
+            torch.cuda.empty_cache()
+            # FP64 fine fields are twice the size: 4 test vectors per setup batch
+            p64 = params("fp64", args.fp64_setup_iters, min(args.fp64_rhs_batch, args.nrhs), min(args.batch, 4))
+            torch.cuda.synchronize()
+            t1 = time.time()
+            c64.setup(p64, [V0, V1])
+            log(f"fp64: setup issued ({time.time() - t1:.1f} s)")
+            _, fp64_stats = c64.solve(b, tol=1e-10, x=x)
+            torch.cuda.synchronize()
+            fp64_s = time.time() - t1
+            c64.close()
+            log(f"fp64 step {fp64_s:.2f} s, stats {fp64_stats}")
 
     cpu = None
+    check = None
     if args.cpu_baseline:
-        log("timing the oracle on the host")
-        cpu = cpu_baseline(args.nrhs, V)
+        log("oracle leg on the host")
+        U_host = synth.gauge_field_device(dims, 0.3, 5001).cpu().numpy()
+        x0 = x[0].cpu().numpy()
+        b0 = b[0].cpu().numpy()
+        cpu, check = oracle_leg(U_host, x0, b0, y0)
+        log(f"oracle: {cpu['value']} GB/s on {cpu['cores']} threads, check {check}")
 
     out = {
         "metric": METRIC,
@@ -248,21 +340,26 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(str(d) for d in reversed(dims))} twisted-mass Wilson-clover, "
                                f"kappa {KAPPA}, c_sw {CSW}, mu {MU}, delta 5, 3 levels (4^4, 2^4 aggregates, "
-                               f"Nv 24/32), {args.nrhs} rhs ({min(args.rhs_batch, args.nrhs)} in lock step), "
+                               f"Nv 24/32), {args.nrhs} rhs ({kb} in lock step), "
                                f"{'learned' if args.learned else 'random'} initial test vectors + "
                                f"{args.setup_iters} setup iteration(s) on batches of {args.batch} test vectors, "
-                               f"preconditioner {args.precision}, outer FGMRES FP64, tol 1e-10",
+                               f"preconditioner {args.precision}, outer FGMRES FP64, tol 1e-10"
+                               + (f", overrides {overrides}" if overrides else ""),
                    "global_batch": args.nrhs, "parallelism": "none"},
         "roofline": {"bound": "hbm", "kernel": "D(mu) FP64 full-lattice apply",
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                      "traffic": traffic_for(src_hash), "algorithmic_bytes_per_launch": bytes_launch,
                      "launches": n_d, "avg_launch_ms": round(avg_ms, 4)},
+        "roofline_sap": sap,
         "cpu_baseline": cpu,
+        "oracle_check": check,
         "mixed_stats": stats,
+        "iters_per_rhs": round(stats["iters"] / max(1, stats["nrhs"]), 2) if stats else None,
         "true_residual_max": resid,
         "fp64_step_s": round(fp64_s, 3) if fp64_s else None,
         "fp64_stats": fp64_stats,
+        "fp64_note": fp64_note,
         "speedup_mixed_vs_fp64": round(fp64_s / dt, 3) if fp64_s else None,
         "kernel_ms": {k: {"launches": v[0], "ms": round(v[1], 2)} for k, v in kinds.items()},
     }

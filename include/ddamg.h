@@ -104,12 +104,16 @@ typedef struct ddamg_params {
 } ddamg_params;
 
 typedef struct ddamg_stats {
-  int iters;             /* outer FGMRES iterations */
-  int converged;         /* 1 if the true relative residual <= tol */
-  double resid;          /* true relative residual |b - D x| / |b| in FP64 */
-  long coarse_iters[4];  /* Krylov iterations per level (index = level) */
+  int iters;             /* outer FGMRES iterations, summed over the right-hand sides */
+  int converged;         /* 1 if the true relative residual <= tol (every right-hand side) */
+  double resid;          /* true relative residual |b - D x| / |b| in FP64, largest over the
+                            right-hand sides */
+  long coarse_iters[4];  /* Krylov iterations per level (index = level), summed over right-hand sides */
   long vcycles;          /* fine-level V-cycles */
   double seconds;        /* wall time of the call */
+  int nrhs;              /* right-hand sides solved */
+  int iters_min;         /* fewest outer iterations of one right-hand side */
+  int iters_max;         /* most outer iterations of one right-hand side */
 } ddamg_stats;
 
 /* Fill p with the defaults documented above (2 levels, 4^4 then 2^4 blocks,
@@ -175,6 +179,13 @@ int ddamg_set_test_vectors(ddamg_ctx* ctx, const ddamg_params* p, const void* co
  * ignored. */
 int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise, int noise_precision,
                         int on_device, const void* coarse_init);
+/* Error-reduction factor of the current preconditioner (Eq. (1)):
+ * rho = (|(I - M D)^n e0| / |e0|)^(1/n), e0 a fine spinor field (host or
+ * device, caller-owned, nonzero), n >= 1 applications, all in FP64 on the
+ * device (M is the setup's cycle in its stored precision).  This is the probe
+ * that decides whether a learned start is kept or the plain setup runs
+ * instead.  BAD_STATE without a setup. */
+int ddamg_error_reduction(ddamg_ctx* ctx, const void* e0, int on_device, int n, double* rho);
 /* Setup update for a changed gauge field (the HMC use of Sec. 3.1: during a
  * trajectory the setup is refreshed by one fine-level and three
  * first-coarse-level iterations instead of being rebuilt).  links: the
@@ -186,9 +197,10 @@ int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise
  * (p->init_sap_iters smoothing sweeps, usually 0; p->setup_iters fine and
  * p->coarse_setup_iters level-1 iterations, 1 and 3 in the paper's use).
  * With both iteration counts 0 the new D_c is the Galerkin operator of the old
- * P on the new field.  On three levels give p->coarse_setup_iters > 0 with
- * p->setup_iters > 0: the level-1 test vectors are coefficients in the fine
- * basis, which a fine iteration changes.  p must keep the levels, precision, nvec and aggregation
+ * P on the new field.  On three levels p->setup_iters > 0 requires
+ * p->coarse_setup_iters > 0 (INVALID_ARG otherwise, the current setup kept):
+ * the level-1 test vectors are coefficients in the fine basis, which a fine
+ * iteration changes.  p must keep the levels, precision, nvec and aggregation
  * blocks of the current setup (INVALID_ARG otherwise).  The old and the new
  * hierarchy are both held while the new one is allocated.  BAD_STATE without a
  * setup; a field with NaN or Inf returns NUMERICAL with the old field and
@@ -199,8 +211,9 @@ int ddamg_update_gauge(ddamg_ctx* ctx, const void* links, int on_device, const d
  * contiguous fields) with FGMRES preconditioned by Eq. (1), stopping at a
  * true relative residual <= tol computed in FP64.  Returns NOT_CONVERGED
  * (x holds the last iterate) when max_iter is hit; BAD_STATE before setup.
- * st (may be NULL) receives the statistics of the last right-hand side,
- * with iteration counts summed over all of them. */
+ * st (may be NULL) receives the statistics of the call: iteration counts
+ * summed over the right-hand sides, and the fewest and most outer iterations
+ * of one right-hand side. */
 int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, ddamg_stats* st, int on_device);
 
 /* ---- single operators, for parity checks (host or device FP64 arrays) ---- */
@@ -318,6 +331,14 @@ int ddamg_bench_coarse(ddamg_ctx* ctx, int level, int nrhs, int napply, int whic
  * launch count and total milliseconds so far (synchronises the stream). */
 int ddamg_timing(ddamg_ctx* ctx, int enable);
 int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms);
+/* Algorithmic bytes of the launches timed so far of a kind, each datum moved
+ * once per launch: kind 0, 1536 bytes per site (spinor in and out, links,
+ * clover in FP64); kind 1, per site of the swept colour the links (36
+ * entries of the storage format), the clover term and the odd-site inverse
+ * factors (108 reals on average) once, and per field b, x in, x out and the
+ * other colour's x (48 complex); other kinds report 0.  bytes / (ms 1e-3) is
+ * the achieved rate. */
+int ddamg_timing_bytes(ddamg_ctx* ctx, int kind, double* bytes);
 
 /* ---- learned setup (not a method of the paper: it replaces the random start
  * of the adaptive setup; the plain setup stays the fallback) ----

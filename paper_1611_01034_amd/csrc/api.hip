@@ -304,6 +304,11 @@ int ddamg_update_gauge(ddamg_ctx* ctx, const void* links, int on_device, const d
     check_params(p);
     if (p->levels != c.p.levels || p->precision != c.p.precision)
       throw Error(INVALID_ARG, "levels and precision must equal those of the current setup");
+    // on three levels the kept level-1 test vectors are coefficients in the
+    // fine basis P_0: a fine iteration changes P_0, and only level-1
+    // iterations adapt those vectors to it again
+    if (p->levels == 3 && p->setup_iters > 0 && p->coarse_setup_iters == 0)
+      throw Error(INVALID_ARG, "a three-level update with fine iterations needs coarse_setup_iters > 0");
     for (int l = 0; l < p->levels - 1; ++l) {
       if (p->nvec[l] != c.p.nvec[l]) throw Error(INVALID_ARG, "nvec must equal that of the current setup");
       for (int d = 0; d < 4; ++d)
@@ -427,22 +432,27 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
     };
     for (int l = 0; l < 4; ++l) c.mg->coarse_iters[l] = 0;
     c.mg->vcycles = 0;
-    int total_it = 0;
+    int total_it = 0, it_min = 1 << 30, it_max = 0;
+    double worst_all = 0;
     bool all_conv = true;
     KrylovResult kr;
     const int Kb = std::min(nrhs, c.p.rhs_batch);
     if (Kb > 1) {
       // right-hand sides in groups of Kb through one lock-step outer FGMRES
       // (the one-column workspace is not allocated on this path)
+      // reduced-precision hierarchies: the preconditioned directions (the
+      // cycle's FP32 output) are kept in FP32, halving that half of the basis
+      const bool zf = c.p.precision != DDAMG_FP64;
       KrylovWSm<double>& ws = c.outer_m;
-      ws.init(c.p.restart, Kb, N, N, true);
+      ws.init(c.p.restart, Kb, N, N, true, zf, true);
       DevBuf bK, xK;
-      bK.alloc(sizeof(cx<double>) * N * Kb);
-      xK.alloc(sizeof(cx<double>) * N * Kb);
+      bK.alloc(sizeof(cx<double>) * N * Kb, true);
+      xK.alloc(sizeof(cx<double>) * N * Kb, true);
       OpM<double> AK = [&c, N](const cx<double>* in, cx<double>* out, int K) {
         for (int k = 0; k < K; ++k) c.dirac64(in + k * N, out + k * N, c.mu);
       };
       OpM<double> MK = [&c](const cx<double>* in, cx<double>* out, int K) { c.mg->precond_multi(in, out, K); };
+      OpMf MKf = [&c](const cx<double>* in, cx<float>* out, int K) { c.mg->precond_multi_f32(in, out, K); };
       double worst = 0;
       for (int r0 = 0; r0 < nrhs; r0 += Kb) {
         const int k = std::min(Kb, nrhs - r0);
@@ -451,17 +461,19 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
           c.upload_fine(bs, on_device, bK.as<cx<double>>() + (long)q * N);
           check_finite(c, (const double*)(bK.as<cx<double>>() + (long)q * N), 2 * N);
         }
-        KrylovResultM km = fgmres_multi<double>(c, ws, k, N, AK, &MK, bK.as<cx<double>>(), xK.as<cx<double>>(), tol,
-                                                c.p.max_iter, false, true);
+        KrylovResultM km = fgmres_multi<double>(c, ws, k, N, AK, zf ? nullptr : &MK, bK.as<cx<double>>(),
+                                                xK.as<cx<double>>(), tol, c.p.max_iter, false, true, zf ? &MKf : nullptr);
         for (int q = 0; q < k; ++q) {
           char* xs = (char*)x + sizeof(cx<double>) * (size_t)N * (r0 + q);
           c.download_fine(xK.as<cx<double>>() + (long)q * N, xs, on_device);
           total_it += km.iters[q];
+          it_min = std::min(it_min, km.iters[q]);
+          it_max = std::max(it_max, km.iters[q]);
           all_conv = all_conv && km.converged[q];
           worst = std::max(worst, km.resid[q]);
         }
       }
-      kr.resid = worst;
+      worst_all = std::max(worst_all, worst);
     }
     if (Kb <= 1) c.outer.init(c.p.restart, N, N, true);
     for (int r = Kb > 1 ? nrhs : 0; r < nrhs; ++r) {
@@ -472,6 +484,9 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
       kr = fgmres<double>(c, c.outer, N, A, &M, c.f64a.as<cx<double>>(), c.f64b.as<cx<double>>(), tol, c.p.max_iter,
                           false, true);
       total_it += kr.iters;
+      it_min = std::min(it_min, kr.iters);
+      it_max = std::max(it_max, kr.iters);
+      worst_all = std::max(worst_all, kr.resid);
       all_conv = all_conv && kr.converged;
       c.download_fine(c.f64b.as<cx<double>>(), xs, on_device);
     }
@@ -487,10 +502,13 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
     if (stats) {
       stats->iters = total_it;
       stats->converged = all_conv ? 1 : 0;
-      stats->resid = kr.resid;
+      stats->resid = worst_all;
       for (int l = 0; l < 4; ++l) stats->coarse_iters[l] = c.mg->coarse_iters[l];
       stats->vcycles = c.mg->vcycles;
       stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      stats->nrhs = nrhs;
+      stats->iters_min = it_min;
+      stats->iters_max = it_max;
     }
     if (!all_conv) {
       c.err = "FGMRES reached max_iter before the tolerance";
@@ -569,6 +587,9 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
       for (int l = 0; l < 4; ++l) stats->coarse_iters[l] = c.mg->coarse_iters[l];
       stats->vcycles = c.mg->vcycles;
       stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      stats->nrhs = 1;
+      stats->iters_min = kr.iters;
+      stats->iters_max = kr.iters;
     }
     if (!kr.converged) {
       c.err = "FGMRES reached max_iter before the tolerance";
@@ -887,6 +908,51 @@ int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms) {
   });
 }
 
+int ddamg_error_reduction(ddamg_ctx* ctx, const void* e0, int on_device, int n, double* rho) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_setup(c);
+    if (!e0 || !rho || n < 1) throw Error(INVALID_ARG, "bad error-reduction arguments");
+    const long N = c.fine_len();
+    DevBuf e, t, z, part;
+    e.alloc(sizeof(cx<double>) * N);
+    t.alloc(sizeof(cx<double>) * N);
+    z.alloc(sizeof(cx<double>) * N);
+    const int nwg = (int)std::min<long>(1024, (N + 255) / 256);
+    part.alloc(sizeof(cx<double>) * (nwg + 1));
+    cx<double>* ep = e.as<cx<double>>();
+    cx<double>* nrm = part.as<cx<double>>() + nwg;
+    auto norm = [&]() {
+      launch_multidot<double>(ep, 0, 1, ep, N, part.as<cx<double>>(), nwg, c.st);
+      launch_reduce(part.as<cx<double>>(), 1, nwg, nrm, 2, c.st);
+      cx<double> h;
+      HIP_CHECK(hipMemcpyAsync(&h, nrm, sizeof(h), hipMemcpyDeviceToHost, c.st));
+      c.sync();
+      return h.re;
+    };
+    c.upload_fine(e0, on_device, ep);
+    check_finite(c, (const double*)ep, 2 * N);
+    const double n0 = norm();
+    if (!(n0 > 0)) throw Error(INVALID_ARG, "the probe vector is zero");
+    for (int i = 0; i < n; ++i) {  // e <- (I - M D) e
+      c.dirac64(ep, t.as<cx<double>>(), c.mu);
+      c.mg->precond(t.as<cx<double>>(), z.as<cx<double>>());
+      launch_sub<double>(N, ep, z.as<cx<double>>(), ep, c.st);
+    }
+    *rho = std::pow(norm() / n0, 1.0 / n);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_timing_bytes(ddamg_ctx* ctx, int kind, double* bytes) {
+  if (!ctx || kind < 0 || kind >= KernelTimer::NKIND || !bytes) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    *bytes = ctx->c.timer.bytes[kind];
+    return DDAMG_OK;
+  });
+}
+
 }  // extern "C"
 
 // ===========================================================================
@@ -1027,8 +1093,8 @@ int ddamg_setup_learned(ddamg_ctx* ctx, const ddamg_params* p, const void* noise
     c.ensure_32();
     const long fl = c.fine_len(), f = (long)c.net.C * fl;
     DevBuf A, B;
-    A.alloc(sizeof(cx<float>) * f);
-    B.alloc(sizeof(cx<float>) * f);
+    A.alloc(sizeof(cx<float>) * f, true);
+    B.alloc(sizeof(cx<float>) * f, true);
     c.lex.ensure(sizeof(cx<double>) * fl);
     for (int ch = 0; ch < c.net.C; ++ch) {
       cx<float>* dst = A.as<cx<float>>() + (long)ch * fl;

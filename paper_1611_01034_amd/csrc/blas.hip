@@ -338,10 +338,10 @@ void launch_reduce_b(const cx<double>* partial, long pcs, int k, int nwg, cx<dou
 }
 
 // w_r += sign * sum_{i<k_r} coef_r[i] V_r[i]   (k_r = kcol ? kcol[r] : k)
-template <class R>
+template <class R, class RW = R>
 __global__ void __launch_bounds__(256) k_multi_axpy_b(const cx<R>* __restrict__ V, long ldv, long csV, int k,
                                                       const int* kcol, const cx<double>* __restrict__ coef, long ccs,
-                                                      double sign, cx<R>* __restrict__ w, long csw, long N,
+                                                      double sign, cx<RW>* __restrict__ w, long csw, long N,
                                                       const int* act) {
   if (col_off(act)) return;
   const long r = blockIdx.y;
@@ -356,14 +356,22 @@ __global__ void __launch_bounds__(256) k_multi_axpy_b(const cx<R>* __restrict__ 
     cx<R> v = V[(long)i * ldv + e];
     cmac(acc, coef[i], mk<double>(v.re, v.im));
   }
-  cx<R> x = w[e];
-  w[e] = mk<R>((R)(x.re + sign * acc.re), (R)(x.im + sign * acc.im));
+  cx<RW> x = w[e];
+  w[e] = mk<RW>((RW)(x.re + sign * acc.re), (RW)(x.im + sign * acc.im));
 }
 template <class R>
 void launch_multi_axpy_b(const cx<R>* V, long ldv, long csV, int k, const int* kcol, const cx<double>* coef, long ccs,
                          double sign, cx<R>* w, long csw, long N, int K, const int* act, hipStream_t st) {
   hipLaunchKernelGGL(k_multi_axpy_b<R>, dim3((N + 255) / 256, K), dim3(256), 0, st, V, ldv, csV, k, kcol, coef, ccs,
                      sign, w, csw, N, act);
+}
+// w (FP64) += sign * sum_i coef_i V_i with an FP32 basis V (the outer solve's
+// preconditioned directions in the mixed form)
+void launch_multi_axpy_b_mixed(const cx<float>* V, long ldv, long csV, int k, const int* kcol, const cx<double>* coef,
+                               long ccs, double sign, cx<double>* w, long csw, long N, int K, const int* act,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((k_multi_axpy_b<float, double>), dim3((N + 255) / 256, K), dim3(256), 0, st, V, ldv, csV, k,
+                     kcol, coef, ccs, sign, w, csw, N, act);
 }
 
 // out_r = in_r / s_r (real part);  an inactive column is zeroed when zero_off

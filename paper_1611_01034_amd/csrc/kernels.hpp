@@ -205,6 +205,9 @@ void launch_reduce_b(const cx<double>* partial, long pcs, int k, int nwg, cx<dou
 template <class R>
 void launch_multi_axpy_b(const cx<R>* V, long ldv, long csV, int k, const int* kcol, const cx<double>* coef, long ccs,
                          double sign, cx<R>* w, long csw, long N, int K, const int* act, hipStream_t st);
+void launch_multi_axpy_b_mixed(const cx<float>* V, long ldv, long csV, int k, const int* kcol, const cx<double>* coef,
+                               long ccs, double sign, cx<double>* w, long csw, long N, int K, const int* act,
+                               hipStream_t st);
 template <class R>
 void launch_scale_by_inv_b(const cx<R>* in, long csi, const cx<double>* s, long scs, cx<R>* out, long cso, long N,
                            int K, const int* act, int zero_off, hipStream_t st);

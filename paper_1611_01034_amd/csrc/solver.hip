@@ -78,13 +78,14 @@ constexpr size_t kMinSlab = size_t(64) << 20;  // small buffers share 64 MiB sla
 constexpr size_t kSlabRound = size_t(2) << 20;
 }  // namespace
 
-void* MemPool::get(size_t b) {
+void* MemPool::get(size_t b, bool transient) {
   b = (b + kGranule - 1) / kGranule * kGranule;
-  // best fit over the free ranges of every slab
+  // best fit over the free ranges of every slab of the same kind
   Slab* best = nullptr;
   size_t best_off = 0, best_len = ~size_t(0);
   for (auto& s : slabs)
-    for (auto& fr : s.free)
+    if (s.transient == transient)
+      for (auto& fr : s.free)
       if (fr.second >= b && fr.second < best_len) {
         best = &s;
         best_off = fr.first;
@@ -119,6 +120,7 @@ void* MemPool::get(size_t b) {
   s.base = (char*)p;
   s.bytes = sb;
   s.used = b;
+  s.transient = transient;
   if (sb > b) s.free[b] = sb - b;
   slabs.push_back(std::move(s));
   return p;
@@ -191,8 +193,9 @@ void KernelTimer::begin(int kind, hipEvent_t* a) {
   *a = get();
   HIP_CHECK(hipEventRecord(*a, st));
 }
-void KernelTimer::end(int kind, hipEvent_t a) {
+void KernelTimer::end(int kind, hipEvent_t a, double nbytes) {
   if (!on || !a) return;
+  bytes[kind] += nbytes;
   hipEvent_t b = get();
   HIP_CHECK(hipEventRecord(b, st));
   recs.push_back({kind, a, b});
@@ -215,6 +218,7 @@ void KernelTimer::reset() {
   for (int i = 0; i < NKIND; ++i) {
     count[i] = 0;
     ms[i] = 0;
+    bytes[i] = 0;
   }
 }
 KernelTimer::~KernelTimer() {
@@ -229,9 +233,22 @@ struct TimeScope {
   KernelTimer& t;
   int kind;
   hipEvent_t a;
-  TimeScope(KernelTimer& t_, int k) : t(t_), kind(k) { t.begin(k, &a); }
-  ~TimeScope() { t.end(kind, a); }
+  double b;
+  TimeScope(KernelTimer& t_, int k, double bytes = 0) : t(t_), kind(k), b(bytes) { t.begin(k, &a); }
+  ~TimeScope() { t.end(kind, a, b); }
 };
+
+// Algorithmic bytes of one fine SAP colour sweep of K fields (each datum
+// moved once): per site of the swept colour the links (36 entries of the
+// storage format), the clover term (72 reals) and, on odd sites, the inverse
+// factors (72 reals, 36 per site on average) once for all fields; per field
+// b, x read and written, and x of the other colour read once for the residual.
+template <class R, class S>
+static double sap_sweep_bytes(const Geom& g, int K) {
+  const double shared = 36.0 * sizeof(typename store_traits<S>::elem) + 108.0 * sizeof(R);
+  const double field = 4.0 * 12 * sizeof(cx<R>);
+  return 0.5 * (double)g.V * (shared + K * field);
+}
 
 // ---------------------------------------------------------------------------
 template <class R>
@@ -401,14 +418,15 @@ static int cgs_nwg(long N) {
 }
 
 template <class R>
-void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex) {
+void KrylovWSm<R>::init(int m_, int K_, long ld_, long N, bool flex, bool z_fp32, bool transient) {
   m = m_;
   K = K_;
   ld = ld_;
   flexible = flex;
-  V.ensure(sizeof(cx<R>) * (size_t)(m + 1) * K * ld);
-  if (flex) Z.ensure(sizeof(cx<R>) * (size_t)m * K * ld);
-  r.ensure(sizeof(cx<R>) * (size_t)K * ld);
+  zf32 = z_fp32;
+  V.ensure(sizeof(cx<R>) * (size_t)(m + 1) * K * ld, transient);
+  if (flex) Z.ensure((z_fp32 ? sizeof(cx<float>) : sizeof(cx<R>)) * (size_t)m * K * ld, transient);
+  r.ensure(sizeof(cx<R>) * (size_t)K * ld, transient);
   H.ensure(sizeof(cx<double>) * (size_t)(m + 1) * m * K);
   cs.ensure(sizeof(double) * m * K);
   sn.ensure(sizeof(cx<double>) * m * K);
@@ -447,8 +465,10 @@ template struct KrylovWSm<float>;
 
 template <class R>
 KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>& A, const OpM<R>* M, const cx<R>* b,
-                           cx<R>* x, double tol, int max_iter, bool fixed, bool x_is_zero) {
+                           cx<R>* x, double tol, int max_iter, bool fixed, bool x_is_zero, const OpMf* Mf) {
   if (K < 1 || K > ws.K || K > 16) throw Error(INVALID_ARG, "lock-step solve: bad column count");
+  if (Mf && (!std::is_same<R, double>::value || !ws.zf32 || M))
+    throw Error(INVALID_ARG, "FP32 directions need an FP64 solve with an FP32 workspace");
   hipStream_t st = c.st;
   const int m = ws.m, ldh = m + 1;
   const long ld = ws.ld, hcs = (long)ldh * m;
@@ -457,6 +477,7 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
   const long pcs = (long)std::max(ws.nwg, ws.nwgf) * ldh;
   cx<R>* V = ws.V.template as<cx<R>>();
   cx<R>* Z = M ? ws.Z.template as<cx<R>>() : V;
+  cx<float>* Zf = Mf ? ws.Z.template as<cx<float>>() : nullptr;
   cx<R>* r = ws.r.template as<cx<R>>();
   cx<double>* H = ws.H.template as<cx<double>>();
   cx<double>* scal = ws.scal.template as<cx<double>>();
@@ -523,7 +544,7 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
     // s+2 are already queued (the device never waits for the host); a column
     // that met its tolerance at step s then drops the later steps it ran, which
     // changed only its Hessenberg columns after s and g entries after s+1.
-    const bool lookahead = !fixed && M == nullptr;
+    const bool lookahead = !fixed && M == nullptr && Mf == nullptr;
     constexpr int LAG = 2, NSLOT = LAG + 1;
     int tested = 0;                // steps 0..tested-1 of this cycle are tested
     int last = -1;                 // last step queued in this cycle
@@ -535,6 +556,14 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
       if (M) {
         z = Z + (long)j * K * ld;
         (*M)(Vj, z, K);
+      } else if (Mf) {
+        if constexpr (std::is_same<R, double>::value) {
+          // r is free until the restart: it holds the widened direction
+          cx<float>* zf = Zf + (long)j * K * ld;
+          (*Mf)(Vj, zf, K);
+          launch_copy_cvt_b<float, R>(zf, ld, r, ld, N, K, st);
+          z = r;
+        }
       }
       A(z, Vn, K);
       cx<double>* hcol = H + (long)j * ldh;
@@ -617,7 +646,14 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
     for (int s = tested; s <= last; ++s) HIP_CHECK(hipEventSynchronize(ws.ready[s % NSLOT]));
     HIP_CHECK(hipMemcpyAsync(jd, ws.h_jd, sizeof(int) * K, hipMemcpyHostToDevice, st));
     launch_trisolve_b(H, ldh, m, g, y, jd, K, st);
-    launch_multi_axpy_b<R>(Z, (long)K * ld, ld, m, jd, y, ldh, 1.0, x, ld, N, K, nullptr, st);
+    if constexpr (std::is_same<R, double>::value) {
+      if (Mf)
+        launch_multi_axpy_b_mixed(Zf, (long)K * ld, ld, m, jd, y, ldh, 1.0, x, ld, N, K, nullptr, st);
+      else
+        launch_multi_axpy_b<R>(Z, (long)K * ld, ld, m, jd, y, ldh, 1.0, x, ld, N, K, nullptr, st);
+    } else {
+      launch_multi_axpy_b<R>(Z, (long)K * ld, ld, m, jd, y, ldh, 1.0, x, ld, N, K, nullptr, st);
+    }
     A(x, r, K);
     launch_sub_b<R>(N, b, ld, r, ld, r, ld, K, st);
     norms(r, 1, nullptr);
@@ -634,9 +670,9 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
 }
 template KrylovResultM fgmres_multi<double>(Ctx&, KrylovWSm<double>&, int, long, const OpM<double>&,
                                             const OpM<double>*, const cx<double>*, cx<double>*, double, int, bool,
-                                            bool);
+                                            bool, const OpMf*);
 template KrylovResultM fgmres_multi<float>(Ctx&, KrylovWSm<float>&, int, long, const OpM<float>&, const OpM<float>*,
-                                           const cx<float>*, cx<float>*, double, int, bool, bool);
+                                           const cx<float>*, cx<float>*, double, int, bool, bool, const OpMf*);
 
 template KrylovResult fgmres<double>(Ctx&, KrylovWS<double>&, long,
                                      const std::function<void(const cx<double>*, cx<double>*)>&,
@@ -671,7 +707,8 @@ void Ctx::rebuild_odd_inverse() {
   if (have_32) launch_cvt_real((long)g.V * 36, M64.as<double>(), M32.as<float>(), st);
 }
 void Ctx::dirac64(const cx<double>* in, cx<double>* out, double tw) {
-  TimeScope ts(timer, 0);
+  // spinor in and out, links and clover once: 1536 bytes per site
+  TimeScope ts(timer, 0, 1536.0 * (double)g.V);
   launch_dirac<double, double>(g, U64.p, H64.as<double>(), tw, in, out, st);
 }
 void Ctx::upload_fine(const void* src, int on_device, cx<double>* dst64) {
@@ -895,7 +932,9 @@ struct MG : MGBase {
     fx.alloc(sizeof(cx<R>) * fl);
     fb.alloc(sizeof(cx<R>) * fl);
     fr.alloc(sizeof(cx<R>) * fl);
-    Vraw[0].alloc(sizeof(cx<R>) * fl * Nv[0]);
+    // the raw test vectors live through the setup only, unless kept for an update
+    const bool vt = !p.keep_test_vectors;
+    Vraw[0].alloc(sizeof(cx<R>) * fl * Nv[0], vt);
     Q[0].alloc(sizeof(cx<R>) * fl * Nv[0]);
     size_t maxnn = 0;
     for (int l = 1; l < L; ++l) {
@@ -962,7 +1001,7 @@ struct MG : MGBase {
   void fine_sap(const cx<R>* b, cx<R>* x, int iters, int nmr) {
     for (int it = 0; it < iters; ++it)
       for (int col = 0; col < 2; ++col) {
-        TimeScope ts(c.timer, 1);
+        TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, 1));
         launch_sap<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, c.st);
       }
   }
@@ -970,7 +1009,7 @@ struct MG : MGBase {
   void fine_sap_m(const cx<R>* b, cx<R>* x, int K, int iters, int nmr) {
     for (int it = 0; it < iters; ++it)
       for (int col = 0; col < 2; ++col) {
-        TimeScope ts(c.timer, 1);
+        TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, K));
         launch_sap_multi<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, K, c.fine_len(), c.st);
       }
   }
@@ -1252,11 +1291,22 @@ struct MG : MGBase {
     if constexpr (std::is_same<R, double>::value) {
       vcycle_m(0, v, z, K);
     } else {
-      fbm.ensure(sizeof(cx<R>) * n * K);
-      fxm.ensure(sizeof(cx<R>) * n * K);
+      fbm.ensure(sizeof(cx<R>) * n * K, true);
+      fxm.ensure(sizeof(cx<R>) * n * K, true);
       launch_copy_cvt_b<double, R>(v, n, fbm.template as<cx<R>>(), n, n, K, c.st);
       vcycle_m(0, fbm.template as<cx<R>>(), fxm.template as<cx<R>>(), K);
       launch_copy_cvt_b<R, double>(fxm.template as<cx<R>>(), n, z, n, n, K, c.st);
+    }
+  }
+  void precond_multi_f32(const cx<double>* v, cx<float>* z, int K) override {
+    if constexpr (std::is_same<R, double>::value) {
+      throw Error(INVALID_ARG, "FP32 directions need a reduced-precision hierarchy");
+    } else {
+      ensure_multi(K);
+      const long n = c.fine_len();
+      fbm.ensure(sizeof(cx<R>) * n * K, true);
+      launch_copy_cvt_b<double, R>(v, n, fbm.template as<cx<R>>(), n, n, K, c.st);
+      vcycle_m(0, fbm.template as<cx<R>>(), z, K);
     }
   }
   void precond(const cx<double>* v, cx<double>* z) override {
@@ -1384,7 +1434,7 @@ struct MG : MGBase {
       ensure_multi(K);
       cx<R>* out;
       if (l == 0) {
-        fxm.ensure(sizeof(cx<R>) * len * K);
+        fxm.ensure(sizeof(cx<R>) * len * K, true);
         out = fxm.template as<cx<R>>();
       } else {
         out = ecm[l].template as<cx<R>>();
@@ -1462,7 +1512,7 @@ struct MG : MGBase {
         ensure_multi(K);
         cx<R>* zb;
         if (l == 0) {
-          fxm.ensure(sizeof(cx<R>) * len * K);
+          fxm.ensure(sizeof(cx<R>) * len * K, true);
           zb = fxm.template as<cx<R>>();
         } else {
           zb = ecm[l].template as<cx<R>>();

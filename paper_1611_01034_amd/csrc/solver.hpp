@@ -26,16 +26,23 @@ namespace ddamg {
 // stream once, which covers synchronous host copies into a reused range
 // (hipFree synchronised the device for the same reason).  When hipMalloc
 // fails, slabs with nothing in use are freed and the allocation retried.
+// Buffers that live only through one phase of a call (the network's
+// activations, the setup's raw test vectors and work fields, the outer
+// solve's Krylov basis) are "transient" and take ranges of transient slabs
+// only; every other buffer takes ranges of persistent slabs.  The phases then
+// reuse one another's ranges in turn, and a long-lived buffer never pins a
+// slab that a later phase needs whole.
 struct MemPool {
   struct Slab {
     char* base = nullptr;
     size_t bytes = 0, used = 0;
+    bool transient = false;
     std::map<size_t, size_t> free;  // offset -> length of the free ranges
   };
   std::vector<Slab> slabs;
   hipStream_t st = nullptr;         // the owning context's stream
   bool dirty = false;               // a range was released since the last synchronisation
-  void* get(size_t b);
+  void* get(size_t b, bool transient = false);
   void put(void* p, size_t b);
   void trim();                      // hipFree every slab with nothing in use
   size_t reserved() const;
@@ -57,12 +64,12 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  void alloc(size_t b) {
+  void alloc(size_t b, bool transient = false) {
     release();
     if (!b) return;
     MemPool* mp = current_pool();
     if (mp) {
-      p = mp->get(b);
+      p = mp->get(b, transient);
       pool = mp;
     } else {
       hipError_t e = hipMalloc(&p, b);
@@ -75,8 +82,8 @@ struct DevBuf {
     }
     bytes = b;
   }
-  void ensure(size_t b) {
-    if (bytes < b) alloc(b);
+  void ensure(size_t b, bool transient = false) {
+    if (bytes < b) alloc(b, transient);
   }
   void release() {
     if (p) {
@@ -109,9 +116,10 @@ struct KernelTimer {
   static constexpr int NKIND = 6;
   long count[NKIND] = {0, 0, 0, 0, 0, 0};
   double ms[NKIND] = {0, 0, 0, 0, 0, 0};
+  double bytes[NKIND] = {0, 0, 0, 0, 0, 0};  // algorithmic bytes of the timed launches (kinds 0, 1)
   hipEvent_t get();
   void begin(int kind, hipEvent_t* a);
-  void end(int kind, hipEvent_t a);
+  void end(int kind, hipEvent_t a, double b = 0);
   void flush();
   void reset();
   ~KernelTimer();
@@ -151,7 +159,9 @@ struct KrylovWSm {
   int act_slot = 0;
   int* h_jd = nullptr;         // pinned: K counts
   int nwg = 0;
-  void init(int m_, int K_, long ld_, long N, bool flex);
+  bool zf32 = false;            // Z holds FP32 directions (mixed outer solve)
+  // transient: the basis (V, Z, r) comes from the pool's transient slabs
+  void init(int m_, int K_, long ld_, long N, bool flex, bool z_fp32 = false, bool transient = false);
   ~KrylovWSm();
 };
 
@@ -166,9 +176,16 @@ struct KrylovResultM {
 template <class R>
 using OpM = std::function<void(const cx<R>*, cx<R>*, int)>;
 
+// preconditioner that writes FP32 directions (the mixed form of the outer solve)
+using OpMf = std::function<void(const cx<double>*, cx<float>*, int)>;
+
+// Flexible GMRES(m) on K columns in lock step.  With Mf (R = double only) the
+// preconditioned directions are stored in FP32 (ws initialised with z_fp32):
+// each is widened to FP64 before the operator, and the iterate is updated in
+// FP64; the basis V, every inner product and the residual stay in FP64.
 template <class R>
 KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>& A, const OpM<R>* M, const cx<R>* b,
-                           cx<R>* x, double tol, int max_iter, bool fixed, bool x_is_zero);
+                           cx<R>* x, double tol, int max_iter, bool fixed, bool x_is_zero, const OpMf* Mf = nullptr);
 
 using OpR64 = std::function<void(const cx<double>*, cx<double>*)>;
 using OpR32 = std::function<void(const cx<float>*, cx<float>*)>;
@@ -213,6 +230,8 @@ struct MGBase {
   virtual void precond(const cx<double>* v, cx<double>* z) = 0;  // fine block layout FP64
   // the same on K fine FP64 fields (stride = fine length), in lock step
   virtual void precond_multi(const cx<double>* v, cx<double>* z, int K) = 0;
+  // the same with FP32 output (reduced-precision hierarchies only)
+  virtual void precond_multi_f32(const cx<double>* v, cx<float>* z, int K) = 0;
   virtual void set_mu(double mu) = 0;
   virtual int nlev() const = 0;
   virtual const CoarseGeo& geo(int l) const = 0;  // l >= 1

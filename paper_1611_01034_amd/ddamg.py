@@ -70,11 +70,15 @@ class Stats(ctypes.Structure):
         ("coarse_iters", ctypes.c_long * 4),
         ("vcycles", ctypes.c_long),
         ("seconds", ctypes.c_double),
+        ("nrhs", ctypes.c_int),
+        ("iters_min", ctypes.c_int),
+        ("iters_max", ctypes.c_int),
     ]
 
     def as_dict(self):
         return dict(iters=self.iters, converged=bool(self.converged), resid=self.resid,
-                    coarse_iters=list(self.coarse_iters), vcycles=self.vcycles, seconds=self.seconds)
+                    coarse_iters=list(self.coarse_iters), vcycles=self.vcycles, seconds=self.seconds,
+                    nrhs=self.nrhs, iters_min=self.iters_min, iters_max=self.iters_max)
 
 
 _vp = ctypes.c_void_p
@@ -117,6 +121,8 @@ _SIGS = {
     "ddamg_bench_dirac": (_i, [_vp, _i, _i]),
     "ddamg_timing": (_i, [_vp, _i]),
     "ddamg_timing_query": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
+    "ddamg_timing_bytes": (_i, [_vp, _i, ctypes.POINTER(_d)]),
+    "ddamg_error_reduction": (_i, [_vp, _vp, _i, _i, ctypes.POINTER(_d)]),
     "ddamg_net_create": (_i, [_vp, _i, _i]),
     "ddamg_net_num_params": (ctypes.c_long, [_vp]),
     "ddamg_net_set_params": (_i, [_vp, ctypes.POINTER(_d), ctypes.c_long]),
@@ -541,3 +547,16 @@ class DDAMG:
         ms = ctypes.c_double()
         self._check(_lib.ddamg_timing_query(self._h, int(kind), ctypes.byref(c), ctypes.byref(ms)))
         return c.value, ms.value
+
+    def error_reduction(self, e0, n=3):
+        """rho = (|(I - M D)^n e0| / |e0|)^(1/n) of the current preconditioner."""
+        e0 = _c128(e0)
+        pe, dev = _ptr(e0)
+        r = ctypes.c_double()
+        self._check(_lib.ddamg_error_reduction(self._h, pe, dev, int(n), ctypes.byref(r)))
+        return r.value
+
+    def timing_bytes(self, kind):
+        b = ctypes.c_double()
+        self._check(_lib.ddamg_timing_bytes(self._h, int(kind), ctypes.byref(b)))
+        return b.value

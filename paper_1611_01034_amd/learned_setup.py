@@ -11,9 +11,10 @@ calls and moves fields.
 
 Judged by multigrid outcomes: the V-cycle error-reduction factor
   rho = (|(I - M D)^n e| / |e|)^(1/n)
-and the FGMRES iteration count to a 1e-10 true residual.  Fallback: when the
-probe rho of the learned start exceeds `margin` times the reference rho of the
-plain setup, the plain setup is run instead (decide_fallback).
+and the FGMRES iteration count to a 1e-10 true residual.  Fallback
+(setup_with_fallback): when the learned start fails or its probe rho
+(ddamg_error_reduction, on the device) exceeds `margin` times a reference
+rho, the plain setup is run instead (decide_fallback).
 """
 from __future__ import annotations
 
@@ -35,6 +36,30 @@ def decide_fallback(rho_probe: float, rho_ref: float, margin: float = 1.25) -> b
     if not np.isfinite(rho_probe):
         return True
     return rho_probe > margin * rho_ref
+
+
+def setup_with_fallback(ctx: ddamg.DDAMG, params, noise, coarse_init, plain_vectors, probe, rho_ref=0.9,
+                        margin=1.0, n_probe=2, plain_params=None):
+    """The learned setup with the plain adaptive setup as its fallback.
+
+    Runs ddamg_setup_learned, then probes the resulting cycle's error
+    reduction rho on `probe` (n_probe applications of I - M D on the device).
+    When the learned start fails (a rank-deficient aggregate: NUMERICAL) or
+    decide_fallback(rho, rho_ref, margin) holds, the plain setup runs instead
+    on plain_vectors() (a callable, so that its random vectors are only made
+    when needed) with plain_params (default: params).  Returns
+    {"fallback": bool, "rho_learned": float, "rho": float}."""
+    try:
+        ctx.setup_learned(params, noise, coarse_init)
+        rho_l = ctx.error_reduction(probe, n_probe)
+    except ddamg.DDAMGError as e:
+        if e.status != ddamg.NUMERICAL:
+            raise
+        rho_l = float("nan")
+    if not decide_fallback(rho_l, rho_ref, margin):
+        return {"fallback": False, "rho_learned": rho_l, "rho": rho_l}
+    ctx.setup(plain_params if plain_params is not None else params, plain_vectors())
+    return {"fallback": True, "rho_learned": rho_l, "rho": ctx.error_reduction(probe, n_probe)}
 
 
 def init_torch_device():

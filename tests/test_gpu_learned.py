@@ -64,3 +64,37 @@ def test_setup_learned_equals_setup_on_network_output(ls):
         Q.append(ctx.get_interpolation(0))
     assert np.linalg.norm(Q[1] - Q[0]) <= 1e-6 * np.linalg.norm(Q[0])
     assert np.array_equal(Q[2], Q[1])
+
+
+def test_fallback_to_plain_setup(ls):
+    # a network that maps everything to zero cannot start the setup (every
+    # aggregate is rank deficient): the plain setup runs instead and the solve
+    # converges; the trained network on a near-critical field keeps its start
+    from oracle import dirac
+    from paper_1611_01034_amd import ddamg, synth
+    params, C, L, _ = ls.load_weights(ls.WEIGHTS)
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.48, 4210)
+    noise = synth.spinor(dims, 4211, nvec=C)
+    probe = synth.spinor(dims, 4212)
+    plain = lambda: [synth.spinor(dims, 4213, nvec=C)]
+    p = ddamg.default_params(levels=2, block=[block], nvec=[C], setup_iters=1, precision="fp32", coarse_mu_factor=5.0)
+    b = synth.spinor(dims, 4214)
+    op = dirac.WilsonClover(U, ls.KAPPA, ls.CSW, ls.MU)
+    with ddamg.DDAMG(dims, block, ls.KAPPA, ls.CSW, ls.MU) as ctx:
+        ctx.set_gauge(U)
+        ctx.net_create(L, C)
+        ctx.net_set_params(np.zeros_like(params))
+        info = ls.setup_with_fallback(ctx, p, noise, None, plain, probe)
+        assert info["fallback"] and not np.isfinite(info["rho_learned"]) and info["rho"] < 0.9
+        x, st = ctx.solve(b, tol=1e-10)
+        assert np.linalg.norm(b - op.apply(x)) <= 1e-10 * np.linalg.norm(b)
+        # a finite but useless start: the probe rejects it against a tight reference
+        ctx.net_set_params(params)
+        info = ls.setup_with_fallback(ctx, p, noise, None, plain, probe, rho_ref=1e-3)
+        assert info["fallback"] and np.isfinite(info["rho_learned"]) and info["rho_learned"] > 1e-3
+        # the trained network keeps its start at the default reference
+        info = ls.setup_with_fallback(ctx, p, noise, None, plain, probe)
+        assert not info["fallback"] and info["rho_learned"] < 0.9
+        x, st = ctx.solve(b, tol=1e-10)
+        assert np.linalg.norm(b - op.apply(x)) <= 1e-10 * np.linalg.norm(b)
