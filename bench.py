@@ -11,7 +11,7 @@ Gaussian sources, network noise and level-1 test vectors, all seeded) are
 generated on the device before the timed region.
 
     python bench.py [--gpus 1] [--steps 1] [--warmup 0] [--nrhs 12]
-                    [--rhs-batch 3] [--fp64-compare 1] [--cpu-baseline 1]
+                    [--rhs-batch 6] [--restart 4] [--fp64-compare 1] [--cpu-baseline 1]
 
 Prints one JSON line.  `value` is the mixed-precision step time in seconds
 (lower is better).  After the timed steps:
@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 T_START = time.time()
 METRIC = "D(μ) GB/s; DD-αAMG time to 1e-10 residual at 48^3×96, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6
 KAPPA, CSW, MU = 0.13729, 1.57551, 0.0009
 # algorithmic bytes per site of one FP64 D(mu) apply: spinor in + out (2 x 192),
 # links (4 x 9 complex), clover (two Hermitian 6x6 = 72 reals)
@@ -56,7 +57,10 @@ def parse():
     ap.add_argument("--fp64-setup-iters", type=int, default=5)
     ap.add_argument("--fp64-rhs-batch", type=int, default=2)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--rhs-batch", type=int, default=3)
+    ap.add_argument("--rhs-batch", type=int, default=6)
+    ap.add_argument("--restart", type=int, default=4,
+                    help="outer FGMRES restart of the mixed form (its FP64 basis of restart+1 fields per "
+                         "right-hand side is what bounds the lock-step group at 48^3x96)")
     ap.add_argument("--learned", type=int, default=1)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--time-budget", type=float, default=540.0,
@@ -67,7 +71,7 @@ def parse():
 
 
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.time() - T_START:6.1f} s]", *a, file=sys.stderr, flush=True)
 
 
 def oracle_leg(U, x0, b0, y_lib, budget_s=25.0):
@@ -219,6 +223,7 @@ def main():
     del U
     torch.cuda.empty_cache()
     p_mixed = params(args.precision, args.setup_iters, kb, args.batch)
+    p_mixed.restart = args.restart
     overrides = {}
     for kv in args.set:
         k, v = kv.split("=", 1)
@@ -254,6 +259,8 @@ def main():
     ctx.timing(False)
     log(f"mixed step {dt:.2f} s, stats {stats}")
 
+    # the solve's workspaces go back to the device for the checks below
+    ctx.release_memory()
     # true residuals of the last solve, checked in FP64 on the device
     resid = 0.0
     for i in range(args.nrhs):
@@ -271,14 +278,20 @@ def main():
     # group); the library adds up each launch's algorithmic bytes
     n_s, ms_s = kinds["fine_sap"]
     bytes_s = ctx.timing_bytes(1)
+    flops_s = ctx.timing_flops(1)
     sap = None
     if n_s and ms_s > 0:
-        a = bytes_s / (ms_s * 1e-3) / 1e9
-        sap = {"bound": "hbm", "kernel": f"fine SAP colour sweep ({args.precision} links, FP32 arithmetic, "
-                                          f"4 MR steps), K fields per launch",
-               "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4),
-               "traffic": None, "algorithmic_bytes": bytes_s, "launches": n_s,
-               "avg_launch_ms": round(ms_s / n_s, 4)}
+        # bound by instruction issue: FP32 flops against the FP32 vector peak
+        # without packed math (the build disables packed FP32 instructions):
+        # 256 CUs x 4 SIMDs x 16 lanes x 2 (fused multiply-add) x 2.4 GHz
+        a = flops_s / (ms_s * 1e-3) / 1e12
+        gbs = bytes_s / (ms_s * 1e-3) / 1e9
+        sap = {"bound": "alu", "kernel": f"fine SAP colour sweep ({args.precision} links, FP32 arithmetic, "
+                                         f"4 MR steps), K fields per launch",
+               "achieved": round(a, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": round(a / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None, "algorithmic_flops": flops_s,
+               "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_s,
+               "launches": n_s, "avg_launch_ms": round(ms_s / n_s, 4)}
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -308,8 +321,28 @@ def main():
             torch.cuda.synchronize()
             t1 = time.time()
             c64.setup(p64, [V0, V1])
-            log(f"fp64: setup issued ({time.time() - t1:.1f} s)")
-            _, fp64_stats = c64.solve(b, tol=1e-10, x=x)
+            del V0
+            torch.cuda.empty_cache()
+            log(f"fp64: setup done ({time.time() - t1:.1f} s)")
+            # the right-hand sides group by group (one call each, so that the
+            # run reports progress); statistics summed as one call would
+            kb64 = p64.rhs_batch
+            fp64_stats = None
+            for g0 in range(0, args.nrhs, kb64):
+                _, st = c64.solve(b[g0:g0 + kb64], tol=1e-10, x=x[g0:g0 + kb64])
+                if fp64_stats is None:
+                    fp64_stats = st
+                else:
+                    for k in ("iters", "vcycles", "nrhs"):
+                        fp64_stats[k] += st[k]
+                    fp64_stats["coarse_iters"] = [a + c for a, c in zip(fp64_stats["coarse_iters"],
+                                                                         st["coarse_iters"])]
+                    fp64_stats["converged"] = fp64_stats["converged"] and st["converged"]
+                    fp64_stats["resid"] = max(fp64_stats["resid"], st["resid"])
+                    fp64_stats["iters_min"] = min(fp64_stats["iters_min"], st["iters_min"])
+                    fp64_stats["iters_max"] = max(fp64_stats["iters_max"], st["iters_max"])
+                    fp64_stats["seconds"] += st["seconds"]
+                log(f"fp64: right-hand sides {g0}..{g0 + kb64 - 1} solved ({time.time() - t1:.1f} s)")
             torch.cuda.synchronize()
             fp64_s = time.time() - t1
             c64.close()
@@ -340,7 +373,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(str(d) for d in reversed(dims))} twisted-mass Wilson-clover, "
                                f"kappa {KAPPA}, c_sw {CSW}, mu {MU}, delta 5, 3 levels (4^4, 2^4 aggregates, "
-                               f"Nv 24/32), {args.nrhs} rhs ({kb} in lock step), "
+                               f"Nv 24/32), {args.nrhs} rhs ({kb} in lock step, outer restart {args.restart}), "
                                f"{'learned' if args.learned else 'random'} initial test vectors + "
                                f"{args.setup_iters} setup iteration(s) on batches of {args.batch} test vectors, "
                                f"preconditioner {args.precision}, outer FGMRES FP64, tol 1e-10"

@@ -314,6 +314,15 @@ int ddamg_coarse_sap_multi(ddamg_ctx* ctx, int level, int nrhs, const void* b, v
  * test).  Same solver and layout as ddamg_coarse_solve; 1 <= nrhs <= 16. */
 int ddamg_coarse_solve_multi(ddamg_ctx* ctx, int level, int nrhs, const void* b, void* x);
 
+/* Device memory of a context: the library keeps the device memory it has
+ * taken (slabs of its own pool) for the context's later calls, because
+ * re-allocating freed device memory is slow on this device.  This call gives
+ * back every slab with nothing in use (the workspaces of finished setups and
+ * solves), keeping the operator, the hierarchy and every live buffer; held
+ * (may be NULL) receives the bytes the context still holds.  Later calls take
+ * memory again as they need it. */
+int ddamg_release_memory(ddamg_ctx* ctx, double* held);
+
 /* ---- measurement ---- */
 /* Run napply applications of D(mu) on device-resident fields in the
  * library's own layout (inputs already in HBM), on the context stream;
@@ -339,6 +348,12 @@ int ddamg_timing_query(ddamg_ctx* ctx, int kind, long* count, double* ms);
  * other colour's x (48 complex); other kinds report 0.  bytes / (ms 1e-3) is
  * the achieved rate. */
 int ddamg_timing_bytes(ddamg_ctx* ctx, int kind, double* bytes);
+/* Real floating-point operations of the launches timed so far of a kind (a
+ * complex multiply-add counts 8): kind 1, per site of the swept colour and
+ * field 4932 + 2604 n_MR (the residual, the odd-site solves, the first rho,
+ * n_MR MR steps on the even-site Schur complement and the odd-site
+ * correction; 15348 at n_MR = 4); other kinds report 0. */
+int ddamg_timing_flops(ddamg_ctx* ctx, int kind, double* flops);
 
 /* ---- learned setup (not a method of the paper: it replaces the random start
  * of the adaptive setup; the plain setup stays the fallback) ----

@@ -945,10 +945,27 @@ int ddamg_error_reduction(ddamg_ctx* ctx, const void* e0, int on_device, int n, 
   });
 }
 
+int ddamg_release_memory(ddamg_ctx* ctx, double* held) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    c.pool.trim();
+    if (held) *held = (double)c.pool.reserved();
+    return DDAMG_OK;
+  });
+}
+
 int ddamg_timing_bytes(ddamg_ctx* ctx, int kind, double* bytes) {
   if (!ctx || kind < 0 || kind >= KernelTimer::NKIND || !bytes) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {
     *bytes = ctx->c.timer.bytes[kind];
+    return DDAMG_OK;
+  });
+}
+int ddamg_timing_flops(ddamg_ctx* ctx, int kind, double* flops) {
+  if (!ctx || kind < 0 || kind >= KernelTimer::NKIND || !flops) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    *flops = ctx->c.timer.flops[kind];
     return DDAMG_OK;
   });
 }

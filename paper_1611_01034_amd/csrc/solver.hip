@@ -193,9 +193,10 @@ void KernelTimer::begin(int kind, hipEvent_t* a) {
   *a = get();
   HIP_CHECK(hipEventRecord(*a, st));
 }
-void KernelTimer::end(int kind, hipEvent_t a, double nbytes) {
+void KernelTimer::end(int kind, hipEvent_t a, double nbytes, double nflops) {
   if (!on || !a) return;
   bytes[kind] += nbytes;
+  flops[kind] += nflops;
   hipEvent_t b = get();
   HIP_CHECK(hipEventRecord(b, st));
   recs.push_back({kind, a, b});
@@ -219,6 +220,7 @@ void KernelTimer::reset() {
     count[i] = 0;
     ms[i] = 0;
     bytes[i] = 0;
+    flops[i] = 0;
   }
 }
 KernelTimer::~KernelTimer() {
@@ -233,10 +235,27 @@ struct TimeScope {
   KernelTimer& t;
   int kind;
   hipEvent_t a;
-  double b;
-  TimeScope(KernelTimer& t_, int k, double bytes = 0) : t(t_), kind(k), b(bytes) { t.begin(k, &a); }
-  ~TimeScope() { t.end(kind, a, b); }
+  double b, f;
+  TimeScope(KernelTimer& t_, int k, double bytes = 0, double flops = 0) : t(t_), kind(k), b(bytes), f(flops) {
+    t.begin(k, &a);
+  }
+  ~TimeScope() { t.end(kind, a, b, f); }
 };
+
+// Real flops of one fine SAP colour sweep of K fields (a complex multiply-add
+// counts 8, a real-times-complex product 2, an addition 1).  A packed
+// Hermitian 6x6 product is 252 (6 diagonal, 15 off-diagonal entries used
+// twice), the twist 4 per component, one hop 204 (spin projection 12, two
+// 3x3 link products 144, reconstruction 48).  Per site of the swept colour:
+// the residual b - D x (site term 552, eight hops 1632, subtraction 24), and
+// on half of the sites each: T_oo^-1 r_o with x_o += t_o (1056 + 24), the
+// first rho (hops), per MR step w = T_oo^-1 D_oe rho and q = T_ee rho - D_eo w
+// with the dots and updates (5208 per pair), and the closing correction (hops,
+// T_oo^-1, two updates: 2736 per pair).
+static double sap_sweep_flops(const Geom& g, int K, int n_mr) {
+  const double per_site = 4932.0 + 2604.0 * n_mr;
+  return 0.5 * (double)g.V * K * per_site;
+}
 
 // Algorithmic bytes of one fine SAP colour sweep of K fields (each datum
 // moved once): per site of the swept colour the links (36 entries of the
@@ -859,6 +878,7 @@ struct MG : MGBase {
   int Nv[3] = {0, 0, 0};
   DevBuf Vraw[3], Q[3];
   DevBuf D64[4], DS[4], Minvc, Xs, invscr;
+  size_t xs_bytes = 0;  // assembly scratch (transient: taken per assembly, released after the setup)
   double tw[4] = {0, 0, 0, 0};
   DevBuf fx, fb, fr;              // fine R vectors
   DevBuf rc[4], ec[4], wk[4][4];  // coarse vectors per level
@@ -957,7 +977,7 @@ struct MG : MGBase {
         invscr.alloc(sizeof(cx<double>) * nn * 2 * (G.nsites - G.neven));
       }
     }
-    Xs.alloc(sizeof(cx<double>) * maxnn);
+    xs_bytes = sizeof(cx<double>) * maxnn;
     for (int l = 1; l < L; ++l) {
       CoarseGeo& G = *geos[l];
       CGeom cg = G.cg();
@@ -1001,7 +1021,7 @@ struct MG : MGBase {
   void fine_sap(const cx<R>* b, cx<R>* x, int iters, int nmr) {
     for (int it = 0; it < iters; ++it)
       for (int col = 0; col < 2; ++col) {
-        TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, 1));
+        TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, 1), sap_sweep_flops(c.g, 1, nmr));
         launch_sap<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, c.st);
       }
   }
@@ -1009,7 +1029,7 @@ struct MG : MGBase {
   void fine_sap_m(const cx<R>* b, cx<R>* x, int K, int iters, int nmr) {
     for (int it = 0; it < iters; ++it)
       for (int col = 0; col < 2; ++col) {
-        TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, K));
+        TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, K), sap_sweep_flops(c.g, K, nmr));
         launch_sap_multi<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, K, c.fine_len(), c.st);
       }
   }
@@ -1150,8 +1170,10 @@ struct MG : MGBase {
       rcm[l].ensure(sizeof(cx<R>) * len * K);
       ecm[l].ensure(sizeof(cx<R>) * len * K);
       for (int k = 0; k < 2; ++k) wkm[l][k].ensure(sizeof(cx<R>) * len * K);
-      if (l < L - 1) kwsm[l].init(p.inter_restart, K, len, len, true);
-      else kwsm[l].init(p.coarse_restart, K, len, (long)G.neven * G.n, false);
+      // the lock-step Krylov bases are transient: the setup's batch width and
+      // the solve's group width differ (released at the end of the setup)
+      if (l < L - 1) kwsm[l].init(p.inter_restart, K, len, len, true, false, true);
+      else kwsm[l].init(p.coarse_restart, K, len, (long)G.neven * G.n, false, false, true);
       CGeom cg = G.cg();
       if (l == L - 1) {
         cx<R>* t = wkm[l][0].template as<cx<R>>();
@@ -1383,6 +1405,7 @@ struct MG : MGBase {
   }
 
   void assemble_next(int l) {
+    Xs.ensure(xs_bytes, true);
     long len = level_len(l);
     CoarseGeo& Gn = *geos[l + 1];
     if (l == 0) {
@@ -1540,6 +1563,15 @@ struct MG : MGBase {
     if (!p.keep_test_vectors)
       for (int l = 0; l < L - 1; ++l) Vraw[l].release();
     fxm.release();
+    Xs.release();
+    // the K-column bases sized for the setup's batch: the solve re-creates
+    // them at its own width (the K-column work fields keep their size)
+    for (int l = 1; l < L; ++l) {
+      kwsm[l].V.release();
+      kwsm[l].Z.release();
+      kwsm[l].r.release();
+    }
+    Km = 0;
   }
 
   // ---- parity helpers (host FP64 in/out) --------------------------------------

@@ -117,9 +117,10 @@ struct KernelTimer {
   long count[NKIND] = {0, 0, 0, 0, 0, 0};
   double ms[NKIND] = {0, 0, 0, 0, 0, 0};
   double bytes[NKIND] = {0, 0, 0, 0, 0, 0};  // algorithmic bytes of the timed launches (kinds 0, 1)
+  double flops[NKIND] = {0, 0, 0, 0, 0, 0};  // algorithmic flops of the timed launches (kind 1)
   hipEvent_t get();
   void begin(int kind, hipEvent_t* a);
-  void end(int kind, hipEvent_t a, double b = 0);
+  void end(int kind, hipEvent_t a, double b = 0, double f = 0);
   void flush();
   void reset();
   ~KernelTimer();

@@ -122,6 +122,8 @@ _SIGS = {
     "ddamg_timing": (_i, [_vp, _i]),
     "ddamg_timing_query": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
     "ddamg_timing_bytes": (_i, [_vp, _i, ctypes.POINTER(_d)]),
+    "ddamg_release_memory": (_i, [_vp, ctypes.POINTER(_d)]),
+    "ddamg_timing_flops": (_i, [_vp, _i, ctypes.POINTER(_d)]),
     "ddamg_error_reduction": (_i, [_vp, _vp, _i, _i, ctypes.POINTER(_d)]),
     "ddamg_net_create": (_i, [_vp, _i, _i]),
     "ddamg_net_num_params": (ctypes.c_long, [_vp]),
@@ -556,7 +558,18 @@ class DDAMG:
         self._check(_lib.ddamg_error_reduction(self._h, pe, dev, int(n), ctypes.byref(r)))
         return r.value
 
+    def release_memory(self):
+        """Give back the device memory of finished workspaces; returns the bytes still held."""
+        h = ctypes.c_double()
+        self._check(_lib.ddamg_release_memory(self._h, ctypes.byref(h)))
+        return h.value
+
     def timing_bytes(self, kind):
         b = ctypes.c_double()
         self._check(_lib.ddamg_timing_bytes(self._h, int(kind), ctypes.byref(b)))
         return b.value
+
+    def timing_flops(self, kind):
+        f = ctypes.c_double()
+        self._check(_lib.ddamg_timing_flops(self._h, int(kind), ctypes.byref(f)))
+        return f.value
