@@ -18,11 +18,12 @@ Prints one JSON line.  `value` is the mixed-precision step time in seconds
   * the plain FP64 form (random start, 5-iteration setup) runs once on the
     same right-hand sides when it fits --time-budget (seconds since start),
     else the line says it was skipped;
-  * the oracle leg (cpu_baseline): the FP64 CPU oracle applies D(mu) to the
-    solution of the first right-hand side over the whole 48^3 x 96 lattice in
-    time slabs on the host's cores, which times the oracle (GB/s with the
-    same algorithmic bytes as the device kernel) and gives the oracle's own
-    true residual of that solution and its agreement with the library's D(mu).
+  * the oracle leg (cpu_baseline), which runs on the host while the GPU
+    works: the FP64 CPU oracle applies D(mu) to the first right-hand side on
+    single time slices, one slice on one thread, then --oracle-procs slices on
+    as many processes (GB/s with the device kernel's algorithmic bytes); the
+    slices are compared with the library's D(mu), and at --oracle-sites
+    random sites the oracle computes b - D x of the first solution.
 """
 import argparse
 import hashlib
@@ -30,6 +31,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -57,6 +60,10 @@ def parse():
     ap.add_argument("--fp64-setup-iters", type=int, default=5)
     ap.add_argument("--fp64-rhs-batch", type=int, default=2)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--oracle-procs", type=int, default=8,
+                    help="worker processes of the oracle leg (one time slice each)")
+    ap.add_argument("--oracle-sites", type=int, default=512,
+                    help="random sites at which the oracle checks b - D x of the first solution")
     ap.add_argument("--rhs-batch", type=int, default=6)
     ap.add_argument("--restart", type=int, default=4,
                     help="outer FGMRES restart of the mixed form (its FP64 basis of restart+1 fields per "
@@ -74,72 +81,132 @@ def log(*a):
     print(f"[{time.time() - T_START:6.1f} s]", *a, file=sys.stderr, flush=True)
 
 
-def oracle_leg(U, x0, b0, y_lib, budget_s=25.0):
-    """The FP64 oracle on the host: D(mu) x0 over the whole lattice in time
-    slabs of two slices (one halo slice each side), on as many threads as the
-    host offers (at most 16).  Returns the cpu_baseline record and the
-    oracle's check of the device result (true residual of x0, agreement of
-    the library's D(mu) x0 with the oracle's)."""
-    import numpy as np
-    from concurrent.futures import ThreadPoolExecutor
-
+def _oracle_slab(args):
+    """One oracle D(mu) apply on one time slice: Us, bs hold the slices
+    t-1, t, t+1 of the links and of the spinor; returns (seconds, D bs on t).
+    Module level, so that worker processes can import it."""
+    Us, bs = args
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
         threadpool_limits = None
     from oracle import dirac
+    lim = threadpool_limits(1) if threadpool_limits else None
+    t = time.time()
+    y = dirac.apply_t_slab(Us, bs, KAPPA, CSW, MU, 1, 1)[0]
+    dt = time.time() - t
+    if lim is not None and hasattr(lim, "unregister"):
+        lim.unregister()
+    return dt, y
 
-    T = U.shape[0]
-    nt = 2
-    slabs = list(range(0, T, nt))
-    sites_slab = nt * int(np.prod(U.shape[1:4]))
-    cores = max(1, min(16, os.cpu_count() or 1))
 
-    def work(t0):
-        t = time.time()
-        Dx = dirac.apply_t_slab(U, x0, KAPPA, CSW, MU, t0, nt)
-        dt = time.time() - t
-        rows = list(range(t0, t0 + nt))
-        r = b0[rows] - Dx
-        d = Dx - y_lib[rows]
-        return (dt, float(np.vdot(r, r).real), float(np.vdot(b0[rows], b0[rows]).real),
-                float(np.abs(d).max()), float(np.abs(Dx).max()))
+class OracleLeg:
+    """The FP64 CPU oracle timed on the host while the GPU runs the steps.
 
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    # one core: slabs one after another until the bounded sample is used
-    t1 = time.time()
-    one = []
-    for t0 in slabs:
-        one.append(work(t0))
-        if time.time() - t1 > budget_s / 2:
-            break
-    t1 = time.time() - t1
-    # all cores: the whole lattice (the slabs done above are not repeated)
-    rest = slabs[len(one):]
-    tp = time.time()
-    with ThreadPoolExecutor(max_workers=cores) as ex:
-        many = list(ex.map(work, rest))
-    tp = time.time() - tp
-    if ctx is not None and hasattr(ctx, "unregister"):
-        ctx.unregister()
-    allr = one + many
-    r2 = sum(v[1] for v in allr)
-    b2 = sum(v[2] for v in allr)
-    dmax = max(v[3] for v in allr)
-    ymax = max(v[4] for v in allr)
-    gbs1 = len(one) * sites_slab * DIRAC_FP64_BYTES_PER_SITE / t1 / 1e9
-    gbsp = len(rest) * sites_slab * DIRAC_FP64_BYTES_PER_SITE / tp / 1e9 if rest else None
-    cpu = {"value": round(gbsp if gbsp else gbs1, 3), "unit": "GB/s", "cores": cores if gbsp else 1,
-           "kind": "oracle",
-           "sample": f"numpy FP64 oracle D(mu) on the 48^3x96 solution of the first right-hand side, time slabs "
-                     f"of {nt} slices with one halo slice each side: {len(rest)} slabs on {cores} threads in "
-                     f"{tp:.1f} s (whole lattice with the {len(one)} slabs timed on one thread in {t1:.1f} s, "
-                     f"{gbs1:.3f} GB/s); bytes counted as the device kernel's {DIRAC_FP64_BYTES_PER_SITE} B/site",
-           "one_core_gbs": round(gbs1, 4)}
-    check = {"oracle_true_residual_rhs0": float(np.sqrt(r2 / b2)),
-             "dirac_max_abs_diff_over_max": dmax / ymax,
-             "sites_checked": len(allr) * sites_slab}
-    return cpu, check
+    D(mu) b_0 on single time slices of the lattice (the oracle's
+    slab apply: slices t-1..t+1 gathered, the operator applied on that slab,
+    the middle slice kept): first one slice on one thread, then `nproc` slices
+    on `nproc` worker processes at once.  GB/s counts the device kernel's
+    algorithmic bytes for the sites produced.  The slices' values are checked
+    against the library's D(mu) b_0 after the steps (`check`)."""
+
+    def __init__(self, U_dev, b0_dev, nproc):
+        import threading
+        T = U_dev.shape[0]
+        self.nproc = nproc
+        self.T = T
+        # slice 0 on one thread, then nproc slices spread over T
+        self.ts = [0] + [1 + k * (T // nproc) for k in range(nproc)]
+        self.inputs = []
+        for t in self.ts:
+            rows = [(t - 1) % T, t, (t + 1) % T]
+            self.inputs.append((U_dev[rows].cpu().numpy(), b0_dev[rows].cpu().numpy()))
+        self.sites_slice = int(np.prod(U_dev.shape[1:4]))
+        self.lattice = "x".join(str(d) for d in reversed(tuple(U_dev.shape[:4])))
+        self.res = {}
+        self.th = threading.Thread(target=self._run, daemon=True)
+        self.th.start()
+
+    def _run(self):
+        try:
+            from concurrent.futures import ProcessPoolExecutor
+            import multiprocessing as mp
+            dt1, y1 = _oracle_slab(self.inputs[0])
+            self.res["one"] = (dt1, y1)
+            log(f"oracle leg: one slice on one thread in {dt1:.1f} s")
+            tp = time.time()
+            ex = ProcessPoolExecutor(max_workers=self.nproc, mp_context=mp.get_context("spawn"))
+            try:
+                many = list(ex.map(_oracle_slab, self.inputs[1:], timeout=900))
+            finally:
+                ex.shutdown(wait=False, cancel_futures=True)
+            tp = time.time() - tp
+            self.res["many"] = (tp, many)
+            log(f"oracle leg: {self.nproc} slices on {self.nproc} processes in {tp:.1f} s")
+        except Exception as e:  # reported in the JSON line
+            self.res["error"] = repr(e)
+        finally:
+            self.inputs = None
+
+    def result(self, yb_slices):
+        """Join; yb_slices[t] = the library's D(mu) b_0 on slice t."""
+        self.th.join(timeout=600)
+        if self.th.is_alive():
+            return None, {"error": "the oracle leg did not finish within 600 s of the GPU work"}
+        if "error" in self.res:
+            return None, {"error": self.res["error"]}
+        dt1, y1 = self.res["one"]
+        tp, many = self.res["many"]
+        bps = self.sites_slice * DIRAC_FP64_BYTES_PER_SITE
+        gbs1 = bps / dt1 / 1e9
+        gbsp = self.nproc * bps / tp / 1e9
+        ys = [y1] + [m[1] for m in many]
+        dmax = max(float(np.abs(y - yb_slices[t]).max()) for t, y in zip(self.ts, ys))
+        ymax = max(float(np.abs(yb_slices[t]).max()) for t in self.ts)
+        cpu = {"value": round(gbsp, 4), "unit": "GB/s", "cores": self.nproc, "kind": "oracle",
+               "sample": f"numpy FP64 oracle D(mu) b_0 on single time slices of the {self.lattice} lattice (slab of 3 "
+                         f"slices gathered, middle slice kept; {self.sites_slice} sites each): {self.nproc} slices "
+                         f"on {self.nproc} worker processes in {tp:.1f} s; bytes counted as the device kernel's "
+                         f"{DIRAC_FP64_BYTES_PER_SITE} B/site; run on the host while the GPU ran the steps",
+               "one_core_gbs": round(gbs1, 5), "one_core_s_per_slice": round(dt1, 2)}
+        check = {"dirac_slices_max_abs_diff_over_max": dmax / ymax,
+                 "dirac_sites_checked": len(ys) * self.sites_slice}
+        return cpu, check
+
+
+def oracle_sites(U_dev, x0_dev, b0_dev, yx_dev, nsites, seed=7):
+    """b - D x of the device solution at random sites, by the oracle: the
+    3^4 neighbourhood of each site (links and x_0) is gathered from the
+    device and the oracle's site apply gives (D x_0)(site); compared with the
+    library's D(mu) x_0 at the same sites."""
+    import torch
+    from oracle import dirac
+    dims = tuple(U_dev.shape[:4])
+    rng = np.random.default_rng(seed)
+    sites = np.stack([rng.integers(0, d, nsites) for d in dims], axis=1)
+    t = time.time()
+    # every site's 3^4 neighbourhood in one gather: index [site, o_T, o_Z, o_Y, o_X]
+    off = np.arange(-1, 2)
+    idx = []
+    for d in range(4):
+        shape = [nsites, 1, 1, 1, 1]
+        shape[1 + d] = 3
+        v = (sites[:, d][:, None] + off[None, :]) % dims[d]
+        idx.append(torch.as_tensor(v.reshape(shape), device=U_dev.device))
+    Up = U_dev[tuple(idx)].cpu().numpy()
+    xp = x0_dev[tuple(idx)].cpu().numpy()
+    centre = tuple(torch.as_tensor(sites[:, d], device=U_dev.device) for d in range(4))
+    bs_all = b0_dev[centre].cpu().numpy()
+    ys_all = yx_dev[centre].cpu().numpy()
+    num = den = dlib = 0.0
+    for k in range(nsites):
+        Dx = dirac.apply_at_sites(Up[k], xp[k], KAPPA, CSW, MU, [(1, 1, 1, 1)])[0]
+        bs, ys = bs_all[k], ys_all[k]
+        num += float(np.sum(np.abs(bs - Dx) ** 2))
+        den += float(np.sum(np.abs(bs) ** 2))
+        dlib = max(dlib, float(np.abs(ys - Dx).max()) / max(float(np.abs(Dx).max()), 1e-300))
+    return {"sites_sampled": int(nsites), "oracle_residual_at_sites": float(np.sqrt(num / den)),
+            "dirac_x0_max_rel_diff_at_sites": dlib, "seconds": round(time.time() - t, 1)}
 
 
 DIRAC_SOURCES = ["dirac.hip", "finedev.hpp", "common.hpp"]
@@ -218,8 +285,11 @@ def main():
                                     rhs_batch=rhs_batch)
 
     ctx = make_ctx(U, net=bool(args.learned))
-    # the device copy of the links is the library's from here on; the host
-    # oracle leg regenerates the same seeded field
+    # the oracle leg takes its slices of the inputs now and runs on the host
+    # while the GPU works
+    leg = OracleLeg(U, b[0], args.oracle_procs) if args.cpu_baseline else None
+    # the device copy of the links is the library's from here on; the site
+    # check after the steps regenerates the same seeded field
     del U
     torch.cuda.empty_cache()
     p_mixed = params(args.precision, args.setup_iters, kb, args.batch)
@@ -266,7 +336,20 @@ def main():
     for i in range(args.nrhs):
         r = ctx.apply_dirac(x[i])
         resid = max(resid, float(torch.linalg.vector_norm(b[i] - r) / torch.linalg.vector_norm(b[i])))
-    y0 = ctx.apply_dirac(x[0]).cpu().numpy() if args.cpu_baseline else None
+    yb_slices = None
+    sites_check = None
+    if leg is not None:
+        # the library's D(mu) b_0 on the oracle's slices, and the oracle's
+        # b - D x at random sites of the first solution
+        yb = ctx.apply_dirac(b[0])
+        yb_slices = {t: yb[t].cpu().numpy() for t in leg.ts}
+        del yb
+        yx = ctx.apply_dirac(x[0])
+        Ud = synth.gauge_field_device(dims, 0.3, 5001)
+        sites_check = oracle_sites(Ud, x[0], b[0], yx, args.oracle_sites)
+        del yx, Ud
+        torch.cuda.empty_cache()
+        log(f"oracle at {args.oracle_sites} random sites: {sites_check}")
 
     # D(mu) FP64 bandwidth inside the timed steps (HIP events around every launch)
     avg_ms = ms_d / max(n_d, 1)
@@ -316,6 +399,8 @@ def main():
             c64 = make_ctx(U)
             del U
             torch.cuda.empty_cache()
+            c64.set_progress(lambda stage, level, i: log(
+                f"fp64: setup level {level} " + ("initial phase done" if stage == 0 else f"iteration {i + 1} done")))
             # FP64 fine fields are twice the size: 4 test vectors per setup batch
             p64 = params("fp64", args.fp64_setup_iters, min(args.fp64_rhs_batch, args.nrhs), min(args.batch, 4))
             torch.cuda.synchronize()
@@ -350,13 +435,10 @@ def main():
 
     cpu = None
     check = None
-    if args.cpu_baseline:
-        log("oracle leg on the host")
-        U_host = synth.gauge_field_device(dims, 0.3, 5001).cpu().numpy()
-        x0 = x[0].cpu().numpy()
-        b0 = b[0].cpu().numpy()
-        cpu, check = oracle_leg(U_host, x0, b0, y0)
-        log(f"oracle: {cpu['value']} GB/s on {cpu['cores']} threads, check {check}")
+    if leg is not None:
+        cpu, check = leg.result(yb_slices)
+        check.update(sites_check)
+        log(f"oracle: {cpu and cpu['value']} GB/s on {cpu and cpu['cores']} processes, check {check}")
 
     out = {
         "metric": METRIC,

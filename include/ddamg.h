@@ -162,6 +162,17 @@ int ddamg_set_mu(ddamg_ctx* ctx, double mu);
  * draws no random numbers itself.  Returns INVALID_ARG for shapes that do
  * not aggregate, NUMERICAL for a rank-deficient aggregate. */
 int ddamg_setup(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_vectors, int on_device);
+/* Progress of a long setup (a host-side notification; the method is
+ * unchanged).  With fn set, ddamg_setup, ddamg_setup_learned and
+ * ddamg_update_gauge call fn(user, stage, level, index) on the calling thread
+ * once the context stream has finished that stage: stage 0 when the initial
+ * phase of level `level` (its test vectors smoothed, level+1 built) is done,
+ * stage 1 when iteration `index` (from 0) of the iterated setup phase on
+ * level `level` is done.  Each notification waits for the stream once;
+ * fn = NULL (the default) turns it off.  fn must not call the library with
+ * the same context.  INVALID_ARG for a NULL context. */
+typedef void (*ddamg_progress_fn)(void* user, int stage, int level, int index);
+int ddamg_set_progress(ddamg_ctx* ctx, ddamg_progress_fn fn, void* user);
 /* Build the hierarchy directly from given test vectors (no smoothing, no
  * setup iteration): P from their block orthonormalisation, D_c by Galerkin
  * assembly.  Same shapes as ddamg_setup. */

@@ -945,6 +945,13 @@ int ddamg_error_reduction(ddamg_ctx* ctx, const void* e0, int on_device, int n, 
   });
 }
 
+int ddamg_set_progress(ddamg_ctx* ctx, ddamg_progress_fn fn, void* user) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  ctx->c.progress_fn = fn;
+  ctx->c.progress_user = fn ? user : nullptr;
+  return DDAMG_OK;
+}
+
 int ddamg_release_memory(ddamg_ctx* ctx, double* held) {
   if (!ctx) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {

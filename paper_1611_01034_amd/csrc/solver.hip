@@ -1546,14 +1546,19 @@ struct MG : MGBase {
                          p.init_sap_iters);
       }
       build_next(l);
+      c.progress(0, l, 0);
     }
     if (run_setup) {
       for (int it = 0; it < p.setup_iters; ++it) {
         iterate(0);
         if (L == 3) {
           assemble_next(1);
-          for (int t = 0; t < p.coarse_setup_iters; ++t) iterate(1);
+          for (int t = 0; t < p.coarse_setup_iters; ++t) {
+            iterate(1);
+            c.progress(1, 1, t);
+          }
         }
+        c.progress(1, 0, it);
       }
     }
     c.sync();

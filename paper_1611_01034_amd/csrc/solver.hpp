@@ -305,12 +305,20 @@ struct Ctx {
   NetState net;
   KernelTimer timer;
   std::string err;
+  ddamg_progress_fn progress_fn = nullptr;  // setup notifications (ddamg_set_progress)
+  void* progress_user = nullptr;
 
   long fine_len() const { return g.V * 12; }
   void ensure_32();
   void ensure_16(int kind);
   void rebuild_odd_inverse();
   void sync() { HIP_CHECK(hipStreamSynchronize(st)); }
+  // setup stage finished: wait for the stream, then tell the caller
+  void progress(int stage, int level, int index) {
+    if (!progress_fn) return;
+    sync();
+    progress_fn(progress_user, stage, level, index);
+  }
   // fine FP64 operator D(tw) in block layout
   void dirac64(const cx<double>* in, cx<double>* out, double tw);
   // host/device lex FP64 field -> block layout

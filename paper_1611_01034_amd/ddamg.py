@@ -84,6 +84,7 @@ class Stats(ctypes.Structure):
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
+_PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int)
 _SIGS = {
     "ddamg_default_params": (None, [ctypes.POINTER(Params)]),
     "ddamg_create": (_i, [ctypes.POINTER(_i), ctypes.POINTER(_i), _d, _d, _d, _vp, ctypes.POINTER(_vp)]),
@@ -123,6 +124,7 @@ _SIGS = {
     "ddamg_timing_query": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
     "ddamg_timing_bytes": (_i, [_vp, _i, ctypes.POINTER(_d)]),
     "ddamg_release_memory": (_i, [_vp, ctypes.POINTER(_d)]),
+    "ddamg_set_progress": (_i, [_vp, _vp, _vp]),
     "ddamg_timing_flops": (_i, [_vp, _i, ctypes.POINTER(_d)]),
     "ddamg_error_reduction": (_i, [_vp, _vp, _i, _i, ctypes.POINTER(_d)]),
     "ddamg_net_create": (_i, [_vp, _i, _i]),
@@ -540,6 +542,18 @@ class DDAMG:
     # ---- measurement ---------------------------------------------------------
     def bench_dirac(self, napply, precision="fp64"):
         self._check(_lib.ddamg_bench_dirac(self._h, PRECISIONS[precision], int(napply)))
+
+    def set_progress(self, fn):
+        """fn(stage, level, index) after every finished setup stage (stage 0:
+        initial phase of a level, 1: one iteration of the iterated phase), or
+        None to stop the notifications."""
+        if fn is None:
+            self._progress = None
+            self._check(_lib.ddamg_set_progress(self._h, None, None))
+            return
+        cb = _PROGRESS_FN(lambda user, stage, level, index: fn(stage, level, index))
+        self._progress = cb  # the library holds the pointer: keep the thunk alive
+        self._check(_lib.ddamg_set_progress(self._h, ctypes.cast(cb, _vp), None))
 
     def timing(self, enable):
         self._check(_lib.ddamg_timing(self._h, int(bool(enable))))

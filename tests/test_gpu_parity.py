@@ -466,3 +466,27 @@ def test_rank_deficient_test_vectors_rejected(dd, prec):
     with pytest.raises(dd.DDAMGError) as e:
         ctx.set_test_vectors(p, [V.reshape((nv,) + dims + (4, 3))])
     assert e.value.status == dd.NUMERICAL
+
+
+def test_setup_progress_notifications(dd):
+    # one notification per finished initial phase and setup iteration, in
+    # order; none after the callback is removed
+    dims = (8, 8, 8, 8)
+    ctx, op, U = make(dd, dims, (2, 2, 2, 2))
+    calls = []
+    ctx.set_progress(lambda stage, level, i: calls.append((stage, level, i)))
+    V0 = synth.gaussian((6,) + dims + (4, 3), 1701)
+    p = dd.default_params(levels=2, block=[(2, 2, 2, 2)], nvec=[6], setup_iters=2, precision="fp32")
+    ctx.setup(p, [V0])
+    assert calls == [(0, 0, 0), (1, 0, 0), (1, 0, 1)]
+    calls.clear()
+    V1 = synth.gaussian((8,) + (4, 4, 4, 4) + (12,), 1702)
+    p3 = dd.default_params(levels=3, block=[(2, 2, 2, 2), (2, 2, 2, 2)], nvec=[6, 8], setup_iters=1,
+                           coarse_setup_iters=2, precision="fp32")
+    ctx.setup(p3, [V0, V1])
+    assert calls == [(0, 0, 0), (0, 1, 0), (1, 1, 0), (1, 1, 1), (1, 0, 0)]
+    calls.clear()
+    ctx.set_progress(None)
+    ctx.setup(p, [V0])
+    assert calls == []
+    ctx.close()
