@@ -66,6 +66,11 @@ def assemble(st: Stencil, Q, bsize, mu_c: float) -> Stencil:
     Qd = _dag(Qs)
     coords = np.indices(dims)
     S_site = Qd @ st.S @ Qs
+    dmu = getattr(st, "dmu", None)
+    if dmu is not None:
+        # the site-dependent part of the twist, i dmu(x) Gamma5, enters the
+        # coarse site term as its Galerkin product (mu_c carries the mean)
+        S_site = S_site + 1j * dmu[..., None, None] * (Qd @ (st.g5[:, None] * Qs))
     X = np.zeros_like(S_site)
     Fc = []
     for mu in range(4):
@@ -78,9 +83,10 @@ def assemble(st: Stencil, Q, bsize, mu_c: float) -> Stencil:
     return Stencil(Sc, np.stack(Fc), mu_c)
 
 
-def brute_force(level_op, Q, bsize, mu_c: float):
+def brute_force(level_op, Q, bsize, mu_c):
     """Dense P^dag D(mu_c) P by applying D to every prolongated coarse unit
-    vector (tiny lattices only)."""
+    vector (tiny lattices only); mu_c None applies the operator's own twist
+    (which may differ between the parities)."""
     dims = level_op.dims
     Nv = Q.shape[0]
     cd = agg.coarse_dims(dims, bsize)

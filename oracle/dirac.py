@@ -165,23 +165,45 @@ class WilsonClover:
     U      links [T,Z,Y,X,4,3,3]
     kappa  hopping parameter (m0 = 1/(2 kappa) - 4)
     csw    clover coefficient (ignored if `clover` is given)
-    mu     twisted mass (mass normalisation)
+    mu     twisted mass (mass normalisation); with mu_odd, the twist of the
+           even sites
     clover optional clover term [T,Z,Y,X,2,6,6] (A only, without m0+4)
     theta  optional boundary phases; the clover term is built from the
            unphased links (closed loops do not see the phases)
+    mu_odd optional twist of the odd sites (Sec. 2: the library takes a
+           different twisted mass on even and odd sites, which the Hasenbusch
+           terms of Sec. 3.1 need): D = D_W + i mu(x) Gamma5 with mu(x) = mu
+           on even and mu_odd on odd sites (parity of the coordinate sum).
+           An explicit `mu` argument of the methods below overrides the
+           twist with that one value on every site.
     """
 
-    def __init__(self, U, kappa: float, csw: float, mu: float, clover=None, theta=None):
+    def __init__(self, U, kappa: float, csw: float, mu: float, clover=None, theta=None, mu_odd=None):
         self.U = np.asarray(U, dtype=np.complex128)
         self.dims = self.U.shape[:4]
         self.m0 = m0_from_kappa(kappa)
         self.mu = float(mu)
+        self.mu_odd = None if mu_odd is None else float(mu_odd)
         if clover is None:
             self.A = clover_matrix(self.U, csw)
         else:
             self.A = clover_from_blocks(np.asarray(clover, dtype=np.complex128))
         if theta is not None:
             self.U = boundary_phase_links(self.U, theta)
+
+    # --- twist ----------------------------------------------------------------
+    def twist(self, mu=None):
+        """The twisted mass of every site: the given value, the one twist, or
+        with mu_odd the field mu(x) [T,Z,Y,X]."""
+        if mu is not None:
+            return float(mu)
+        if self.mu_odd is None:
+            return self.mu
+        return self.mu + (self.mu_odd - self.mu) * odd_mask(self.dims)
+
+    def mean_twist(self) -> float:
+        """(mu_even + mu_odd) / 2: the twist the coarse levels carry."""
+        return self.mu if self.mu_odd is None else 0.5 * (self.mu + self.mu_odd)
 
     # --- pieces -------------------------------------------------------------
     def hop(self, psi):
@@ -196,16 +218,18 @@ class WilsonClover:
 
     def site(self, psi, mu=None):
         """T(x) psi(x) = (m0+4) psi + A psi + i mu gamma5 psi."""
-        mu = self.mu if mu is None else mu
+        t = self.twist(mu)
+        t = t[..., None, None] if np.ndim(t) else t
         flat = psi.reshape(psi.shape[:-2] + (12,))
         a = np.einsum("...ij,...j->...i", self.A, flat).reshape(psi.shape)
-        return (self.m0 + 4.0) * psi + a + 1j * mu * spin_mul(GAMMA5, psi)
+        return (self.m0 + 4.0) * psi + a + 1j * t * spin_mul(GAMMA5, psi)
 
     def site_matrix(self, mu=None):
         """T(x) as a 12x12 matrix per site."""
-        mu = self.mu if mu is None else mu
+        t = self.twist(mu)
+        t = t[..., None, None] if np.ndim(t) else t
         g5 = np.kron(GAMMA5, np.eye(3))
-        return self.A + (self.m0 + 4.0) * np.eye(12) + 1j * mu * g5
+        return self.A + (self.m0 + 4.0) * np.eye(12) + 1j * t * g5
 
     def site_inv(self, psi, mu=None):
         """T(x)^{-1} psi(x) by a direct solve per site."""

@@ -30,6 +30,14 @@ Readings taken where the paper is silent (all tunable, all recorded):
       D_c,2 = P_2^dag D_c,1 P_2 with the current P_2, followed by
       coarse_setup_iters level-1 iterations (w_j <- V-cycle_1(w_j), rebuild).
   * the setup uses +mu; D(-mu) reuses it with every twist negated (Sec. 1).
+  * different twists on even and odd sites (Sec. 2, needed by the Hasenbusch
+    terms of Sec. 3.1): the fine level applies each site's own twist; the
+    coarse operators are the Galerkin products of the full operator, with the
+    mean of the two twists as their i mu_c Gamma5,c term (delta times the
+    mean on the coarsest level) and the rest, i (mu(x) - mean) Gamma5 summed
+    over each aggregate, in their site blocks.  The paper defines delta for a
+    single twist only; reading: delta raises the mean, the parity rest enters
+    unscaled.
 """
 from __future__ import annotations
 
@@ -158,7 +166,7 @@ class Hierarchy:
         """Adaptive setup.  init_vectors[l] = random starting vectors for the
         interpolation from level l to l+1 ([Nv_l, level-l field shape])."""
         p = self.p
-        mu = self.fine_op.mu
+        mu = self.fine_op.mean_twist()  # coarse levels carry the mean twist
         zero = None
         # initial phase, level by level
         for l in range(p.levels - 1):
@@ -192,7 +200,7 @@ class Hierarchy:
         """Build the hierarchy directly from given test vectors (no setup
         iterations): vecs[l] are the raw vectors of level l."""
         p = self.p
-        mu = self.fine_op.mu if mu is None else mu
+        mu = self.fine_op.mean_twist() if mu is None else mu
         for l in range(p.levels - 1):
             L = self.levels[l]
             L.bsize = tuple(p.blocks[l])
@@ -207,6 +215,8 @@ class Hierarchy:
         h = Hierarchy.__new__(Hierarchy)
         h.p = self.p
         fo = self.fine_op
+        if getattr(fo, "mu_odd", None) is not None:
+            raise NotImplementedError("different twists on the two parities: build a hierarchy per operator")
         new_fine = object.__new__(type(fo))
         new_fine.__dict__.update(fo.__dict__)
         new_fine.mu = mu

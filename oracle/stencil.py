@@ -36,16 +36,27 @@ def _mv(M, y):
 
 
 class Stencil:
-    def __init__(self, S, F, mu: float):
+    """dmu (optional, [T,Z,Y,X] real): a site-dependent addition to the twist,
+    i (mu + dmu(x)) Gamma5 (the fine level with different twists on the two
+    parities: mu their mean, dmu = -+ half their difference).  An explicit
+    `mu` argument of the methods below drops it."""
+
+    def __init__(self, S, F, mu: float, dmu=None):
         self.S = np.asarray(S, dtype=np.complex128)
         self.F = np.asarray(F, dtype=np.complex128)
         self.dims = self.S.shape[:4]
         self.n = self.S.shape[-1]
         self.mu = float(mu)
+        self.dmu = None if dmu is None else np.asarray(dmu, dtype=np.float64)
         self.g5 = gamma5_diag(self.n)
 
     def with_mu(self, mu: float) -> "Stencil":
         return Stencil(self.S, self.F, mu)
+
+    def _twist(self, mu):
+        if mu is not None or self.dmu is None:
+            return self.mu if mu is None else mu
+        return (self.mu + self.dmu)[..., None]
 
     def backward_block(self, mu: int):
         """B_mu(x) = Gamma5 F_mu(x-mu)^dag Gamma5, coupling x to x-mu."""
@@ -53,12 +64,11 @@ class Stencil:
         return self.g5[:, None] * _dag(Fb) * self.g5[None, :]
 
     def site(self, y, mu=None):
-        mu = self.mu if mu is None else mu
-        return _mv(self.S, y) + 1j * mu * self.g5 * y
+        return _mv(self.S, y) + 1j * self._twist(mu) * self.g5 * y
 
     def site_matrix(self, mu=None):
-        mu = self.mu if mu is None else mu
-        return self.S + 1j * mu * np.diag(self.g5)
+        t = self._twist(mu)
+        return self.S + 1j * (t[..., None] if np.ndim(t) else t) * np.diag(self.g5)
 
     def site_inv(self, y, mu=None):
         return np.linalg.solve(self.site_matrix(mu), y[..., None])[..., 0]
@@ -87,14 +97,17 @@ class Stencil:
 
 def wilson_stencil(op: "dirac.WilsonClover") -> Stencil:
     """The fine operator written as a 12x12 block stencil:
-    S(x) = (m0+4) + A(x), F_mu(x) = -1/2 (1 - gamma_mu) (x) U_mu(x)."""
+    S(x) = (m0+4) + A(x), F_mu(x) = -1/2 (1 - gamma_mu) (x) U_mu(x); the twist
+    as its mean over the parities plus the site-dependent rest."""
     dims = op.dims
     S = op.A + (op.m0 + 4.0) * np.eye(12)
     F = np.zeros((4,) + dims + (12, 12), dtype=np.complex128)
     for mu in range(4):
         P = -0.5 * (np.eye(4) - dirac.GAMMA[mu])
         F[mu] = np.einsum("st,...ab->...satb", P, op.U[..., mu, :, :]).reshape(dims + (12, 12))
-    return Stencil(S, F, op.mu)
+    mean = op.mean_twist()
+    dmu = None if op.mu_odd is None else op.twist() - mean
+    return Stencil(S, F, mean, dmu)
 
 
 class FineLevel:
