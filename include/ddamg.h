@@ -152,8 +152,22 @@ int ddamg_set_clover(ddamg_ctx* ctx, const void* clover, int on_device);
 int ddamg_get_clover(ddamg_ctx* ctx, void* clover);
 /* Change mu for every later solve, keeping the setup (Sec. 1: the same setup
  * serves D(+mu) and D(-mu)); coarse twists are rescaled (delta on the
- * coarsest level). */
+ * coarsest level).  Sets the same twist on both parities. */
 int ddamg_set_mu(ddamg_ctx* ctx, double mu);
+/* Different twisted masses on even and odd sites (Sec. 2 lists this among the
+ * library's features; the Hasenbusch terms of Sec. 3.1 need it):
+ * D = D_W + i mu(x) Gamma5 with mu(x) = mu_even on even and mu_odd on odd
+ * sites (parity of the global coordinate sum), for ddamg_apply_dirac, the
+ * SAP entry points and every later setup and solve.  A current setup keeps
+ * its P on every level; its coarse operators become the Galerkin products of
+ * the new operator: each level's i mu_c Gamma5,c term carries the mean
+ * (mu_even + mu_odd)/2 (delta times it on the coarsest level), and the rest,
+ * i (mu(x) - mean) Gamma5 summed over each aggregate, enters the coarse site
+ * blocks.  When that rest changes, the coarse operators are assembled again
+ * from the kept P (about the cost of one Galerkin assembly); otherwise only
+ * the twists change.  ddamg_set_mu(mu) is ddamg_set_mu_eo(mu, mu).
+ * INVALID_ARG for non-finite twists. */
+int ddamg_set_mu_eo(ddamg_ctx* ctx, double mu_even, double mu_odd);
 
 /* Adaptive setup (Sec. 1; setup_iters / coarse_setup_iters of Listing 1).
  * init_vectors[l] (l < levels-1) holds the random starting test vectors of
@@ -242,7 +256,10 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
  * pair, Gamma5hat Dhat(-mu) Gamma5hat - i rho Gamma5hat, is this solve after
  * ddamg_set_mu(-mu) with -rho and Gamma5 b, followed by Gamma5 on x.  Stops
  * at a true relative residual <= tol of the full system; NOT_CONVERGED, the
- * other errors and st as for ddamg_solve. */
+ * other errors and st as for ddamg_solve.  INVALID_ARG when the two parities
+ * carry different twists (ddamg_set_mu_eo): the same system with a hierarchy
+ * built for it is ddamg_set_mu_eo(mu, mu + rho) followed by ddamg_solve on
+ * (0, b_o). */
 int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, double tol, ddamg_stats* st,
                             int on_device);
 /* out = D(sign*mu) in, full lattice (Sec. 1); precision FP64 or FP32 (and

@@ -228,6 +228,7 @@ int ddamg_create(const int dims[4], const int block[4], double kappa, double csw
     c.kappa = kappa;
     c.csw = csw;
     c.mu = mu;
+    c.mu_odd = mu;
     c.m0 = 1.0 / (2.0 * kappa) - 4.0;
     double tab[6 * 2 * 4 * 2];
     sigma_table(tab);
@@ -381,8 +382,23 @@ int ddamg_set_mu(ddamg_ctx* ctx, double mu) {
     Ctx& c = ctx->c;
     if (!std::isfinite(mu)) throw Error(INVALID_ARG, "mu must be finite");
     c.mu = mu;
+    c.mu_odd = mu;
     if (c.have_gauge) c.rebuild_odd_inverse();
-    if (c.mg) c.mg->set_mu(mu);
+    if (c.mg) c.mg->set_twist(c.twist());
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_set_mu_eo(ddamg_ctx* ctx, double mu_even, double mu_odd) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    if (!std::isfinite(mu_even) || !std::isfinite(mu_odd)) throw Error(INVALID_ARG, "twists must be finite");
+    c.mu = mu_even;
+    c.mu_odd = mu_odd;
+    if (c.have_gauge) c.rebuild_odd_inverse();
+    if (c.mg) c.mg->set_twist(c.twist());
     c.sync();
     return DDAMG_OK;
   });
@@ -425,7 +441,7 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
     long N = c.fine_len();
     c.f64c.ensure(sizeof(cx<double>) * N);
     std::function<void(const cx<double>*, cx<double>*)> A = [&c](const cx<double>* in, cx<double>* out) {
-      c.dirac64(in, out, c.mu);
+      c.dirac64(in, out, c.twist());
     };
     std::function<void(const cx<double>*, cx<double>*)> M = [&c](const cx<double>* in, cx<double>* out) {
       c.mg->precond(in, out);
@@ -449,7 +465,7 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
       bK.alloc(sizeof(cx<double>) * N * Kb, true);
       xK.alloc(sizeof(cx<double>) * N * Kb, true);
       OpM<double> AK = [&c, N](const cx<double>* in, cx<double>* out, int K) {
-        for (int k = 0; k < K; ++k) c.dirac64(in + k * N, out + k * N, c.mu);
+        for (int k = 0; k < K; ++k) c.dirac64(in + k * N, out + k * N, c.twist());
       };
       OpM<double> MK = [&c](const cx<double>* in, cx<double>* out, int K) { c.mg->precond_multi(in, out, K); };
       OpMf MKf = [&c](const cx<double>* in, cx<float>* out, int K) { c.mg->precond_multi_f32(in, out, K); };
@@ -527,6 +543,8 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
     if (!b || !x) throw Error(INVALID_ARG, "bad right-hand side arguments");
     if (!(tol > 0) || !std::isfinite(tol)) throw Error(INVALID_ARG, "tol must be > 0");
     if (!std::isfinite(rho)) throw Error(INVALID_ARG, "rho must be finite");
+    if (c.mu_odd != c.mu)
+      throw Error(INVALID_ARG, "the odd-shifted solve starts from one twist on both parities (ddamg_set_mu)");
     auto t0 = std::chrono::steady_clock::now();
     const long N = c.fine_len();
     c.f64c.ensure(sizeof(cx<double>) * N);
@@ -535,7 +553,7 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
     // level (restored on return)
     const double mu0 = c.mu;
     std::function<void(const cx<double>*, cx<double>*)> A = [&c, mu0, rho](const cx<double>* in, cx<double>* out) {
-      c.dirac64(in, out, mu0);
+      c.dirac64(in, out, Twist(mu0));
       launch_odd_twist_add(c.g, in, out, rho, c.st);
     };
     struct TwistScope {
@@ -544,9 +562,9 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
       bool on;
       void restore() {
         on = false;
-        c.mu = mu0;
+        c.mu = c.mu_odd = mu0;
         c.rebuild_odd_inverse();
-        c.mg->set_mu(mu0);
+        c.mg->set_twist(c.twist());
         c.sync();
       }
       // on an error path the solve's own error is the one reported
@@ -559,9 +577,9 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
       }
     } scope{c, mu0, rho != 0.0};
     if (rho != 0.0) {
-      c.mu = mu0 + 0.5 * rho;
+      c.mu = c.mu_odd = mu0 + 0.5 * rho;
       c.rebuild_odd_inverse();
-      c.mg->set_mu(c.mu);
+      c.mg->set_twist(c.twist());
     }
     std::function<void(const cx<double>*, cx<double>*)> M = [&c](const cx<double>* in, cx<double>* out) {
       c.mg->precond(in, out);
@@ -605,7 +623,7 @@ int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int p
     Ctx& c = ctx->c;
     need_gauge(c);
     if (!in || !out) throw Error(INVALID_ARG, "NULL field");
-    double tw = sign < 0 ? -c.mu : c.mu;
+    const Twist tw = c.twist(sign);
     long N = c.fine_len();
     c.upload_fine(in, on_device, c.f64a.as<cx<double>>());
     if (precision == DDAMG_FP64) {
@@ -659,7 +677,7 @@ int ddamg_sap_multi(ddamg_ctx* ctx, int nfields, const void* b, void* x, int ite
     if (precision == DDAMG_FP64) {
       for (int it = 0; it < iters; ++it)
         for (int col = 0; col < 2; ++col)
-          launch_sap_multi<double, double>(c.g, col, c.U64.p, c.H64.as<double>(), c.M64.as<double>(), c.mu,
+          launch_sap_multi<double, double>(c.g, col, c.U64.p, c.H64.as<double>(), c.M64.as<double>(), c.twist(),
                                            b64.as<cx<double>>(), x64.as<cx<double>>(), mr_steps, K, N, c.st);
     } else {
       c.ensure_32();
@@ -676,13 +694,13 @@ int ddamg_sap_multi(ddamg_ctx* ctx, int nfields, const void* b, void* x, int ite
       for (int it = 0; it < iters; ++it)
         for (int col = 0; col < 2; ++col) {
           if (precision == DDAMG_FP32)
-            launch_sap_multi<float, float>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.mu,
+            launch_sap_multi<float, float>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.twist(),
                                            b32.as<cx<float>>(), x32.as<cx<float>>(), mr_steps, K, N, c.st);
           else if (precision == DDAMG_FP16)
-            launch_sap_multi<float, f16>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.mu,
+            launch_sap_multi<float, f16>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.twist(),
                                          b32.as<cx<float>>(), x32.as<cx<float>>(), mr_steps, K, N, c.st);
           else
-            launch_sap_multi<float, bf16>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.mu,
+            launch_sap_multi<float, bf16>(c.g, col, U, c.H32.as<float>(), c.M32.as<float>(), c.twist(),
                                           b32.as<cx<float>>(), x32.as<cx<float>>(), mr_steps, K, N, c.st);
         }
       launch_copy_cvt<float, double>(x32.as<cx<float>>(), x64.as<cx<double>>(), N * K, c.st);
@@ -855,7 +873,7 @@ int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply) {
       for (int i = 0; i < napply; ++i) {
         const cx<double>* in = (i & 1) ? c.f64b.as<cx<double>>() : c.f64a.as<cx<double>>();
         cx<double>* out = (i & 1) ? c.f64a.as<cx<double>>() : c.f64b.as<cx<double>>();
-        c.dirac64(in, out, c.mu);
+        c.dirac64(in, out, c.twist());
       }
       return DDAMG_OK;
     }
@@ -872,9 +890,9 @@ int ddamg_bench_dirac(ddamg_ctx* ctx, int precision, int napply) {
       cx<float>* out = (i & 1) ? c.f32a.as<cx<float>>() : c.f32b.as<cx<float>>();
       hipEvent_t a;
       c.timer.begin(4, &a);
-      if (precision == DDAMG_FP32) launch_dirac<float, float>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
-      else if (precision == DDAMG_FP16) launch_dirac<float, f16>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
-      else launch_dirac<float, bf16>(c.g, U, c.H32.as<float>(), c.mu, in, out, c.st);
+      if (precision == DDAMG_FP32) launch_dirac<float, float>(c.g, U, c.H32.as<float>(), c.twist(), in, out, c.st);
+      else if (precision == DDAMG_FP16) launch_dirac<float, f16>(c.g, U, c.H32.as<float>(), c.twist(), in, out, c.st);
+      else launch_dirac<float, bf16>(c.g, U, c.H32.as<float>(), c.twist(), in, out, c.st);
       c.timer.end(4, a);
     }
     return DDAMG_OK;
@@ -936,7 +954,7 @@ int ddamg_error_reduction(ddamg_ctx* ctx, const void* e0, int on_device, int n, 
     const double n0 = norm();
     if (!(n0 > 0)) throw Error(INVALID_ARG, "the probe vector is zero");
     for (int i = 0; i < n; ++i) {  // e <- (I - M D) e
-      c.dirac64(ep, t.as<cx<double>>(), c.mu);
+      c.dirac64(ep, t.as<cx<double>>(), c.twist());
       c.mg->precond(t.as<cx<double>>(), z.as<cx<double>>());
       launch_sub<double>(N, ep, z.as<cx<double>>(), ep, c.st);
     }

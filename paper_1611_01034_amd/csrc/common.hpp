@@ -118,6 +118,27 @@ template <> __device__ __forceinline__ b2 st_cvt<bf16, double>(cx<double> v) {
 // and the components of one site are a compile-time stride apart, so one
 // address plus immediate offsets serves a whole site.
 constexpr int TILE = 8;
+
+// Twisted mass of the fine site terms: e on the even sites, o on the odd ones
+// (the same value on both unless the operator carries a different twist on
+// each parity).  TwistR is its copy in a kernel's arithmetic.
+struct Twist {
+  double e = 0, o = 0;
+  Twist() = default;
+  Twist(double t) : e(t), o(t) {}
+  Twist(double te, double to) : e(te), o(to) {}
+  Twist operator-() const { return Twist(-e, -o); }
+  double mean() const { return 0.5 * (e + o); }
+  double half_diff() const { return 0.5 * (o - e); }
+};
+template <class R>
+struct TwistR {
+  R e, o;
+  TwistR() = default;
+  __host__ __device__ TwistR(R te, R to) : e(te), o(to) {}
+  __host__ explicit TwistR(const Twist& t) : e((R)t.e), o((R)t.o) {}
+};
+
 struct Geom {
   int L[4];      // extents T,Z,Y,X
   int b[4];      // block extents
@@ -198,6 +219,17 @@ __host__ __device__ __forceinline__ void neighbour(const Geom& g, int B, int s, 
 __host__ __device__ __forceinline__ int xcd_remap(int w, int nwg) {
   int q = nwg >> 3, r = nwg & 7, x = w & 7, k = w >> 3;
   return x * q + (x < r ? x : r) + k;
+}
+
+// Workgroup -> lattice block for whole-lattice stencils.  The dispatcher
+// hands workgroup w to XCD w % 8; here each group of m consecutive blocks
+// (in block order) runs on one XCD, its blocks dispatched 8 workgroups apart,
+// while the 8 XCDs work on neighbouring groups at the same time.  Halos inside
+// a group meet in the XCD's L2, halos between groups in the shared
+// last-level cache.  Needs nwg divisible by 8m (a bijection of [0, nwg)).
+__host__ __device__ __forceinline__ int group_remap(int w, int m) {
+  const int x = w & 7, r = (w >> 3) % m, i = w / (8 * m);
+  return i * 8 * m + x * m + r;
 }
 
 // index of component 0 of slot s of block B, field with C components

@@ -6,17 +6,19 @@
 namespace ddamg {
 
 // ---------------------------------------------------------------------------
-// D(tw) psi, full lattice.  One workgroup per lattice block, one work-item per
+// D(tw) psi, full lattice (tw: the twist of each parity).  One workgroup per lattice block, one work-item per
 // site; the block's input spinors are staged in LDS, so only hops that leave
-// the block read neighbours from global memory.  Workgroups are remapped so
-// each XCD sweeps a contiguous range of blocks.
+// the block read neighbours from global memory.  With gm > 0 each XCD takes
+// groups of gm consecutive blocks (two rows of blocks along X) while the XCDs
+// sweep neighbouring groups together (group_remap); else each XCD sweeps one
+// contiguous range of blocks (xcd_remap).
 template <class R, class S>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 3, 8)))
-k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H, R tw,
+k_dirac(Geom g, int gm, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H, TwistR<R> tw,
         const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
   extern __shared__ char smem_raw[];
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x bs, parity-split
-  const int B = xcd_remap(blockIdx.x, gridDim.x), s = threadIdx.x;
+  const int B = gm > 0 ? group_remap(blockIdx.x, gm) : xcd_remap(blockIdx.x, gridDim.x), s = threadIdx.x;
   SiteNbr me;
   me_of(g, B, s, me);
   cx<R> psi[12], acc[12];
@@ -30,18 +32,19 @@ k_dirac(Geom g, const typename store_traits<S>::elem* __restrict__ U, const R* _
 }
 
 template <class R, class S>
-void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<R>* in, cx<R>* out, hipStream_t st) {
+void launch_dirac(const Geom& g, const void* U, const R* H, Twist tw, const cx<R>* in, cx<R>* out, hipStream_t st) {
   size_t sm = 12 * (size_t)g.bs * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_dirac<R, S>), dim3(g.nblocks), dim3(g.bs), sm, st, g,
-                     (const typename store_traits<S>::elem*)U, H, (R)tw, in, out);
+  const int gm = g.nblocks % (16 * g.nb[3]) == 0 ? 2 * g.nb[3] : 0;
+  hipLaunchKernelGGL((k_dirac<R, S>), dim3(g.nblocks), dim3(g.bs), sm, st, g, gm,
+                     (const typename store_traits<S>::elem*)U, H, TwistR<R>(tw), in, out);
 }
-template void launch_dirac<double, double>(const Geom&, const void*, const double*, double, const cx<double>*,
+template void launch_dirac<double, double>(const Geom&, const void*, const double*, Twist, const cx<double>*,
                                            cx<double>*, hipStream_t);
-template void launch_dirac<float, float>(const Geom&, const void*, const float*, double, const cx<float>*,
+template void launch_dirac<float, float>(const Geom&, const void*, const float*, Twist, const cx<float>*,
                                          cx<float>*, hipStream_t);
-template void launch_dirac<float, f16>(const Geom&, const void*, const float*, double, const cx<float>*,
+template void launch_dirac<float, f16>(const Geom&, const void*, const float*, Twist, const cx<float>*,
                                           cx<float>*, hipStream_t);
-template void launch_dirac<float, bf16>(const Geom&, const void*, const float*, double,
+template void launch_dirac<float, bf16>(const Geom&, const void*, const float*, Twist,
                                                   const cx<float>*, cx<float>*, hipStream_t);
 
 }  // namespace ddamg

@@ -98,7 +98,7 @@ __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::el
 template <class R, class S>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 1 : 2, 8)))
 k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, const R* __restrict__ H,
-      const R* __restrict__ Minv, R tw, const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr, int K,
+      const R* __restrict__ Minv, TwistR<R> tw, const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr, int K,
       long ld) {
   extern __shared__ char smem_raw[];
   cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x half, even slots
@@ -236,32 +236,32 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
 }
 
 template <class R, class S>
-void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, Twist tw, const cx<R>* b,
                 cx<R>* x, int n_mr, hipStream_t st) {
   launch_sap_multi<R, S>(g, colour, U, H, Minv, tw, b, x, n_mr, 1, 0, st);
 }
 template <class R, class S>
-void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, Twist tw, const cx<R>* b,
                       cx<R>* x, int n_mr, int K, long ld, hipStream_t st) {
   size_t sm = 2 * 12 * (size_t)g.half * sizeof(cx<R>);
   hipLaunchKernelGGL((k_sap<R, S>), dim3((g.nblocks / 2) * K), dim3(g.half), sm, st, g, colour,
-                     (const typename store_traits<S>::elem*)U, H, Minv, (R)tw, b, x, n_mr, K, ld);
+                     (const typename store_traits<S>::elem*)U, H, Minv, TwistR<R>(tw), b, x, n_mr, K, ld);
 }
-template void launch_sap_multi<double, double>(const Geom&, int, const void*, const double*, const double*, double,
+template void launch_sap_multi<double, double>(const Geom&, int, const void*, const double*, const double*, Twist,
                                                const cx<double>*, cx<double>*, int, int, long, hipStream_t);
-template void launch_sap_multi<float, float>(const Geom&, int, const void*, const float*, const float*, double,
+template void launch_sap_multi<float, float>(const Geom&, int, const void*, const float*, const float*, Twist,
                                              const cx<float>*, cx<float>*, int, int, long, hipStream_t);
-template void launch_sap_multi<float, f16>(const Geom&, int, const void*, const float*, const float*, double,
+template void launch_sap_multi<float, f16>(const Geom&, int, const void*, const float*, const float*, Twist,
                                            const cx<float>*, cx<float>*, int, int, long, hipStream_t);
-template void launch_sap_multi<float, bf16>(const Geom&, int, const void*, const float*, const float*, double,
+template void launch_sap_multi<float, bf16>(const Geom&, int, const void*, const float*, const float*, Twist,
                                             const cx<float>*, cx<float>*, int, int, long, hipStream_t);
-template void launch_sap<double, double>(const Geom&, int, const void*, const double*, const double*, double,
+template void launch_sap<double, double>(const Geom&, int, const void*, const double*, const double*, Twist,
                                          const cx<double>*, cx<double>*, int, hipStream_t);
-template void launch_sap<float, float>(const Geom&, int, const void*, const float*, const float*, double,
+template void launch_sap<float, float>(const Geom&, int, const void*, const float*, const float*, Twist,
                                        const cx<float>*, cx<float>*, int, hipStream_t);
-template void launch_sap<float, f16>(const Geom&, int, const void*, const float*, const float*, double,
+template void launch_sap<float, f16>(const Geom&, int, const void*, const float*, const float*, Twist,
                                         const cx<float>*, cx<float>*, int, hipStream_t);
-template void launch_sap<float, bf16>(const Geom&, int, const void*, const float*, const float*, double,
+template void launch_sap<float, bf16>(const Geom&, int, const void*, const float*, const float*, Twist,
                                                 const cx<float>*, cx<float>*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -913,7 +913,7 @@ __device__ __forceinline__ void half_hop(int hb, const cx<RQ> p6[6], const cx<T>
 
 template <class RQ, class T, int CS, int NG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4, 8)))
-k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* __restrict__ H,
+k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* __restrict__ H, double dtw,
                 const cx<RQ>* __restrict__ Q, long qstride, const int* __restrict__ f2c, cx<double>* __restrict__ Dc,
                 cx<double>* __restrict__ Xs) {
   using MF = mfma_k4<T>;
@@ -977,6 +977,13 @@ k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* 
 #pragma unroll
           for (int c = 0; c < 6; ++c) psi[c] = qs[xs][6 * hb + c][j];
           herm_mv(&hs[xs][36 * hb], 1, psi, hy);
+          if (dtw != 0) {
+            // the parity rest of the twist, i d(x) Gamma5 with d = -+ dtw on
+            // even / odd sites (Gamma5 = -1 on chirality 0, +1 on chirality 1)
+            const T d = (T)((x0 + xs >= g.half) == (hb == 1) ? dtw : -dtw);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) hy[c] += mk<T>(-d * psi[c].im, d * psi[c].re);
+          }
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
             y[c] = hb == 0 ? hy[c] : mk<T>(0, 0);
@@ -1050,8 +1057,8 @@ k_assemble_fine(Geom g, int Nv, const cx<double>* __restrict__ U, const double* 
   }
 }
 template <class RQ>
-void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, const cx<RQ>* Q, long qstride,
-                          const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st) {
+void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, double dtw, const cx<RQ>* Q,
+                          long qstride, const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st) {
   if (Nv < 1 || Nv > 32) throw Error(INVALID_ARG, "assembly: nvec must be in [1, 32]");
   // The Galerkin products are formed and summed in FP64 on the FP64 matrix
   // cores for both storage formats of the test vectors (FP32 vectors are
@@ -1060,15 +1067,15 @@ void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const doub
   constexpr int CS = 4, CS4 = 3;
   const dim3 grid(6 * g.nblocks), blk(256);
   switch ((2 * Nv + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 1>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
-    case 2: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 2>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
-    case 3: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 3>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
-    default: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS4, 4>), grid, blk, 0, st, g, Nv, U, H, Q, qstride, f2c, Dc, Xs); break;
+    case 1: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 1>), grid, blk, 0, st, g, Nv, U, H, dtw, Q, qstride, f2c, Dc, Xs); break;
+    case 2: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 2>), grid, blk, 0, st, g, Nv, U, H, dtw, Q, qstride, f2c, Dc, Xs); break;
+    case 3: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS, 3>), grid, blk, 0, st, g, Nv, U, H, dtw, Q, qstride, f2c, Dc, Xs); break;
+    default: hipLaunchKernelGGL((k_assemble_fine<RQ, T, CS4, 4>), grid, blk, 0, st, g, Nv, U, H, dtw, Q, qstride, f2c, Dc, Xs); break;
   }
 }
-template void launch_assemble_fine<double>(const Geom&, int, const cx<double>*, const double*, const cx<double>*,
+template void launch_assemble_fine<double>(const Geom&, int, const cx<double>*, const double*, double, const cx<double>*,
                                            long, const int*, cx<double>*, cx<double>*, hipStream_t);
-template void launch_assemble_fine<float>(const Geom&, int, const cx<double>*, const double*, const cx<float>*,
+template void launch_assemble_fine<float>(const Geom&, int, const cx<double>*, const double*, double, const cx<float>*,
                                           long, const int*, cx<double>*, cx<double>*, hipStream_t);
 
 // ---------------------------------------------------------------------------

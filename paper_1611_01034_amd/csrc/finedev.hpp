@@ -114,10 +114,11 @@ __device__ __forceinline__ void herm_mv(const R* hp, long stride, const cx<R> x[
     }
 }
 
-// T psi at (B,s): (m0+4+A) psi + i tw gamma5 psi
+// T psi at (B,s): (m0+4+A) psi + i tw gamma5 psi, tw the twist of the slot's parity
 template <class R>
-__device__ __forceinline__ void site_term(const R* H, const Geom& g, int B, int s, R tw, const cx<R> psi[12],
-                                          cx<R> out[12]) {
+__device__ __forceinline__ void site_term(const R* H, const Geom& g, int B, int s, TwistR<R> twp,
+                                          const cx<R> psi[12], cx<R> out[12]) {
+  const R tw = s < g.half ? twp.e : twp.o;
   const R* hp = H + fidx(g, B, s, 72);
   herm_mv(hp, TILE, psi, out);
   herm_mv(hp + 36L * TILE, TILE, psi + 6, out + 6);
@@ -132,8 +133,9 @@ __device__ __forceinline__ void site_term(const R* H, const Geom& g, int B, int 
 // (H is Hermitian, so (H + i a)^{-1} = (H - i a)(H^2 + a^2)^{-1}); chirality 0 has
 // the twist -i tw, chirality 1 +i tw.
 template <class R>
-__device__ __forceinline__ void site_inv(const R* H, const R* Minv, const Geom& g, int B, int s, R tw,
+__device__ __forceinline__ void site_inv(const R* H, const R* Minv, const Geom& g, int B, int s, TwistR<R> twp,
                                          const cx<R> psi[12], cx<R> out[12]) {
+  const R tw = twp.o;
   const R* hp = H + fidx(g, B, s, 72);
   const R* mp = Minv + oidx(g, B, s - g.half, 72);
   cx<R> t[12];

@@ -52,12 +52,12 @@ struct CGeom {
 
 // ---------------------------------------------------------------- fine level
 template <class R, class S>
-void launch_dirac(const Geom& g, const void* U, const R* H, double tw, const cx<R>* in, cx<R>* out, hipStream_t st);
+void launch_dirac(const Geom& g, const void* U, const R* H, Twist tw, const cx<R>* in, cx<R>* out, hipStream_t st);
 template <class R, class S>
-void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, Twist tw, const cx<R>* b,
                 cx<R>* x, int n_mr, hipStream_t st);
 template <class R, class S>
-void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, double tw, const cx<R>* b,
+void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, Twist tw, const cx<R>* b,
                       cx<R>* x, int n_mr, int K, long ld, hipStream_t st);
 template <class R>
 void launch_from_lex(const Geom& g, const cx<double>* lex, cx<R>* out, int ncomp, hipStream_t st);
@@ -98,8 +98,10 @@ template <class RI, class RO>
 void launch_qr_fine(const Geom& g, int Nv, const cx<RI>* V, long vstride, cx<RO>* Q, long qstride, int* fail,
                     hipStream_t st);
 template <class RQ>
-void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, const cx<RQ>* Q, long qstride,
-                          const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st);
+// dtw: half the difference of the odd- and even-site twists, whose parity
+// rest i (-+dtw) Gamma5 enters the coarse site blocks (0: one twist)
+void launch_assemble_fine(const Geom& g, int Nv, const cx<double>* U, const double* H, double dtw, const cx<RQ>* Q,
+                          long qstride, const int* f2c, cx<double>* Dc, cx<double>* Xs, hipStream_t st);
 template <class S>
 void launch_cvt_cx(long n, const cx<double>* in, void* out, hipStream_t st);
 void launch_cvt_real(long n, const double* in, float* out, hipStream_t st);

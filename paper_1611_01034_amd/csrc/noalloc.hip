@@ -66,7 +66,7 @@ extern "C" int ddamg_apply_dirac_noalloc(ddamg_ctx* ctx, const void* in, void* o
     cx<double>* b = a + kNoAllocMaxSites * 12;
     // every entry of the first V*12 of each half is written before it is read
     launch_from_lex<double>(c.g, (const cx<double>*)in, a, 12, c.st);
-    launch_dirac<double, double>(c.g, c.U64.p, c.H64.as<double>(), sign < 0 ? -c.mu : c.mu, a, b, c.st);
+    launch_dirac<double, double>(c.g, c.U64.p, c.H64.as<double>(), c.twist(sign), a, b, c.st);
     launch_to_lex<double>(c.g, b, (cx<double>*)out, 12, c.st);
     HIP_CHECK(hipGetLastError());
     return DDAMG_OK;

@@ -722,10 +722,10 @@ void Ctx::ensure_16(int kind) {
   u16_kind = kind;
 }
 void Ctx::rebuild_odd_inverse() {
-  launch_odd_inverse(g, H64.as<double>(), mu, M64.as<double>(), st);
+  launch_odd_inverse(g, H64.as<double>(), mu_odd, M64.as<double>(), st);
   if (have_32) launch_cvt_real((long)g.V * 36, M64.as<double>(), M32.as<float>(), st);
 }
-void Ctx::dirac64(const cx<double>* in, cx<double>* out, double tw) {
+void Ctx::dirac64(const cx<double>* in, cx<double>* out, Twist tw) {
   // spinor in and out, links and clover once: 1536 bytes per site
   TimeScope ts(timer, 0, 1536.0 * (double)g.V);
   launch_dirac<double, double>(g, U64.p, H64.as<double>(), tw, in, out, st);
@@ -879,7 +879,9 @@ struct MG : MGBase {
   DevBuf Vraw[3], Q[3];
   DevBuf D64[4], DS[4], Minvc, Xs, invscr;
   size_t xs_bytes = 0;  // assembly scratch (transient: taken per assembly, released after the setup)
-  double tw[4] = {0, 0, 0, 0};
+  double tw[4] = {0, 0, 0, 0};  // twist of each coarse level (tw[0]: the fine mean)
+  Twist tw0;                      // the fine level's twists
+  double dtw_asm = 0;             // parity rest of the fine twist in the coarse site blocks
   DevBuf fx, fb, fr;              // fine R vectors
   DevBuf rc[4], ec[4], wk[4][4];  // coarse vectors per level
   KrylovWS<R> kws[4];
@@ -946,7 +948,7 @@ struct MG : MGBase {
       Hf = c.H32.template as<float>();
       Mf = c.M32.template as<float>();
     }
-    set_twists(c.mu);
+    set_twists(c.twist());
     // allocations
     long fl = c.fine_len();
     fx.alloc(sizeof(cx<R>) * fl);
@@ -1005,7 +1007,11 @@ struct MG : MGBase {
     else return DS[l].p;
   }
 
-  void set_twists(double mu) {
+  // coarse levels carry the mean of the two fine twists (delta times it on the
+  // coarsest); the parity rest enters their site blocks through the assembly
+  void set_twists(const Twist& t) {
+    tw0 = t;
+    const double mu = t.mean();
     tw[0] = mu;
     for (int l = 1; l < L; ++l) tw[l] = (l == L - 1) ? p.coarse_mu_factor * mu : mu;
   }
@@ -1016,13 +1022,13 @@ struct MG : MGBase {
   // ---- level operations ----------------------------------------------------
   void fine_dirac(const cx<R>* in, cx<R>* out) {
     TimeScope ts(c.timer, 4);
-    launch_dirac<R, S>(c.g, U, Hf, tw[0], in, out, c.st);
+    launch_dirac<R, S>(c.g, U, Hf, tw0, in, out, c.st);
   }
   void fine_sap(const cx<R>* b, cx<R>* x, int iters, int nmr) {
     for (int it = 0; it < iters; ++it)
       for (int col = 0; col < 2; ++col) {
         TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, 1), sap_sweep_flops(c.g, 1, nmr));
-        launch_sap<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, c.st);
+        launch_sap<R, S>(c.g, col, U, Hf, Mf, tw0, b, x, nmr, c.st);
       }
   }
   // SAP on K fine fields (stride = fine length), one launch per colour
@@ -1030,7 +1036,7 @@ struct MG : MGBase {
     for (int it = 0; it < iters; ++it)
       for (int col = 0; col < 2; ++col) {
         TimeScope ts(c.timer, 1, sap_sweep_bytes<R, S>(c.g, K), sap_sweep_flops(c.g, K, nmr));
-        launch_sap_multi<R, S>(c.g, col, U, Hf, Mf, tw[0], b, x, nmr, K, c.fine_len(), c.st);
+        launch_sap_multi<R, S>(c.g, col, U, Hf, Mf, tw0, b, x, nmr, K, c.fine_len(), c.st);
       }
   }
   // SAP on K fields of an intermediate level: residuals of all fields in one
@@ -1342,8 +1348,15 @@ struct MG : MGBase {
     }
   }
 
-  void set_mu(double mu) override {
-    set_twists(mu);
+  void set_twist(const Twist& t) override {
+    set_twists(t);
+    if (t.half_diff() != dtw_asm) {
+      // the parity rest lives in the coarse site blocks: Galerkin again from
+      // the same P (this also rebuilds the coarsest odd-site inverses)
+      for (int l = 0; l < L - 1; ++l) assemble_next(l);
+      Xs.release();
+      return;
+    }
     CoarseGeo& G = *geos[L - 1];
     launch_coarse_odd_inverse<R>(G.cg(), D64[L - 1].template as<cx<double>>(), tw[L - 1],
                                  invscr.template as<cx<double>>(), Minvc.template as<cx<R>>(), c.st);
@@ -1409,7 +1422,8 @@ struct MG : MGBase {
     long len = level_len(l);
     CoarseGeo& Gn = *geos[l + 1];
     if (l == 0) {
-      launch_assemble_fine<R>(c.g, Nv[0], c.U64.template as<cx<double>>(), c.H64.template as<double>(),
+      dtw_asm = tw0.half_diff();
+      launch_assemble_fine<R>(c.g, Nv[0], c.U64.template as<cx<double>>(), c.H64.template as<double>(), dtw_asm,
                               Q[0].template as<cx<R>>(), len, f2c.template as<int>(), D64[1].template as<cx<double>>(),
                               Xs.template as<cx<double>>(), c.st);
     } else {

@@ -233,7 +233,9 @@ struct MGBase {
   virtual void precond_multi(const cx<double>* v, cx<double>* z, int K) = 0;
   // the same with FP32 output (reduced-precision hierarchies only)
   virtual void precond_multi_f32(const cx<double>* v, cx<float>* z, int K) = 0;
-  virtual void set_mu(double mu) = 0;
+  // new twists on every level from the same P: the coarse operators are
+  // assembled again when the parity rest of the fine twist changes
+  virtual void set_twist(const Twist& t) = 0;
   virtual int nlev() const = 0;
   virtual const CoarseGeo& geo(int l) const = 0;  // l >= 1
   virtual void get_interp(int l, cx<double>* host) = 0;
@@ -287,6 +289,7 @@ struct Ctx {
   int dev = 0;                 // HIP device current at ddamg_create
   Geom g{};
   double kappa = 0, csw = 0, mu = 0, m0 = 0;
+  double mu_odd = 0;           // twist of the odd sites (equal to mu unless set apart)
   double theta[4] = {0, 0, 0, 0};  // twisted boundary conditions (0: periodic)
   bool have_gauge = false, have_setup = false;
   DevBuf U64, H64, M64;        // fine operator, FP64
@@ -313,6 +316,8 @@ struct Ctx {
   void ensure_16(int kind);
   void rebuild_odd_inverse();
   void sync() { HIP_CHECK(hipStreamSynchronize(st)); }
+  // the fine operator's twists, both negated for sign < 0 (D(-mu))
+  Twist twist(int sign = 1) const { return sign < 0 ? Twist(-mu, -mu_odd) : Twist(mu, mu_odd); }
   // setup stage finished: wait for the stream, then tell the caller
   void progress(int stage, int level, int index) {
     if (!progress_fn) return;
@@ -320,7 +325,7 @@ struct Ctx {
     progress_fn(progress_user, stage, level, index);
   }
   // fine FP64 operator D(tw) in block layout
-  void dirac64(const cx<double>* in, cx<double>* out, double tw);
+  void dirac64(const cx<double>* in, cx<double>* out, Twist tw);
   // host/device lex FP64 field -> block layout
   void upload_fine(const void* src, int on_device, cx<double>* dst64);
   void download_fine(const cx<double>* src64, void* dst, int on_device);

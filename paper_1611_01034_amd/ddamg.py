@@ -96,6 +96,7 @@ _SIGS = {
     "ddamg_set_clover": (_i, [_vp, _vp, _i]),
     "ddamg_get_clover": (_i, [_vp, _vp]),
     "ddamg_set_mu": (_i, [_vp, _d]),
+    "ddamg_set_mu_eo": (_i, [_vp, _d, _d]),
     "ddamg_setup": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
     "ddamg_set_test_vectors": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
     "ddamg_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(Stats), _i]),
@@ -291,6 +292,10 @@ class DDAMG:
 
     def set_mu(self, mu):
         self._check(_lib.ddamg_set_mu(self._h, float(mu)))
+
+    def set_mu_eo(self, mu_even, mu_odd):
+        """Twisted mass mu_even on the even and mu_odd on the odd sites."""
+        self._check(_lib.ddamg_set_mu_eo(self._h, float(mu_even), float(mu_odd)))
 
     def _vec_ptrs(self, vecs):
         arrs = [_c128(v) for v in vecs]
