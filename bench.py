@@ -3,8 +3,9 @@ right-hand sides, mixed precision vs FP64, with the fine operator's D(mu) and
 the SAP smoother's bandwidth against the HBM roofline.
 
 One step = the whole hot path on one batch of synthetic input: the adaptive
-setup (learned initial test vectors, one refinement iteration, block QR,
-Galerkin coarse operators on every level) followed by the preconditioned
+setup (initial test vectors from Gaussian noise or from the learned network,
+one refinement iteration, block QR, Galerkin coarse operators on every level)
+followed by the preconditioned
 FGMRES solve of every right-hand side to a true relative residual <= 1e-10
 (lock-step groups of --rhs-batch).  Inputs (SU(3) links exp(i 0.3 H),
 Gaussian sources, network noise and level-1 test vectors, all seeded) are
@@ -15,6 +16,8 @@ generated on the device before the timed region.
 
 Prints one JSON line.  `value` is the mixed-precision step time in seconds
 (lower is better).  After the timed steps:
+  * one untimed step with the other initial test vectors (learned <-> random)
+    on the same inputs, when it fits --time-budget (`other_start`);
   * the plain FP64 form (random start, 5-iteration setup) runs once on the
     same right-hand sides when it fits --time-budget (seconds since start),
     else the line says it was skipped;
@@ -68,7 +71,12 @@ def parse():
     ap.add_argument("--restart", type=int, default=4,
                     help="outer FGMRES restart of the mixed form (its FP64 basis of restart+1 fields per "
                          "right-hand side is what bounds the lock-step group at 48^3x96)")
-    ap.add_argument("--learned", type=int, default=1)
+    ap.add_argument("--learned", type=int, default=0,
+                    help="1: the network proposes the initial test vectors; 0: Gaussian random vectors "
+                         "(the faster start at this roughness after one setup iteration; the other one is "
+                         "timed after the timed steps, see --alt-start)")
+    ap.add_argument("--alt-start", type=int, default=1,
+                    help="after the timed steps, one untimed step with the other initial vectors")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--time-budget", type=float, default=540.0,
                     help="seconds since start beyond which the FP64 leg is skipped")
@@ -268,7 +276,8 @@ def main():
         noise = synth.gaussian_device((C,) + dims + (4, 3), 5501, dtype="complex64")
         V0 = None
     else:
-        V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
+        # complex64, like the network's noise: the setup stores them in FP32 or lower
+        V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501, dtype="complex64")
     torch.cuda.synchronize()
 
     def make_ctx(Ug, net=False):
@@ -375,6 +384,51 @@ def main():
                "frac": round(a / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None, "algorithmic_flops": flops_s,
                "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_s,
                "launches": n_s, "avg_launch_ms": round(ms_s / n_s, 4)}
+
+    # the other initial test vectors (learned <-> random), one untimed step on
+    # the same right-hand sides, when the run's time budget allows it
+    alt = None
+    if args.alt_start:
+        elapsed = time.time() - T_START
+        other = "random" if args.learned else "learned"
+        if elapsed + 2.0 * dt > args.time_budget:
+            alt = {"start": other + f"+{args.setup_iters}",
+                   "note": f"skipped: {elapsed:.0f} s elapsed + about {2 * dt:.0f} s exceeds the "
+                           f"{args.time_budget:.0f} s budget of this run"}
+        else:
+            ctx.release_memory()
+            if args.learned:
+                noise = None
+                torch.cuda.empty_cache()
+                V0a = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501, dtype="complex64")
+            else:
+                from paper_1611_01034_amd import learned_setup
+                wts, C, L, _ = learned_setup.load_weights(learned_setup.WEIGHTS)
+                ctx.net_create(L, C)
+                ctx.net_set_params(wts)
+                V0 = None
+                torch.cuda.empty_cache()
+                noise_a = synth.gaussian_device((C,) + dims + (4, 3), 5501, dtype="complex64")
+            torch.cuda.synchronize()
+            t = time.time()
+            if args.learned:
+                ctx.setup(p_mixed, [V0a, V1])
+            else:
+                ctx.setup_learned(p_mixed, noise_a, V1)
+            _, st_a = ctx.solve(b, tol=1e-10, x=x)
+            torch.cuda.synchronize()
+            dt_a = time.time() - t
+            alt = {"start": other + f"+{args.setup_iters}", "step_s": round(dt_a, 3),
+                   "iters_per_rhs": round(st_a["iters"] / max(1, st_a["nrhs"]), 2),
+                   "iters_min": st_a["iters_min"], "iters_max": st_a["iters_max"], "resid": st_a["resid"],
+                   "note": "one untimed step after the timed ones, same inputs"}
+            log(f"other start ({other}): step {dt_a:.2f} s, {alt['iters_per_rhs']} iterations per rhs")
+            if args.learned:
+                del V0a
+            else:
+                del noise_a
+            ctx.release_memory()
+            torch.cuda.empty_cache()
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -391,9 +445,8 @@ def main():
                          f"{args.time_budget:.0f} s budget of this run")
             log("fp64:", fp64_note)
         else:
-            if args.learned:
-                del noise
-                torch.cuda.empty_cache()
+            noise = None
+            torch.cuda.empty_cache()
             V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
             U = synth.gauge_field_device(dims, 0.3, 5001)
             c64 = make_ctx(U)
@@ -476,6 +529,7 @@ def main():
         "fp64_stats": fp64_stats,
         "fp64_note": fp64_note,
         "speedup_mixed_vs_fp64": round(fp64_s / dt, 3) if fp64_s else None,
+        "other_start": alt,
         "kernel_ms": {k: {"launches": v[0], "ms": round(v[1], 2)} for k, v in kinds.items()},
     }
     print(json.dumps(out), flush=True)

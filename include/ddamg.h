@@ -187,6 +187,14 @@ int ddamg_setup(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_v
  * the same context.  INVALID_ARG for a NULL context. */
 typedef void (*ddamg_progress_fn)(void* user, int stage, int level, int index);
 int ddamg_set_progress(ddamg_ctx* ctx, ddamg_progress_fn fn, void* user);
+/* ddamg_setup with the fine level's initial vectors in a chosen precision:
+ * fine_precision DDAMG_FP64 (complex128, exactly ddamg_setup) or DDAMG_FP32
+ * (init_vectors[0] holds nvec[0] complex64 fields in the spinor layout, which
+ * halves what the caller keeps resident for them; the setup converts each to
+ * its own storage as it reads it).  Coarse-level vectors stay complex128.
+ * Errors as for ddamg_setup; INVALID_ARG for another precision. */
+int ddamg_setup_prec(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_vectors, int fine_precision,
+                     int on_device);
 /* Build the hierarchy directly from given test vectors (no smoothing, no
  * setup iteration): P from their block orthonormalisation, D_c by Galerkin
  * assembly.  Same shapes as ddamg_setup. */

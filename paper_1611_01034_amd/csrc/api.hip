@@ -426,6 +426,44 @@ static int do_build(ddamg_ctx* ctx, const ddamg_params* p, const void* const* ve
 int ddamg_setup(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_vectors, int on_device) {
   return do_build(ctx, p, init_vectors, on_device, true);
 }
+int ddamg_setup_prec(ddamg_ctx* ctx, const ddamg_params* p, const void* const* init_vectors, int fine_precision,
+                     int on_device) {
+  if (fine_precision == DDAMG_FP64) return do_build(ctx, p, init_vectors, on_device, true);
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    check_params(p);
+    if (fine_precision != DDAMG_FP32)
+      throw Error(INVALID_ARG, "fine initial vectors must be complex128 (DDAMG_FP64) or complex64 (DDAMG_FP32)");
+    if (!init_vectors || !init_vectors[0] || (p->levels == 3 && !init_vectors[1]))
+      throw Error(INVALID_ARG, "init vectors are NULL");
+    const long fl = c.fine_len();
+    c.have_setup = false;
+    c.mg.reset();
+    c.p = *p;
+    c.mg = make_mg(c);
+    c.lex.ensure(sizeof(cx<double>) * fl);
+    c.f64b.ensure(sizeof(cx<double>) * fl);
+    c.f32a.ensure(sizeof(cx<float>) * fl);
+    for (int i = 0; i < p->nvec[0]; ++i) {
+      // complex64 lexicographic -> FP64 lexicographic staging -> FP32 block layout
+      const cx<float>* src = (const cx<float>*)init_vectors[0] + (long)i * fl;
+      if (!on_device) {
+        HIP_CHECK(hipMemcpyAsync(c.f64b.p, src, sizeof(cx<float>) * fl, hipMemcpyHostToDevice, c.st));
+        src = c.f64b.as<cx<float>>();
+      }
+      launch_copy_cvt<float, double>(src, c.lex.as<cx<double>>(), fl, c.st);
+      launch_from_lex<float>(c.g, c.lex.as<cx<double>>(), c.f32a.as<cx<float>>(), 12, c.st);
+      c.mg->load_fine_vec(i, c.f32a.as<cx<float>>());
+    }
+    const void* vecs[3] = {nullptr, init_vectors[1], nullptr};
+    c.mg->build(vecs, on_device, true);
+    c.have_setup = true;
+    return DDAMG_OK;
+  });
+}
+
 int ddamg_set_test_vectors(ddamg_ctx* ctx, const ddamg_params* p, const void* const* vectors, int on_device) {
   return do_build(ctx, p, vectors, on_device, false);
 }

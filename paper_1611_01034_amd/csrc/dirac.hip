@@ -28,7 +28,14 @@ k_dirac(Geom g, int gm, const typename store_traits<S>::elem* __restrict__ U, co
   site_term(H, g, B, s, tw, psi, acc);
   __syncthreads();
   hop_staged<R, S>(U, in, lds, g, B, s, me, acc);
-  store_spinor(out, g, B, s, acc);
+  // streaming stores: the result is not read again by this sweep, so it does
+  // not need to take L2 from the halo lines of the blocks still running
+  const long base = fidx(g, B, s, 12);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    __builtin_nontemporal_store(acc[c].re, &out[base + (long)c * TILE].re);
+    __builtin_nontemporal_store(acc[c].im, &out[base + (long)c * TILE].im);
+  }
 }
 
 template <class R, class S>

@@ -1296,9 +1296,12 @@ struct MG : MGBase {
 
   void load_fine_init(const cx<float>* v) override {
     const long len = c.fine_len();
-    for (int i = 0; i < Nv[0]; ++i)
-      launch_copy_cvt<float, R>(v + (long)i * len, Vraw[0].template as<cx<R>>() + (long)i * len, len, c.st);
+    for (int i = 0; i < Nv[0]; ++i) load_fine_vec(i, v + (long)i * len);
     c.sync();
+  }
+  void load_fine_vec(int i, const cx<float>* v) override {
+    const long len = c.fine_len();
+    launch_copy_cvt<float, R>(v, Vraw[0].template as<cx<R>>() + (long)i * len, len, c.st);
     loaded[0] = true;
   }
   void adopt_vectors(MGBase& prev_) override {

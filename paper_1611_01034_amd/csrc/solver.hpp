@@ -260,6 +260,8 @@ struct MGBase {
   // level-0 initial vectors from the device (block layout, FP32, stride = fine
   // length), copied into the hierarchy; build() then skips vecs[0]
   virtual void load_fine_init(const cx<float>* v) = 0;
+  // one of them (index i, block layout, FP32); build() then skips vecs[0]
+  virtual void load_fine_vec(int i, const cx<float>* v) = 0;
   // the test vectors of a previous hierarchy of the same precision, levels
   // and N_v (the kept raw vectors, else its interpolation bases Q_l) become
   // this one's (moved, not copied); build() then skips vecs for those levels

@@ -99,6 +99,7 @@ _SIGS = {
     "ddamg_set_mu_eo": (_i, [_vp, _d, _d]),
     "ddamg_setup": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
     "ddamg_set_test_vectors": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i]),
+    "ddamg_setup_prec": (_i, [_vp, ctypes.POINTER(Params), ctypes.POINTER(_vp), _i, _i]),
     "ddamg_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_solve_odd_shifted": (_i, [_vp, _vp, _vp, _d, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_apply_dirac": (_i, [_vp, _vp, _vp, _i, _i, _i]),
@@ -307,8 +308,24 @@ class DDAMG:
         return arrs, ptrs, dev
 
     def setup(self, params: Params, init_vectors):
-        arrs, ptrs, dev = self._vec_ptrs(init_vectors)
-        self._check(_lib.ddamg_setup(self._h, ctypes.byref(params), ptrs, dev))
+        """Adaptive setup from random initial vectors per level; the fine
+        level's may be complex64 (numpy or torch), which is passed as it is."""
+        v0 = init_vectors[0]
+        c64 = (v0.dtype == np.complex64) if not _is_torch(v0) else (str(v0.dtype) == "torch.complex64")
+        if not c64:
+            arrs, ptrs, dev = self._vec_ptrs(init_vectors)
+            self._check(_lib.ddamg_setup(self._h, ctypes.byref(params), ptrs, dev))
+            self.params = params
+            return
+        v0 = v0.contiguous() if _is_torch(v0) else np.ascontiguousarray(v0)
+        rest = [_c128(v) for v in init_vectors[1:]]
+        ptrs = (ctypes.c_void_p * 3)()
+        ptrs[0], dev = _ptr(v0)
+        for i, a in enumerate(rest):
+            ptrs[i + 1], dev_i = _ptr(a)
+            if dev_i != dev:
+                raise ValueError("initial vectors must all be on the host or all on the device")
+        self._check(_lib.ddamg_setup_prec(self._h, ctypes.byref(params), ptrs, FP32, dev))
         self.params = params
 
     def setup_learned(self, params: Params, noise, coarse_init=None):

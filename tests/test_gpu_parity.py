@@ -490,3 +490,20 @@ def test_setup_progress_notifications(dd):
     ctx.setup(p, [V0])
     assert calls == []
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_setup_from_complex64_initial_vectors(dd, prec):
+    # the fine initial vectors passed as complex64 give the hierarchy of the
+    # same values passed as complex128 (the setup stores them in FP32 or
+    # lower either way)
+    dims, block, nv = (8, 8, 8, 8), (4, 4, 4, 4), 8
+    ctx, op, _ = make(dd, dims, block)
+    V = synth.spinor(dims, 1801, nvec=nv).astype(np.complex64)
+    p = dd.default_params(levels=2, block=[block], nvec=[nv], setup_iters=1, precision=prec)
+    ctx.setup(p, [V.astype(np.complex128)])
+    Q128 = ctx.get_interpolation(0)
+    ctx.setup(p, [V])
+    Q64 = ctx.get_interpolation(0)
+    assert np.array_equal(Q64, Q128)
+    ctx.close()
