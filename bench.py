@@ -16,8 +16,9 @@ generated on the device before the timed region.
 
 Prints one JSON line.  `value` is the mixed-precision step time in seconds
 (lower is better).  After the timed steps:
-  * one untimed step with the other initial test vectors (learned <-> random)
-    on the same inputs, when it fits --time-budget (`other_start`);
+  * with --alt-start 1, one untimed step with the other initial test vectors
+    (learned <-> random) on the same inputs ran before the warm-up steps
+    (`other_start`);
   * the plain FP64 form (random start, 5-iteration setup) runs once on the
     same right-hand sides when it fits --time-budget (seconds since start),
     else the line says it was skipped;
@@ -73,10 +74,10 @@ def parse():
                          "right-hand side is what bounds the lock-step group at 48^3x96)")
     ap.add_argument("--learned", type=int, default=0,
                     help="1: the network proposes the initial test vectors; 0: Gaussian random vectors "
-                         "(the faster start at this roughness after one setup iteration; the other one is "
-                         "timed after the timed steps, see --alt-start)")
-    ap.add_argument("--alt-start", type=int, default=1,
-                    help="after the timed steps, one untimed step with the other initial vectors")
+                         "(the faster start at this roughness after one setup iteration; --alt-start 1 "
+                         "times the other one in an untimed step)")
+    ap.add_argument("--alt-start", type=int, default=0,
+                    help="one untimed step with the other initial vectors before the warm-up steps")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--time-budget", type=float, default=540.0,
                     help="seconds since start beyond which the FP64 leg is skipped")
@@ -268,16 +269,21 @@ def main():
     b = synth.gaussian_device((args.nrhs,) + dims + (4, 3), 5101)
     x = torch.empty_like(b)
     V1 = synth.gaussian_device((nv[1],) + cd + (2 * nv[0],), 5502)
-    if args.learned:
+    need_net = bool(args.learned or args.alt_start)
+    if need_net:
         from paper_1611_01034_amd import learned_setup
         wts, C, L, _ = learned_setup.load_weights(learned_setup.WEIGHTS)
         if C != nv[0]:
             raise SystemExit("network channels must equal the level-0 test vector count")
-        noise = synth.gaussian_device((C,) + dims + (4, 3), 5501, dtype="complex64")
-        V0 = None
-    else:
-        # complex64, like the network's noise: the setup stores them in FP32 or lower
-        V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501, dtype="complex64")
+
+    def start_input(learned):
+        """The fine-level input of a start: the network's noise (learned) or
+        the Gaussian initial vectors, both complex64 (the setup stores them in
+        FP32 or lower) and drawn from the same seed."""
+        v = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501, dtype="complex64")
+        # the real and imaginary parts it was built from go back to the device
+        torch.cuda.empty_cache()
+        return v
     torch.cuda.synchronize()
 
     def make_ctx(Ug, net=False):
@@ -293,7 +299,7 @@ def main():
                                     coarse_setup_iters=3, precision=prec, coarse_mu_factor=5.0, batch=batch,
                                     rhs_batch=rhs_batch)
 
-    ctx = make_ctx(U, net=bool(args.learned))
+    ctx = make_ctx(U, net=need_net)
     # the oracle leg takes its slices of the inputs now and runs on the host
     # while the GPU works
     leg = OracleLeg(U, b[0], args.oracle_procs) if args.cpu_baseline else None
@@ -309,26 +315,47 @@ def main():
         overrides[k] = float(v) if "." in v or "e" in v else int(v)
         setattr(p_mixed, k, overrides[k])
 
-    def step(c, tag):
+    def step(c, tag, learned, init):
         t = time.time()
-        if args.learned:
-            c.setup_learned(p_mixed, noise, V1)
+        if learned:
+            c.setup_learned(p_mixed, init, V1)
         else:
-            c.setup(p_mixed, [V0, V1])
+            c.setup(p_mixed, [init, V1])
         log(f"{tag}: setup issued ({time.time() - t:.1f} s)")
         _, st = c.solve(b, tol=1e-10, x=x)
         log(f"{tag}: solve done ({time.time() - t:.1f} s, {st['iters']} iterations over {st['nrhs']} rhs, "
             f"{st['iters_min']}-{st['iters_max']} per rhs)")
         return st
 
+    # the other start first (one untimed step on the same inputs), so that it
+    # runs with the memory the timed steps use
+    other_start = None
+    if args.alt_start:
+        o_learned = not args.learned
+        init = start_input(o_learned)
+        torch.cuda.synchronize()
+        t = time.time()
+        st_o = step(ctx, "other start", o_learned, init)
+        torch.cuda.synchronize()
+        dt_o = time.time() - t
+        other_start = {"start": ("learned" if o_learned else "random") + f"+{args.setup_iters}",
+                       "step_s": round(dt_o, 3), "iters_per_rhs": round(st_o["iters"] / max(1, st_o["nrhs"]), 2),
+                       "iters_min": st_o["iters_min"], "iters_max": st_o["iters_max"], "resid": st_o["resid"],
+                       "note": "one untimed step before the warm-up steps, same inputs; its first-call "
+                               "allocations are in its time"}
+        init = None
+        torch.cuda.empty_cache()
+        ctx.release_memory()
+    init = start_input(bool(args.learned))
+    torch.cuda.synchronize()
     for i in range(args.warmup):
-        step(ctx, f"warmup {i}")
+        step(ctx, f"warmup {i}", bool(args.learned), init)
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.time()
     stats = None
     for i in range(args.steps):
-        stats = step(ctx, f"step {i}")
+        stats = step(ctx, f"step {i}", bool(args.learned), init)
     torch.cuda.synchronize()
     dt = (time.time() - t0) / args.steps
     n_d, ms_d = ctx.timing_query(0)
@@ -385,50 +412,6 @@ def main():
                "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_s,
                "launches": n_s, "avg_launch_ms": round(ms_s / n_s, 4)}
 
-    # the other initial test vectors (learned <-> random), one untimed step on
-    # the same right-hand sides, when the run's time budget allows it
-    alt = None
-    if args.alt_start:
-        elapsed = time.time() - T_START
-        other = "random" if args.learned else "learned"
-        if elapsed + 2.0 * dt > args.time_budget:
-            alt = {"start": other + f"+{args.setup_iters}",
-                   "note": f"skipped: {elapsed:.0f} s elapsed + about {2 * dt:.0f} s exceeds the "
-                           f"{args.time_budget:.0f} s budget of this run"}
-        else:
-            ctx.release_memory()
-            if args.learned:
-                noise = None
-                torch.cuda.empty_cache()
-                V0a = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501, dtype="complex64")
-            else:
-                from paper_1611_01034_amd import learned_setup
-                wts, C, L, _ = learned_setup.load_weights(learned_setup.WEIGHTS)
-                ctx.net_create(L, C)
-                ctx.net_set_params(wts)
-                V0 = None
-                torch.cuda.empty_cache()
-                noise_a = synth.gaussian_device((C,) + dims + (4, 3), 5501, dtype="complex64")
-            torch.cuda.synchronize()
-            t = time.time()
-            if args.learned:
-                ctx.setup(p_mixed, [V0a, V1])
-            else:
-                ctx.setup_learned(p_mixed, noise_a, V1)
-            _, st_a = ctx.solve(b, tol=1e-10, x=x)
-            torch.cuda.synchronize()
-            dt_a = time.time() - t
-            alt = {"start": other + f"+{args.setup_iters}", "step_s": round(dt_a, 3),
-                   "iters_per_rhs": round(st_a["iters"] / max(1, st_a["nrhs"]), 2),
-                   "iters_min": st_a["iters_min"], "iters_max": st_a["iters_max"], "resid": st_a["resid"],
-                   "note": "one untimed step after the timed ones, same inputs"}
-            log(f"other start ({other}): step {dt_a:.2f} s, {alt['iters_per_rhs']} iterations per rhs")
-            if args.learned:
-                del V0a
-            else:
-                del noise_a
-            ctx.release_memory()
-            torch.cuda.empty_cache()
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -445,7 +428,7 @@ def main():
                          f"{args.time_budget:.0f} s budget of this run")
             log("fp64:", fp64_note)
         else:
-            noise = None
+            init = None
             torch.cuda.empty_cache()
             V0 = synth.gaussian_device((nv[0],) + dims + (4, 3), 5501)
             U = synth.gauge_field_device(dims, 0.3, 5001)
@@ -529,7 +512,7 @@ def main():
         "fp64_stats": fp64_stats,
         "fp64_note": fp64_note,
         "speedup_mixed_vs_fp64": round(fp64_s / dt, 3) if fp64_s else None,
-        "other_start": alt,
+        "other_start": other_start,
         "kernel_ms": {k: {"launches": v[0], "ms": round(v[1], 2)} for k, v in kinds.items()},
     }
     print(json.dumps(out), flush=True)
