@@ -30,57 +30,77 @@ namespace ddamg {
 // slot (even slots first).  r = b - D x on the block, then n_mr MR steps
 // on the block-local even-site Schur complement S = T_ee - D_eo T_oo^{-1} D_oe
 // (hops leaving the block dropped), odd reconstruction, x += e.
+
+// In-block neighbours of a slot, packed: for direction mu the forward and the
+// backward neighbour's index within the other parity's half of the block
+// (bytes 2(mu&1) and 2(mu&1)+1 of word mu>>1), or `half` where the hop
+// leaves the block.  Computed once per thread; the block solve reads its
+// neighbours from LDS halves whose index `half` holds a zero spinor, so a
+// dropped hop costs neither an index computation nor a mask.
+struct BlockNbr {
+  unsigned w[2];
+};
+__device__ __forceinline__ BlockNbr block_nbrs(const Geom& g, const SiteNbr& me) {
+  BlockNbr nb{{0u, 0u}};
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
+    const int l0 = l[mu];
+    int f = g.half, b = g.half;
+    if (l0 + 1 < g.b[mu]) {
+      l[mu] = l0 + 1;
+      const int sn = local_slot(g, l);
+      f = sn >= g.half ? sn - g.half : sn;
+    }
+    if (l0 > 0) {
+      l[mu] = l0 - 1;
+      const int sn = local_slot(g, l);
+      b = sn >= g.half ? sn - g.half : sn;
+    }
+    nb.w[mu >> 1] |= (unsigned)(f | (b << 8)) << (16 * (mu & 1));
+  }
+  return nb;
+}
+
+// out += (or -= with SUB) the in-block hops of slot s, the neighbours' spinors
+// read from lds (12 x hs, component-major, the other parity's half of the
+// block; entry `half` of every component is zero).  noff: slot offset of the
+// neighbours' parity (their links are read for the backward hops).  Both links
+// of a direction are loaded before its arithmetic (one memory latency per
+// direction); a dropped backward hop reads a link of the block, multiplied by
+// the zero spinor.
 template <class R, class S, bool SUB = false>
 __device__ __forceinline__ void hop_block_lds(const typename store_traits<S>::elem* U, const Geom& g, int B, int s,
-                                              const SiteNbr& me, const cx<R>* lds, int lds_off, cx<R> out[12]) {
-  // lds holds a 12 x half field of the opposite parity (component-major);
-  // hops leaving the block are dropped (Dirichlet cut of the SAP domain).
-  // Both links of a direction are loaded before its arithmetic, and a dropped
-  // hop is masked by a zero link rather than a branch, so each direction costs
-  // one memory latency instead of two.
+                                              BlockNbr nb, int noff, const cx<R>* lds, int hs, cx<R> out[12]) {
   using E = typename store_traits<S>::elem;
-  const long base_s = fidx(g, B, s, 36);
-  auto issue = [&](int mu, E* lf, E* lb, int& sf, int& sb, bool& vf, bool& vb) {
-    int l[4] = {me.l[0], me.l[1], me.l[2], me.l[3]};
-    vf = l[mu] + 1 < g.b[mu];
-    vb = l[mu] > 0;
-    const int l0 = l[mu];
-    l[mu] = l0 + 1;
-    int snf = local_slot(g, l);
-    l[mu] = l0 - 1;
-    int snb = vb ? local_slot(g, l) : s;
-    sf = vf ? snf - lds_off : 0;
-    sb = vb ? snb - lds_off : 0;
-    const long bf = base_s + (long)mu * 9 * TILE;
-    const long bb = fidx(g, B, snb, 36) + (long)mu * 9 * TILE;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      lf[k] = U[bf + (long)k * TILE];
-      lb[k] = U[bb + (long)k * TILE];
-    }
-  };
+  // opaque per call: nothing derived from the neighbour words or the slot is
+  // kept live across the MR steps
+  __asm__ volatile("" : "+v"(nb.w[0]), "+v"(nb.w[1]), "+v"(s));
+  const long blk = (long)B * (g.bs / TILE) * 36 * TILE;
+  const long base_s = blk + (long)(s / TILE) * 36 * TILE + (s % TILE);
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
+    const unsigned wd = (mu < 2 ? nb.w[0] : nb.w[1]) >> (16 * (mu & 1));
+    const int sf = wd & 255, sb = (wd >> 8) & 255;
+    const int lb = min(sb, g.half - 1) + noff;
+    const long bf = base_s + (long)mu * 9 * TILE;
+    const long bb = blk + (long)(lb / TILE) * 36 * TILE + (lb % TILE) + (long)mu * 9 * TILE;
     E cf[9], cb[9];
-    int sf, sb;
-    bool vf, vb;
-    issue(mu, cf, cb, sf, sb, vf, vb);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      cf[k] = U[bf + (long)k * TILE];
+      cb[k] = U[bb + (long)k * TILE];
+    }
     cx<R> psi[12], u[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      cx<R> v = mk<R>((R)cf[k].re, (R)cf[k].im);
-      u[k] = vf ? v : mk<R>(0, 0);
-    }
+    for (int k = 0; k < 9; ++k) u[k] = mk<R>((R)cf[k].re, (R)cf[k].im);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sf] : lds[c * g.half + sf];
+    for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * hs + sf] : lds[c * hs + sf];
     hop_accum<0>(mu, psi, u, out);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      cx<R> v = mk<R>((R)cb[k].re, (R)cb[k].im);
-      u[k] = vb ? v : mk<R>(0, 0);
-    }
+    for (int k = 0; k < 9; ++k) u[k] = mk<R>((R)cb[k].re, (R)cb[k].im);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * g.half + sb] : lds[c * g.half + sb];
+    for (int c = 0; c < 12; ++c) psi[c] = SUB ? -lds[c * hs + sb] : lds[c * hs + sb];
     hop_accum<1>(mu, psi, u, out);
   }
 }
@@ -101,8 +121,12 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
       const R* __restrict__ Minv, TwistR<R> tw, const cx<R>* __restrict__ b, cx<R>* __restrict__ x, int n_mr, int K,
       long ld) {
   extern __shared__ char smem_raw[];
-  cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x half, even slots
-  cx<R>* od = ev + 12 * g.half;                     // 12 x half, odd slots
+  // the residual stages x of the block parity-split (24 x half); the block
+  // solve then keeps one field per parity as 12 x hs (hs = half + 1: entry
+  // half of each component is the zero spinor of dropped hops)
+  const int hs = g.half + 1;
+  cx<R>* ev = reinterpret_cast<cx<R>*>(smem_raw);  // 12 x hs, even slots
+  cx<R>* od = ev + 12 * hs;                         // 12 x hs, odd slots
   __shared__ double red[2][3][2];                    // per-wavefront sums, by MR step parity
   int B;
   {
@@ -154,13 +178,15 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
     load_spinor(x, g, B, so, psi);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      od[c * g.half + i] = tmp[c];
+      od[c * hs + i] = tmp[c];
       psi[c] += tmp[c];
     }
     store_spinor(x, g, B, so, psi);
+    for (int e = i; e < 24; e += g.half) (e < 12 ? ev : od)[(e % 12) * hs + g.half] = mk<R>(0, 0);
   }
+  const BlockNbr nb_e = block_nbrs(g, me_e), nb_o = block_nbrs(g, me_o);
   __syncthreads();
-  hop_block_lds<R, S, true>(U, g, B, se, me_e, od, g.half, rho);  // rho = r_e - D_eo t_o
+  hop_block_lds<R, S, true>(U, g, B, se, nb_e, g.half, od, hs, rho);  // rho = r_e - D_eo t_o
 #pragma unroll
   for (int c = 0; c < 12; ++c) ee[c] = mk<R>(0, 0);
   const int nact = min(64, g.half - wv * 64);
@@ -169,22 +195,22 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
     // links, clover and inverses in registers would exceed the register file
     __asm__ volatile("" ::: "memory");
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ev[c * g.half + i] = rho[c];
+    for (int c = 0; c < 12; ++c) ev[c * hs + i] = rho[c];
     __syncthreads();
     {  // w = T_oo^{-1} D_oe rho
       cx<R> u[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) u[c] = mk<R>(0, 0);
-      hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, u);
+      hop_block_lds<R, S>(U, g, B, so, nb_o, 0, ev, hs, u);
       site_inv(H, Minv, g, B, so, tw, u, tmp);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) od[c * g.half + i] = tmp[c];
+      for (int c = 0; c < 12; ++c) od[c * hs + i] = tmp[c];
     }
     __syncthreads();
     __asm__ volatile("" ::: "memory");
     // q = T_ee rho - D_eo w
     site_term(H, g, B, se, tw, rho, tmp);
-    hop_block_lds<R, S, true>(U, g, B, se, me_e, od, g.half, tmp);
+    hop_block_lds<R, S, true>(U, g, B, se, nb_e, g.half, od, hs, tmp);
     double qr_re = 0, qr_im = 0, qq = 0;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -216,13 +242,13 @@ k_sap(Geom g, int colour, const typename store_traits<S>::elem* __restrict__ U, 
     }
   }
 #pragma unroll
-  for (int c = 0; c < 12; ++c) ev[c * g.half + i] = ee[c];
+  for (int c = 0; c < 12; ++c) ev[c * hs + i] = ee[c];
   __syncthreads();
   {  // x_o -= T_oo^{-1} D_oe e_e
     cx<R> u[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) u[c] = mk<R>(0, 0);
-    hop_block_lds<R, S>(U, g, B, so, me_o, ev, 0, u);
+    hop_block_lds<R, S>(U, g, B, so, nb_o, 0, ev, hs, u);
     site_inv(H, Minv, g, B, so, tw, u, tmp);
     load_spinor(x, g, B, so, u);
 #pragma unroll
@@ -243,7 +269,7 @@ void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* M
 template <class R, class S>
 void launch_sap_multi(const Geom& g, int colour, const void* U, const R* H, const R* Minv, Twist tw, const cx<R>* b,
                       cx<R>* x, int n_mr, int K, long ld, hipStream_t st) {
-  size_t sm = 2 * 12 * (size_t)g.half * sizeof(cx<R>);
+  size_t sm = 2 * 12 * (size_t)(g.half + 1) * sizeof(cx<R>);
   hipLaunchKernelGGL((k_sap<R, S>), dim3((g.nblocks / 2) * K), dim3(g.half), sm, st, g, colour,
                      (const typename store_traits<S>::elem*)U, H, Minv, TwistR<R>(tw), b, x, n_mr, K, ld);
 }
