@@ -231,8 +231,12 @@ def dirac_sources_sha256():
     return h.hexdigest()
 
 
-def traffic_for(kernel_src_hash):
-    p = os.path.join(ROOT, "profiles", "dirac_fp64_48x48x48x96_traffic.json")
+def traffic_for(kernel_src_hash, nfields):
+    """Calibrated HBM bytes per launch of the FP64 D(mu) kernel on nfields
+    fields at 48^3x96, from the committed counter record of that launch shape,
+    or None when there is none or the kernel sources changed since."""
+    tag = f"{nfields}fields_" if nfields > 1 else ""
+    p = os.path.join(ROOT, "profiles", f"dirac_fp64_{tag}48x48x48x96_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -387,10 +391,14 @@ def main():
         torch.cuda.empty_cache()
         log(f"oracle at {args.oracle_sites} random sites: {sites_check}")
 
-    # D(mu) FP64 bandwidth inside the timed steps (HIP events around every launch)
+    # D(mu) FP64 bandwidth inside the timed steps (HIP events around every
+    # launch); each launch applies the operator to the K fields of a lock-step
+    # group and reads the links and clover once: (1152 + 384 K) B per site
     avg_ms = ms_d / max(n_d, 1)
-    bytes_launch = DIRAC_FP64_BYTES_PER_SITE * V
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if n_d else None
+    bytes_d = ctx.timing_bytes(0)
+    bytes_launch = bytes_d / max(n_d, 1)
+    d_fields = int(round((bytes_launch / V - 1152) / 384)) if n_d else 0
+    achieved = bytes_d / (ms_d * 1e-3) / 1e9 if n_d else None
     src_hash = dirac_sources_sha256()
     # fine SAP colour sweeps inside the timed steps: every launch sweeps the
     # blocks of one colour for K fields (K = the setup's batch or the rhs
@@ -497,11 +505,12 @@ def main():
                                f"preconditioner {args.precision}, outer FGMRES FP64, tol 1e-10"
                                + (f", overrides {overrides}" if overrides else ""),
                    "global_batch": args.nrhs, "parallelism": "none"},
-        "roofline": {"bound": "hbm", "kernel": "D(mu) FP64 full-lattice apply",
+        "roofline": {"bound": "hbm", "kernel": f"D(mu) FP64 full-lattice apply on the {d_fields} fields of a "
+                                               f"lock-step group per launch",
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": traffic_for(src_hash), "algorithmic_bytes_per_launch": bytes_launch,
-                     "launches": n_d, "avg_launch_ms": round(avg_ms, 4)},
+                     "traffic": traffic_for(src_hash, d_fields), "algorithmic_bytes_per_launch": bytes_launch,
+                     "fields_per_launch": d_fields, "launches": n_d, "avg_launch_ms": round(avg_ms, 4)},
         "roofline_sap": sap,
         "cpu_baseline": cpu,
         "oracle_check": check,

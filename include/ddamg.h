@@ -273,6 +273,16 @@ int ddamg_solve_odd_shifted(ddamg_ctx* ctx, const void* b, void* x, double rho, 
 /* out = D(sign*mu) in, full lattice (Sec. 1); precision FP64 or FP32 (and
  * FP16/BF16 links with FP32 arithmetic). */
 int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int precision, int on_device);
+/* out_k = D(sign*mu) in_k for nfields (1..16) fields in one launch (Sec. 1):
+ * in and out hold the fields one after the other (spinor layout above, each
+ * field V*12 complex128); the kernel reads the links and the clover term once
+ * for all fields, as the lock-step outer solve does.  Same arithmetic per
+ * field as ddamg_apply_dirac (bit-identical results); the library stages the
+ * fields in device memory of its own for the call.  INVALID_ARG for NULL
+ * fields, nfields out of range or an unknown precision; BAD_STATE without a
+ * gauge field. */
+int ddamg_apply_dirac_multi(ddamg_ctx* ctx, int nfields, const void* in, void* out, int sign, int precision,
+                            int on_device);
 /* out = D(sign*mu) in in FP64, allocating nothing: for callers that cannot
  * allocate device memory (code under HIP graph capture, serving loops,
  * harnesses that forbid hipMalloc).  Same operator and kernels as

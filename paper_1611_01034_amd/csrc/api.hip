@@ -503,7 +503,7 @@ int ddamg_solve(ddamg_ctx* ctx, const void* b, void* x, int nrhs, double tol, dd
       bK.alloc(sizeof(cx<double>) * N * Kb, true);
       xK.alloc(sizeof(cx<double>) * N * Kb, true);
       OpM<double> AK = [&c, N](const cx<double>* in, cx<double>* out, int K) {
-        for (int k = 0; k < K; ++k) c.dirac64(in + k * N, out + k * N, c.twist());
+        c.dirac64_multi(in, out, K, N, c.twist());
       };
       OpM<double> MK = [&c](const cx<double>* in, cx<double>* out, int K) { c.mg->precond_multi(in, out, K); };
       OpMf MKf = [&c](const cx<double>* in, cx<float>* out, int K) { c.mg->precond_multi_f32(in, out, K); };
@@ -687,6 +687,52 @@ int ddamg_apply_dirac(ddamg_ctx* ctx, const void* in, void* out, int sign, int p
       launch_copy_cvt<float, double>(c.f32b.as<cx<float>>(), c.f64b.as<cx<double>>(), N, c.st);
     }
     c.download_fine(c.f64b.as<cx<double>>(), out, on_device);
+    c.sync();
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_apply_dirac_multi(ddamg_ctx* ctx, int nfields, const void* in, void* out, int sign, int precision,
+                            int on_device) {
+  if (!ctx) return DDAMG_INVALID_ARG;
+  return guard(ctx, [&]() {
+    Ctx& c = ctx->c;
+    need_gauge(c);
+    if (!in || !out) throw Error(INVALID_ARG, "NULL field");
+    if (nfields < 1 || nfields > 16) throw Error(INVALID_ARG, "nfields must be in [1, 16]");
+    if (precision < DDAMG_FP64 || precision > DDAMG_BF16) throw Error(INVALID_ARG, "unknown precision");
+    const Twist tw = c.twist(sign);
+    const long N = c.fine_len();
+    const size_t fb = sizeof(cx<double>) * (size_t)N;
+    DevBuf a64, b64;
+    a64.alloc(fb * nfields, true);
+    b64.alloc(fb * nfields, true);
+    for (int k = 0; k < nfields; ++k)
+      c.upload_fine((const char*)in + fb * k, on_device, a64.as<cx<double>>() + (long)k * N);
+    if (precision == DDAMG_FP64) {
+      c.dirac64_multi(a64.as<cx<double>>(), b64.as<cx<double>>(), nfields, N, tw);
+    } else {
+      c.ensure_32();
+      DevBuf a32, b32;
+      a32.alloc(sizeof(cx<float>) * (size_t)N * nfields, true);
+      b32.alloc(sizeof(cx<float>) * (size_t)N * nfields, true);
+      launch_copy_cvt<double, float>(a64.as<cx<double>>(), a32.as<cx<float>>(), N * nfields, c.st);
+      if (precision == DDAMG_FP32) {
+        launch_dirac_multi<float, float>(c.g, c.U32.p, c.H32.as<float>(), tw, nfields, N, a32.as<cx<float>>(),
+                                         b32.as<cx<float>>(), c.st);
+      } else {
+        c.ensure_16(precision);
+        if (precision == DDAMG_FP16)
+          launch_dirac_multi<float, f16>(c.g, c.U16.p, c.H32.as<float>(), tw, nfields, N, a32.as<cx<float>>(),
+                                         b32.as<cx<float>>(), c.st);
+        else
+          launch_dirac_multi<float, bf16>(c.g, c.U16.p, c.H32.as<float>(), tw, nfields, N, a32.as<cx<float>>(),
+                                          b32.as<cx<float>>(), c.st);
+      }
+      launch_copy_cvt<float, double>(b32.as<cx<float>>(), b64.as<cx<double>>(), N * nfields, c.st);
+    }
+    for (int k = 0; k < nfields; ++k)
+      c.download_fine(b64.as<cx<double>>() + (long)k * N, (char*)out + fb * k, on_device);
     c.sync();
     return DDAMG_OK;
   });

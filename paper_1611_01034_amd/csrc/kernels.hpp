@@ -53,6 +53,10 @@ struct CGeom {
 // ---------------------------------------------------------------- fine level
 template <class R, class S>
 void launch_dirac(const Geom& g, const void* U, const R* H, Twist tw, const cx<R>* in, cx<R>* out, hipStream_t st);
+// K fields at a stride of ld complex in one launch (links and clover read once)
+template <class R, class S>
+void launch_dirac_multi(const Geom& g, const void* U, const R* H, Twist tw, int K, long ld, const cx<R>* in,
+                        cx<R>* out, hipStream_t st);
 template <class R, class S>
 void launch_sap(const Geom& g, int colour, const void* U, const R* H, const R* Minv, Twist tw, const cx<R>* b,
                 cx<R>* x, int n_mr, hipStream_t st);

@@ -725,10 +725,12 @@ void Ctx::rebuild_odd_inverse() {
   launch_odd_inverse(g, H64.as<double>(), mu_odd, M64.as<double>(), st);
   if (have_32) launch_cvt_real((long)g.V * 36, M64.as<double>(), M32.as<float>(), st);
 }
-void Ctx::dirac64(const cx<double>* in, cx<double>* out, Twist tw) {
-  // spinor in and out, links and clover once: 1536 bytes per site
-  TimeScope ts(timer, 0, 1536.0 * (double)g.V);
-  launch_dirac<double, double>(g, U64.p, H64.as<double>(), tw, in, out, st);
+void Ctx::dirac64(const cx<double>* in, cx<double>* out, Twist tw) { dirac64_multi(in, out, 1, 0, tw); }
+void Ctx::dirac64_multi(const cx<double>* in, cx<double>* out, int K, long ld, Twist tw) {
+  // per site links and clover once (1152 bytes), spinor in and out per field
+  // (384 bytes)
+  TimeScope ts(timer, 0, (1152.0 + 384.0 * K) * (double)g.V);
+  launch_dirac_multi<double, double>(g, U64.p, H64.as<double>(), tw, K, ld, in, out, st);
 }
 void Ctx::upload_fine(const void* src, int on_device, cx<double>* dst64) {
   const cx<double>* s = (const cx<double>*)src;

@@ -328,6 +328,8 @@ struct Ctx {
   }
   // fine FP64 operator D(tw) in block layout
   void dirac64(const cx<double>* in, cx<double>* out, Twist tw);
+  // K fields at a stride of ld complex in one launch
+  void dirac64_multi(const cx<double>* in, cx<double>* out, int K, long ld, Twist tw);
   // host/device lex FP64 field -> block layout
   void upload_fine(const void* src, int on_device, cx<double>* dst64);
   void download_fine(const cx<double>* src64, void* dst, int on_device);

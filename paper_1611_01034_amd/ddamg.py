@@ -103,6 +103,7 @@ _SIGS = {
     "ddamg_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_solve_odd_shifted": (_i, [_vp, _vp, _vp, _d, _d, ctypes.POINTER(Stats), _i]),
     "ddamg_apply_dirac": (_i, [_vp, _vp, _vp, _i, _i, _i]),
+    "ddamg_apply_dirac_multi": (_i, [_vp, _i, _vp, _vp, _i, _i, _i]),
     "ddamg_apply_dirac_noalloc": (_i, [_vp, _vp, _vp, _i]),
     "ddamg_sap": (_i, [_vp, _vp, _vp, _i, _i, _i, _i]),
     "ddamg_sap_multi": (_i, [_vp, _i, _vp, _vp, _i, _i, _i, _i]),
@@ -398,6 +399,16 @@ class DDAMG:
         out = np.empty_like(psi) if not _is_torch(psi) else psi.new_empty(psi.shape)
         pi, dev = _ptr(psi)
         self._check(_lib.ddamg_apply_dirac(self._h, pi, _ptr(out)[0], int(sign), PRECISIONS[precision], dev))
+        return out
+
+    def apply_dirac_multi(self, psis, sign=+1, precision="fp64"):
+        """D(sign*mu) on K fields [K, T, Z, Y, X, 4, 3] (host array or
+        complex128 CUDA tensor) in one launch."""
+        psis = _c128(psis)
+        out = np.empty_like(psis) if not _is_torch(psis) else psis.new_empty(psis.shape)
+        pi, dev = _ptr(psis)
+        self._check(_lib.ddamg_apply_dirac_multi(self._h, int(psis.shape[0]), pi, _ptr(out)[0], int(sign),
+                                                 PRECISIONS[precision], dev))
         return out
 
     def apply_dirac_noalloc(self, psi, out, sign=+1):

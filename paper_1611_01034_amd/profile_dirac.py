@@ -1,5 +1,7 @@
 """Profiling driver for the fine operator: a fixed number of D(mu) applies on
-a seeded synthetic field, followed by a plain device copy of known size.
+a seeded synthetic field (or, with --nfields K > 1, on K Gaussian fields in
+one launch each, as the lock-step outer solve applies it), followed by a
+plain device copy of known size.
 
 The copy calibrates rocprofv3's HBM byte counters (FETCH_SIZE, WRITE_SIZE):
 it reads and writes exactly `--copy-mib` MiB, so counter / known bytes is the
@@ -25,6 +27,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=2048)
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--seed", type=int, default=5001)
+    ap.add_argument("--nfields", type=int, default=1)
     a = ap.parse_args()
 
     import torch
@@ -39,7 +42,13 @@ def main():
         ctx.set_gauge(U)
         del U
         torch.cuda.synchronize()
-        ctx.bench_dirac(a.napply, a.precision)
+        if a.nfields == 1:
+            ctx.bench_dirac(a.napply, a.precision)
+        else:
+            psis = synth.gaussian_device((a.nfields,) + dims + (4, 3), a.seed + 1)
+            torch.cuda.empty_cache()
+            for _ in range(a.napply):
+                ctx.apply_dirac_multi(psis, precision=a.precision)
         torch.cuda.synchronize()
     n = a.copy_mib * (1 << 20) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -47,7 +56,7 @@ def main():
     for _ in range(3):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
-    print(f"profile_dirac: dims {dims}, {a.napply} x D(mu) {a.precision}, "
+    print(f"profile_dirac: dims {dims}, {a.napply} x D(mu) {a.precision} on {a.nfields} field(s), "
           f"copy {a.copy_mib} MiB read + {a.copy_mib} MiB written x 3", flush=True)
 
 
