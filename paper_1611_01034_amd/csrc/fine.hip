@@ -732,15 +732,22 @@ template void launch_prolong_fine<float>(const Geom&, int, const cx<float>*, lon
 
 // K-column restriction: one thread per slot (threads past the block's slots
 // contribute zero), columns in groups of KC whose inputs stay in registers, test
-// vectors in groups of four, so Q is read once per group of columns.  The 16 KC
-// values (vector, column, half, re/im) of a group are summed over the wavefront
-// by a transposing butterfly and over the wavefronts in LDS in fixed order.
-template <class R, int KC>
+// vectors in groups of II, so Q is read once per group of columns.  The 4 II KC
+// values (vector, column, half, re/im) of a group, padded to a power of two,
+// are summed over the wavefront by a transposing butterfly and over the
+// wavefronts in LDS in fixed order.
+template <int N>
+constexpr int pow2_ceil() {
+  int p = 1;
+  while (p < N) p *= 2;
+  return p;
+}
+template <class R, int KC, int II>
 __global__ void __launch_bounds__(256) k_restrict_fine_m(Geom g, int Nv, const cx<R>* __restrict__ Q, long vstride,
                                                          const cx<R>* __restrict__ r, long rld, int K,
                                                          const int* __restrict__ f2c, cx<R>* __restrict__ rc,
                                                          long cld) {
-  constexpr int NVAL = 16 * KC;
+  constexpr int NV0 = 4 * II * KC, NVAL = pow2_ceil<NV0>();
   __shared__ R red[4][NVAL];
   const int B = blockIdx.x, s = threadIdx.x, lane = s & 63, wv = s >> 6, nw = blockDim.x >> 6;
   const bool live = s < g.bs;
@@ -753,12 +760,12 @@ __global__ void __launch_bounds__(256) k_restrict_fine_m(Geom g, int Nv, const c
 #pragma unroll
       for (int c = 0; c < 12; ++c)
         rv[kk][c] = live && k0 + kk < K ? r[(long)(k0 + kk) * rld + base + (long)c * TILE] : mk<R>(0, 0);
-    for (int i0 = 0; i0 < Nv; i0 += 4) {
+    for (int i0 = 0; i0 < Nv; i0 += II) {
       R acc[NVAL];
 #pragma unroll
       for (int v = 0; v < NVAL; ++v) acc[v] = R(0);
 #pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
+      for (int ii = 0; ii < II; ++ii) {
         const int i = i0 + ii;
         if (i < Nv && live) {
           cx<R> q[12];
@@ -777,7 +784,7 @@ __global__ void __launch_bounds__(256) k_restrict_fine_m(Geom g, int Nv, const c
       const R tot = wave_transpose_sum<NVAL>(acc, lane);
       if (lane < NVAL) red[wv][lane] = tot;
       __syncthreads();
-      if (s < NVAL) {
+      if (s < NV0) {
         R sum = R(0);
         for (int w = 0; w < nw; ++w) sum += red[w][s];
         const int p = s & 1, h = (s >> 1) & 1, kk = (s >> 2) % KC, ii = (s >> 2) / KC;
@@ -793,11 +800,13 @@ void launch_restrict_fine_m(const Geom& g, int Nv, const cx<R>* Q, long vstride,
                             const int* f2c, cx<R>* rc, long cld, hipStream_t st) {
   const dim3 grid(g.nblocks), blk(((g.bs + 63) / 64) * 64);
   if (K == 1)
-    hipLaunchKernelGGL((k_restrict_fine_m<R, 1>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
+    hipLaunchKernelGGL((k_restrict_fine_m<R, 1, 4>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
   else if (K == 2 || sizeof(R) == 8)
-    hipLaunchKernelGGL((k_restrict_fine_m<R, 2>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
+    hipLaunchKernelGGL((k_restrict_fine_m<R, 2, 4>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
+  else if (K == 5 || K == 6)
+    hipLaunchKernelGGL((k_restrict_fine_m<R, 6, 1>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
   else
-    hipLaunchKernelGGL((k_restrict_fine_m<R, 4>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
+    hipLaunchKernelGGL((k_restrict_fine_m<R, 4, 4>), grid, blk, 0, st, g, Nv, Q, vstride, r, rld, K, f2c, rc, cld);
 }
 template void launch_restrict_fine_m<double>(const Geom&, int, const cx<double>*, long, const cx<double>*, long, int,
                                              const int*, cx<double>*, long, hipStream_t);
@@ -852,6 +861,8 @@ void launch_prolong_fine_m(const Geom& g, int Nv, const cx<R>* Q, long vstride, 
     hipLaunchKernelGGL((k_prolong_fine_m<R, 1>), grid, blk, 0, st, g, Nv, Q, vstride, ec, cld, K, f2c, x, xld, accumulate);
   else if (K == 2 || sizeof(R) == 8)
     hipLaunchKernelGGL((k_prolong_fine_m<R, 2>), grid, blk, 0, st, g, Nv, Q, vstride, ec, cld, K, f2c, x, xld, accumulate);
+  else if (K == 5 || K == 6)
+    hipLaunchKernelGGL((k_prolong_fine_m<R, 6>), grid, blk, 0, st, g, Nv, Q, vstride, ec, cld, K, f2c, x, xld, accumulate);
   else
     hipLaunchKernelGGL((k_prolong_fine_m<R, 4>), grid, blk, 0, st, g, Nv, Q, vstride, ec, cld, K, f2c, x, xld, accumulate);
 }

@@ -1631,6 +1631,27 @@ struct MG : MGBase {
     launch_copy_cvt<R, double>(setup_out(l), b.as<cx<double>>(), len, c.st);
     download_level(l, b.as<cx<double>>(), out);
   }
+  // fine-level restriction (dir 0) or prolongation (dir 1) of K columns with
+  // the K-column kernels of the lock-step cycle
+  void transfer_multi_host(int dir, int K, const cx<double>* in, cx<double>* out) override {
+    const long len = c.fine_len(), lenc = level_len(1);
+    const long lin = dir == 0 ? len : lenc, lout = dir == 0 ? lenc : len;
+    DevBuf a, b, ar, br;
+    a.alloc(sizeof(cx<double>) * lin * K, true);
+    b.alloc(sizeof(cx<double>) * lout * K, true);
+    ar.alloc(sizeof(cx<R>) * lin * K, true);
+    br.alloc(sizeof(cx<R>) * lout * K, true);
+    for (int k = 0; k < K; ++k) upload_level(dir, in + k * lin, 0, a.as<cx<double>>() + k * lin);
+    launch_copy_cvt<double, R>(a.as<cx<double>>(), ar.as<cx<R>>(), lin * K, c.st);
+    if (dir == 0)
+      launch_restrict_fine_m<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), len, ar.as<cx<R>>(), len, K,
+                                f2c.template as<int>(), br.as<cx<R>>(), lenc, c.st);
+    else
+      launch_prolong_fine_m<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), len, ar.as<cx<R>>(), lenc, K,
+                               f2c.template as<int>(), br.as<cx<R>>(), len, 0, c.st);
+    launch_copy_cvt<R, double>(br.as<cx<R>>(), b.as<cx<double>>(), lout * K, c.st);
+    for (int k = 0; k < K; ++k) download_level(1 - dir, b.as<cx<double>>() + k * lout, out + k * lout);
+  }
   void get_coarse_op(int l, cx<double>* S_, cx<double>* F_) override {
     CoarseGeo& G = *geos[l];
     size_t nn = (size_t)G.n * G.n;

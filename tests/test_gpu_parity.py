@@ -139,6 +139,29 @@ def _two_level(dd, dims, block, nv, delta=1.0, mu=MU, **kw):
     return ctx, op, h, V
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 6, 8])
+def test_transfers_k_columns(dd, prec, tol, K):
+    """The K-column fine restriction and prolongation of the lock-step cycle
+    (column groups of 1, 2, 4 and 6, one or two passes over P) against the
+    oracle's P^dag and P with its own test vectors, column by column,
+    relative and element-wise."""
+    dims, block, nv = (8, 8, 8, 16), (4, 4, 4, 4), 20
+    ctx, op, h, V = _two_level(dd, dims, block, nv, delta=5.0, precision=prec)
+    Q = h.levels[0].Q
+    rs = np.stack([synth.gaussian(dims + (12,), 40 + k) for k in range(K)])
+    got = ctx.restrict_multi(rs.reshape((K,) + dims + (4, 3)))
+    es = np.stack([synth.gaussian(got.shape[1:], 60 + k) for k in range(K)])
+    xs = ctx.prolong_multi(es).reshape((K,) + dims + (12,))
+    for k in range(K):
+        want = agg.restrict(Q, rs[k], block)
+        assert rel(got[k], want) < tol
+        assert np.abs(got[k] - want).max() < tol * np.abs(want).max()
+        want = agg.prolong(Q, es[k], block)
+        assert rel(xs[k], want) < tol
+        assert np.abs(xs[k] - want).max() < tol * np.abs(want).max()
+
+
 @pytest.mark.parametrize("dims,block,nv", [((4, 4, 4, 4), (2, 2, 2, 2), 8), ((8, 8, 8, 16), (4, 4, 4, 4), 20),
                                           ((8, 4, 8, 8), (4, 2, 4, 2), 12)])
 def test_interpolation_transfer_and_coarse_operator(dd, dims, block, nv):
