@@ -400,6 +400,7 @@ def main():
     d_fields = int(round((bytes_launch / V - 1152) / 384)) if n_d else 0
     achieved = bytes_d / (ms_d * 1e-3) / 1e9 if n_d else None
     src_hash = dirac_sources_sha256()
+    d_traffic = traffic_for(src_hash, d_fields)
     # fine SAP colour sweeps inside the timed steps: every launch sweeps the
     # blocks of one colour for K fields (K = the setup's batch or the rhs
     # group); the library adds up each launch's algorithmic bytes
@@ -509,8 +510,10 @@ def main():
                                                f"lock-step group per launch",
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": traffic_for(src_hash, d_fields), "algorithmic_bytes_per_launch": bytes_launch,
-                     "fields_per_launch": d_fields, "launches": n_d, "avg_launch_ms": round(avg_ms, 4)},
+                     "traffic": d_traffic, "algorithmic_bytes_per_launch": bytes_launch,
+                     "traffic_gbs": round(d_traffic / (avg_ms * 1e-3) / 1e9, 1) if d_traffic and n_d else None,
+                     "fields_per_launch": d_fields, "launches": n_d, "avg_launch_ms": round(avg_ms, 4),
+                     "ms_per_field": round(avg_ms / max(d_fields, 1), 4)},
         "roofline_sap": sap,
         "cpu_baseline": cpu,
         "oracle_check": check,
