@@ -492,7 +492,11 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
   const int m = ws.m, ldh = m + 1;
   const long ld = ws.ld, hcs = (long)ldh * m;
   const int nwg = (int)std::min<long>(ws.nwg, std::max<long>(1, (N + 255) / 256));
-  const int nwgf = std::min(ws.nwgf, cgs_nwg<R>(N));  // fused Arnoldi launches
+  // fused Arnoldi launches: for FP32 vectors about 512 workgroups over all K
+  // columns (two per CU) fill the device; more only add per-workgroup
+  // partial sums to reduce
+  int nwgf = std::min(ws.nwgf, cgs_nwg<R>(N));
+  if (sizeof(R) == 4) nwgf = std::min(nwgf, std::max(32, (512 + K - 1) / K));
   const long pcs = (long)std::max(ws.nwg, ws.nwgf) * ldh;
   cx<R>* V = ws.V.template as<cx<R>>();
   cx<R>* Z = M ? ws.Z.template as<cx<R>>() : V;
