@@ -319,13 +319,13 @@ int ddamg_get_interpolation(ddamg_ctx* ctx, int level, void* Q);
 /* r_c = P^dag r from level l to l+1; x = P e_c from level l+1 to l. */
 int ddamg_restrict(ddamg_ctx* ctx, int level, const void* in, void* out);
 int ddamg_prolong(ddamg_ctx* ctx, int level, const void* in, void* out);
-/* The same two transfers between the fine level and level 1 for nrhs (1..16)
- * columns stored one after the other (host arrays, complex128), through the
- * K-column kernels of the lock-step cycle, which read P once per group of
- * columns (Sec. 1, aggregation-based interpolation).  BAD_STATE without a
- * setup; INVALID_ARG for NULL arrays or nrhs out of range. */
-int ddamg_restrict_multi(ddamg_ctx* ctx, int nrhs, const void* in, void* out);
-int ddamg_prolong_multi(ddamg_ctx* ctx, int nrhs, const void* in, void* out);
+/* The same two transfers between levels l and l+1 for nrhs (1..16) columns
+ * stored one after the other (host arrays, complex128), through the K-column
+ * kernels of the lock-step cycle, which read P once per group of columns
+ * (Sec. 1, aggregation-based interpolation).  BAD_STATE without a setup;
+ * INVALID_ARG for a bad level, NULL arrays or nrhs out of range. */
+int ddamg_restrict_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out);
+int ddamg_prolong_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out);
 /* coarse operator of level l >= 1 as blocks: S [Vl][n][n] (self, without
  * twist) and F [4][Vl][n][n] (forward T,Z,Y,X), row-major, FP64, host. */
 int ddamg_get_coarse_op(ddamg_ctx* ctx, int level, void* S, void* F);

@@ -848,23 +848,23 @@ int ddamg_prolong(ddamg_ctx* ctx, int level, const void* in, void* out) {
     return DDAMG_OK;
   });
 }
-int ddamg_restrict_multi(ddamg_ctx* ctx, int nrhs, const void* in, void* out) {
+int ddamg_restrict_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out) {
   if (!ctx) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {
     Ctx& c = ctx->c;
-    need_setup(c);
+    LEVEL_CHECK(0, 1);
     if (!in || !out || nrhs < 1 || nrhs > 16) throw Error(INVALID_ARG, "bad K-column restriction arguments");
-    c.mg->transfer_multi_host(0, nrhs, (const cx<double>*)in, (cx<double>*)out);
+    c.mg->transfer_multi_host(level, 0, nrhs, (const cx<double>*)in, (cx<double>*)out);
     return DDAMG_OK;
   });
 }
-int ddamg_prolong_multi(ddamg_ctx* ctx, int nrhs, const void* in, void* out) {
+int ddamg_prolong_multi(ddamg_ctx* ctx, int level, int nrhs, const void* in, void* out) {
   if (!ctx) return DDAMG_INVALID_ARG;
   return guard(ctx, [&]() {
     Ctx& c = ctx->c;
-    need_setup(c);
+    LEVEL_CHECK(0, 1);
     if (!in || !out || nrhs < 1 || nrhs > 16) throw Error(INVALID_ARG, "bad K-column prolongation arguments");
-    c.mg->transfer_multi_host(1, nrhs, (const cx<double>*)in, (cx<double>*)out);
+    c.mg->transfer_multi_host(level, 1, nrhs, (const cx<double>*)in, (cx<double>*)out);
     return DDAMG_OK;
   });
 }

@@ -243,6 +243,95 @@ void launch_restrict_coarse(int n, int Nv, int nagg, int asz, const int* agg_sit
   hipLaunchKernelGGL(k_restrict_coarse<R>, dim3(nagg), dim3(256), 0, st, n, Nv, asz, agg_sites, Q, qstride, r, rc);
 }
 
+// K columns (stride rld in, cld out): one workgroup per (aggregate, column),
+// the K columns of an aggregate in consecutive workgroups of one XCD, so its
+// part of Q comes from HBM once and from L2 for the other columns
+template <class R>
+__global__ void __launch_bounds__(256) k_restrict_coarse_m(int n, int Nv, int asz, const int* __restrict__ agg_sites,
+                                                           const cx<R>* __restrict__ Q, long qstride,
+                                                           const cx<R>* __restrict__ r, long rld,
+                                                           cx<R>* __restrict__ rc, long cld, int K) {
+  const int wq = xcd_remap(blockIdx.x, gridDim.x), A = wq / K, col = wq - A * K;
+  r += (long)col * rld;
+  rc += (long)col * cld;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tot = asz * n, hn = n >> 1;
+  for (int i0 = 8 * w; i0 < Nv; i0 += 32) {
+    double acc[32];  // [4 ii + 2 h + p]
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+#pragma unroll 2
+    for (int e = lane; e < tot; e += 64) {
+      const int j = e / n, k = e - j * n;
+      const long idx = (long)agg_sites[A * asz + j] * n + k;
+      const cx<R> rv = r[idx];
+      const bool up = k >= hn;
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) {
+        const int iv = i0 + ii < Nv ? i0 + ii : Nv - 1;  // clamped: every load in flight
+        const cx<R> qv = Q[(long)iv * qstride + idx];
+        const double re = (double)qv.re * rv.re + (double)qv.im * rv.im;
+        const double im = (double)qv.re * rv.im - (double)qv.im * rv.re;
+        acc[4 * ii + 0] += up ? 0.0 : re;
+        acc[4 * ii + 1] += up ? 0.0 : im;
+        acc[4 * ii + 2] += up ? re : 0.0;
+        acc[4 * ii + 3] += up ? im : 0.0;
+      }
+    }
+    const double v = wave_transpose_sum<32>(acc, lane);  // lane l: total of value l % 32
+    if (lane < 32) {
+      const int ii = lane >> 2, hh = (lane >> 1) & 1, p = lane & 1;
+      if (i0 + ii < Nv) reinterpret_cast<R*>(rc + (long)A * 2 * Nv + hh * Nv + i0 + ii)[p] = (R)v;
+    }
+  }
+}
+template <class R>
+void launch_restrict_coarse_m(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<R>* Q, long qstride,
+                              const cx<R>* r, long rld, cx<R>* rc, long cld, int K, hipStream_t st) {
+  hipLaunchKernelGGL(k_restrict_coarse_m<R>, dim3(nagg * K), dim3(256), 0, st, n, Nv, asz, agg_sites, Q, qstride, r,
+                     rld, rc, cld, K);
+}
+
+// K columns: one thread per entry for all columns, in groups of KC whose
+// accumulators stay in registers (Q read once per group)
+template <class R, int KC>
+__global__ void k_prolong_coarse_m(int n, int Nv, int nsites, const int* __restrict__ site_agg,
+                                   const cx<R>* __restrict__ Q, long qstride, const cx<R>* __restrict__ ec, long cld,
+                                   cx<R>* __restrict__ x, long xld, int K, int accumulate) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)nsites * n) return;
+  const int site = (int)(gid / n), k = (int)(gid - (long)site * n);
+  const int h = k >= (n >> 1) ? 1 : 0;
+  const cx<R>* e = ec + (long)site_agg[site] * 2 * Nv + h * Nv;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    cx<R> acc[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+      acc[kk] = accumulate && k0 + kk < K ? x[(long)(k0 + kk) * xld + gid] : mk<R>(0, 0);
+    for (int i = 0; i < Nv; ++i) {
+      const cx<R> q = Q[(long)i * qstride + gid];
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk)
+        if (k0 + kk < K) cmac(acc[kk], q, e[(long)(k0 + kk) * cld + i]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+      if (k0 + kk < K) x[(long)(k0 + kk) * xld + gid] = acc[kk];
+  }
+}
+template <class R>
+void launch_prolong_coarse_m(int n, int Nv, int nsites, const int* site_agg, const cx<R>* Q, long qstride,
+                             const cx<R>* ec, long cld, cx<R>* x, long xld, int K, int accumulate, hipStream_t st) {
+  const long tot = (long)nsites * n;
+  const dim3 grid((unsigned)((tot + 255) / 256)), blk(256);
+  if (K <= 4)
+    hipLaunchKernelGGL((k_prolong_coarse_m<R, 4>), grid, blk, 0, st, n, Nv, nsites, site_agg, Q, qstride, ec, cld, x,
+                       xld, K, accumulate);
+  else
+    hipLaunchKernelGGL((k_prolong_coarse_m<R, 8>), grid, blk, 0, st, n, Nv, nsites, site_agg, Q, qstride, ec, cld, x,
+                       xld, K, accumulate);
+}
+
 template <class R>
 __global__ void k_prolong_coarse(int n, int Nv, int nsites, const int* __restrict__ site_agg,
                                  const cx<R>* __restrict__ Q, long qstride, const cx<R>* __restrict__ ec,
@@ -686,6 +775,10 @@ INST_RS(float, bf16)
                                           cx<R>*, hipStream_t);                                                    \
   template void launch_prolong_coarse<R>(int, int, int, const int*, const cx<R>*, long, const cx<R>*, cx<R>*, int, \
                                          hipStream_t);                                                             \
+  template void launch_restrict_coarse_m<R>(int, int, int, int, const int*, const cx<R>*, long, const cx<R>*, long, \
+                                            cx<R>*, long, int, hipStream_t);                                       \
+  template void launch_prolong_coarse_m<R>(int, int, int, const int*, const cx<R>*, long, const cx<R>*, long, cx<R>*, \
+                                           long, int, int, hipStream_t);                                           \
   template void launch_qr_coarse<R, R>(int, int, int, int, const int*, const cx<R>*, long, cx<R>*, long, int*,   \
                                        hipStream_t);                                                               \
   template void launch_assemble_coarse<R>(const CGeom&, int, int, const int*, const int*, const cx<double>*,       \

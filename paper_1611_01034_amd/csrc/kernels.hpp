@@ -132,6 +132,13 @@ void launch_restrict_coarse(int n, int Nv, int nagg, int asz, const int* agg_sit
 template <class R>
 void launch_prolong_coarse(int n, int Nv, int nsites, const int* site_agg, const cx<R>* Q, long qstride,
                            const cx<R>* ec, cx<R>* x, int accumulate, hipStream_t st);
+// K columns at strides rld / cld (restriction) and cld / xld (prolongation)
+template <class R>
+void launch_restrict_coarse_m(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<R>* Q, long qstride,
+                              const cx<R>* r, long rld, cx<R>* rc, long cld, int K, hipStream_t st);
+template <class R>
+void launch_prolong_coarse_m(int n, int Nv, int nsites, const int* site_agg, const cx<R>* Q, long qstride,
+                             const cx<R>* ec, long cld, cx<R>* x, long xld, int K, int accumulate, hipStream_t st);
 template <class RI, class RO>
 void launch_qr_coarse(int n, int Nv, int nagg, int asz, const int* agg_sites, const cx<RI>* V, long vstride,
                       cx<RO>* Q, long qstride, int* fail, hipStream_t st);

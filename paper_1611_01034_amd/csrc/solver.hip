@@ -1112,6 +1112,19 @@ struct MG : MGBase {
                                 (long)G.nsites * G.n, in, out, c.st);
     }
   }
+  // K columns between coarse levels l >= 1 and l + 1 (strides ld, ldc)
+  void restrict_m(int l, const cx<R>* in, long ld, cx<R>* out, long ldc, int K) {
+    TimeScope ts(c.timer, 3);
+    CoarseGeo& G = *geos[l];
+    launch_restrict_coarse_m<R>(G.n, Nv[l], G.nagg, G.asz, G.agg_sites.template as<int>(), Q[l].template as<cx<R>>(),
+                                (long)G.nsites * G.n, in, ld, out, ldc, K, c.st);
+  }
+  void prolong_m(int l, const cx<R>* in, long ldc, cx<R>* out, long ld, int K) {
+    TimeScope ts(c.timer, 3);
+    CoarseGeo& G = *geos[l];
+    launch_prolong_coarse_m<R>(G.n, Nv[l], G.nsites, G.site_agg.template as<int>(), Q[l].template as<cx<R>>(),
+                               (long)G.nsites * G.n, in, ldc, out, ld, K, 0, c.st);
+  }
   void prolong_(int l, const cx<R>* in, cx<R>* out, int acc) {
     TimeScope ts(c.timer, 3);
     if (l == 0) {
@@ -1293,9 +1306,9 @@ struct MG : MGBase {
       }
       fine_sap_m(v, x, K, p.sap_post, p.mr_steps);
     } else {
-      for (int k = 0; k < K; ++k) restrict_(l, v + k * len, rc_ + k * lenc);
+      restrict_m(l, v, len, rc_, lenc, K);
       coarse_solve_m(l + 1, rc_, ec_, K);
-      for (int k = 0; k < K; ++k) prolong_(l, ec_ + k * lenc, x + k * len, 0);
+      prolong_m(l, ec_, lenc, x, len, K);
       coarse_sap_m(l, v, x, K, p.coarse_sap_post);
     }
   }
@@ -1635,26 +1648,30 @@ struct MG : MGBase {
     launch_copy_cvt<R, double>(setup_out(l), b.as<cx<double>>(), len, c.st);
     download_level(l, b.as<cx<double>>(), out);
   }
-  // fine-level restriction (dir 0) or prolongation (dir 1) of K columns with
-  // the K-column kernels of the lock-step cycle
-  void transfer_multi_host(int dir, int K, const cx<double>* in, cx<double>* out) override {
-    const long len = c.fine_len(), lenc = level_len(1);
+  // restriction (dir 0) or prolongation (dir 1) of K columns between levels l
+  // and l + 1 with the K-column kernels of the lock-step cycle
+  void transfer_multi_host(int l, int dir, int K, const cx<double>* in, cx<double>* out) override {
+    const long len = level_len(l), lenc = level_len(l + 1);
     const long lin = dir == 0 ? len : lenc, lout = dir == 0 ? lenc : len;
     DevBuf a, b, ar, br;
     a.alloc(sizeof(cx<double>) * lin * K, true);
     b.alloc(sizeof(cx<double>) * lout * K, true);
     ar.alloc(sizeof(cx<R>) * lin * K, true);
     br.alloc(sizeof(cx<R>) * lout * K, true);
-    for (int k = 0; k < K; ++k) upload_level(dir, in + k * lin, 0, a.as<cx<double>>() + k * lin);
+    for (int k = 0; k < K; ++k) upload_level(l + dir, in + k * lin, 0, a.as<cx<double>>() + k * lin);
     launch_copy_cvt<double, R>(a.as<cx<double>>(), ar.as<cx<R>>(), lin * K, c.st);
-    if (dir == 0)
+    if (l == 0 && dir == 0)
       launch_restrict_fine_m<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), len, ar.as<cx<R>>(), len, K,
                                 f2c.template as<int>(), br.as<cx<R>>(), lenc, c.st);
-    else
+    else if (l == 0)
       launch_prolong_fine_m<R>(c.g, Nv[0], Q[0].template as<cx<R>>(), len, ar.as<cx<R>>(), lenc, K,
                                f2c.template as<int>(), br.as<cx<R>>(), len, 0, c.st);
+    else if (dir == 0)
+      restrict_m(l, ar.as<cx<R>>(), len, br.as<cx<R>>(), lenc, K);
+    else
+      prolong_m(l, ar.as<cx<R>>(), lenc, br.as<cx<R>>(), len, K);
     launch_copy_cvt<R, double>(br.as<cx<R>>(), b.as<cx<double>>(), lout * K, c.st);
-    for (int k = 0; k < K; ++k) download_level(1 - dir, b.as<cx<double>>() + k * lout, out + k * lout);
+    for (int k = 0; k < K; ++k) download_level(l + 1 - dir, b.as<cx<double>>() + k * lout, out + k * lout);
   }
   void get_coarse_op(int l, cx<double>* S_, cx<double>* F_) override {
     CoarseGeo& G = *geos[l];

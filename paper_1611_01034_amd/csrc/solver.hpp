@@ -241,7 +241,7 @@ struct MGBase {
   virtual void get_interp(int l, cx<double>* host) = 0;
   virtual void restrict_host(int l, const cx<double>* in, cx<double>* out) = 0;
   virtual void prolong_host(int l, const cx<double>* in, cx<double>* out) = 0;
-  virtual void transfer_multi_host(int dir, int K, const cx<double>* in, cx<double>* out) = 0;
+  virtual void transfer_multi_host(int l, int dir, int K, const cx<double>* in, cx<double>* out) = 0;
   virtual void get_coarse_op(int l, cx<double>* S, cx<double>* F) = 0;
   virtual void apply_coarse_host(int l, const cx<double>* in, cx<double>* out) = 0;
   virtual void coarse_sap_host(int l, const cx<double>* b, cx<double>* x, int iters) = 0;

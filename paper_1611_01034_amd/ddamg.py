@@ -113,8 +113,8 @@ _SIGS = {
     "ddamg_get_interpolation": (_i, [_vp, _i, _vp]),
     "ddamg_restrict": (_i, [_vp, _i, _vp, _vp]),
     "ddamg_prolong": (_i, [_vp, _i, _vp, _vp]),
-    "ddamg_restrict_multi": (_i, [_vp, _i, _vp, _vp]),
-    "ddamg_prolong_multi": (_i, [_vp, _i, _vp, _vp]),
+    "ddamg_restrict_multi": (_i, [_vp, _i, _i, _vp, _vp]),
+    "ddamg_prolong_multi": (_i, [_vp, _i, _i, _vp, _vp]),
     "ddamg_get_coarse_op": (_i, [_vp, _i, _vp, _vp]),
     "ddamg_apply_coarse": (_i, [_vp, _i, _vp, _vp]),
     "ddamg_coarse_sap": (_i, [_vp, _i, _vp, _vp, _i]),
@@ -469,18 +469,18 @@ class DDAMG:
         self._check(_lib.ddamg_prolong(self._h, int(level), _ptr(e)[0], _ptr(out)[0]))
         return out
 
-    def restrict_multi(self, rs):
-        """P^dag of K fine fields [K, T, Z, Y, X, 4, 3] through the K-column kernel."""
+    def restrict_multi(self, level, rs):
+        """P^dag of K level-`level` fields [K, ...] through the K-column kernel."""
         rs = _c128(rs)
-        out = np.empty((rs.shape[0],) + self._level_shape(1), dtype=np.complex128)
-        self._check(_lib.ddamg_restrict_multi(self._h, int(rs.shape[0]), _ptr(rs)[0], _ptr(out)[0]))
+        out = np.empty((rs.shape[0],) + self._level_shape(level + 1), dtype=np.complex128)
+        self._check(_lib.ddamg_restrict_multi(self._h, int(level), int(rs.shape[0]), _ptr(rs)[0], _ptr(out)[0]))
         return out
 
-    def prolong_multi(self, es):
-        """P of K level-1 fields [K, ...] through the K-column kernel."""
+    def prolong_multi(self, level, es):
+        """P of K level-(level+1) fields [K, ...] through the K-column kernel."""
         es = _c128(es)
-        out = np.empty((es.shape[0],) + self._level_shape(0), dtype=np.complex128)
-        self._check(_lib.ddamg_prolong_multi(self._h, int(es.shape[0]), _ptr(es)[0], _ptr(out)[0]))
+        out = np.empty((es.shape[0],) + self._level_shape(level), dtype=np.complex128)
+        self._check(_lib.ddamg_prolong_multi(self._h, int(level), int(es.shape[0]), _ptr(es)[0], _ptr(out)[0]))
         return out
 
     def get_coarse_op(self, level):

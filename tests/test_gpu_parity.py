@@ -150,9 +150,9 @@ def test_transfers_k_columns(dd, prec, tol, K):
     ctx, op, h, V = _two_level(dd, dims, block, nv, delta=5.0, precision=prec)
     Q = h.levels[0].Q
     rs = np.stack([synth.gaussian(dims + (12,), 40 + k) for k in range(K)])
-    got = ctx.restrict_multi(rs.reshape((K,) + dims + (4, 3)))
+    got = ctx.restrict_multi(0, rs.reshape((K,) + dims + (4, 3)))
     es = np.stack([synth.gaussian(got.shape[1:], 60 + k) for k in range(K)])
-    xs = ctx.prolong_multi(es).reshape((K,) + dims + (12,))
+    xs = ctx.prolong_multi(0, es).reshape((K,) + dims + (12,))
     for k in range(K):
         want = agg.restrict(Q, rs[k], block)
         assert rel(got[k], want) < tol
@@ -481,6 +481,28 @@ def _three_level(dd, **kw):
                           coarse_sap_post=p.coarse_sap_post, coarse_mr_steps=p.coarse_mr_steps)
     h = mg.Hierarchy(op, op_params).set_test_vectors([V0, V1])
     return ctx, op, h
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("K", [1, 3, 6, 9])
+def test_coarse_transfers_k_columns(dd, prec, tol, K):
+    """Level 1 <-> level 2 restriction and prolongation of K columns in one
+    launch each (column groups of 4 and 8) against the oracle's P^dag and P of
+    level 1, column by column, relative and element-wise."""
+    ctx, op, h = _three_level(dd, precision=prec)
+    Q1, b1 = h.levels[1].Q, (2, 2, 2, 2)
+    shape1 = Q1.shape[1:]
+    rs = np.stack([synth.gaussian(shape1, 70 + k) for k in range(K)])
+    got = ctx.restrict_multi(1, rs)
+    es = np.stack([synth.gaussian(got.shape[1:], 80 + k) for k in range(K)])
+    xs = ctx.prolong_multi(1, es)
+    for k in range(K):
+        want = agg.restrict(Q1, rs[k], b1)
+        assert rel(got[k], want) < tol
+        assert np.abs(got[k] - want).max() < tol * np.abs(want).max()
+        want = agg.prolong(Q1, es[k], b1)
+        assert rel(xs[k], want) < tol
+        assert np.abs(xs[k] - want).max() < tol * np.abs(want).max()
 
 
 def test_three_level_operators(dd):
