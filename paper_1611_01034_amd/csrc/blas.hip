@@ -553,9 +553,8 @@ void launch_init_g_b(cx<double>* g, int ldh, const cx<double>* s, long scs, int 
 
 // ---------------------------------------------------------------------------
 // Classical Gram-Schmidt, norm and Givens step of K lock-step Arnoldi
-// processes: two Gram-Schmidt passes for FP64 vectors (four launches), one for
-// FP32 vectors (three launches; the FP32 inner solves stop at loose relative
-// tolerances, far above the orthogonality one pass keeps in FP32 arithmetic).
+// processes: two Gram-Schmidt passes (four launches) or one (three launches),
+// as cgs_two_pass decides from the vector type and the cycle length.
 // Grid (nwg, K), column r = blockIdx.y; inactive
 // columns return at once (the last launch zeroes their next basis vector).
 // Every workgroup stores per-workgroup partial sums; the next launch begins by
@@ -784,7 +783,7 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
                         cx<double>* sn, cx<double>* g, int j, double* resid, double* resid_host, int K, const int* act,
                         hipStream_t st) {
   const dim3 grid(nwg, K), blk(BS);
-  constexpr bool two_pass = cgs_two_pass<R>();
+  const bool two_pass = cgs_two_pass<R>(m);
   // the axpy kernels of 16 or more vectors hold twice the registers: half the
   // threads per workgroup (same workgroup count, so the partials match)
 #define CGS_LAUNCH(KM)                                                                                                 \
@@ -792,7 +791,7 @@ static void cgs_step_bs(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, lon
     constexpr int BA = (BS == 1024 && KM >= 16) ? 512 : BS;                                                            \
     hipLaunchKernelGGL((k_cgs_dot<R, KM, BS>), grid, blk, 0, st, V, ldv, csV, k, (const cx<R>*)w, csw, N, a, pcs,     \
                        act);                                                                                           \
-    if constexpr (two_pass) {                                                                                          \
+    if (two_pass) {                                                                                                    \
       hipLaunchKernelGGL((k_cgs_axpy_dot<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,               \
                          (const double*)a, b, pcs, hcol, hcs, act);                                                    \
       hipLaunchKernelGGL((k_cgs_axpy_norm<R, KM, BA>), grid, dim3(BA), 0, st, V, ldv, csV, k, w, csw, N,              \

@@ -239,10 +239,14 @@ void launch_zero_b(long N, cx<R>* x, long cs, int K, hipStream_t st);
 // memory, may be null) receives a copy of the K residual estimates
 template <class R>
 int cgs_block_size();
-// Gram-Schmidt passes of the Arnoldi step: two in FP64, one in FP32
+// Gram-Schmidt passes of the Arnoldi step of a cycle of m steps: two for
+// FP64 vectors in cycles longer than 8 steps, one otherwise.  One classical
+// pass loses orthogonality in proportion to the squared condition number of
+// the basis it orthogonalises against, which a short cycle keeps small; FP32
+// inner solves stop at loose tolerances, far above what one pass keeps.
 template <class R>
-constexpr bool cgs_two_pass() {
-  return sizeof(R) == 8;
+inline bool cgs_two_pass(int m) {
+  return sizeof(R) == 8 && m > 8;
 }
 template <class R>
 void launch_cgs_step(const cx<R>* V, long ldv, long csV, int k, cx<R>* w, long csw, long N, cx<double>* pa,

@@ -369,7 +369,7 @@ KrylovResult fgmres(Ctx& c, KrylovWS<R>& ws, long N, const std::function<void(co
       launch_multidot<R>(V, ld, j + 1, Vn, N, part, nwg, st);
       launch_reduce(part, j + 1, nwg, hcol, 0, st);
       launch_multi_axpy<R>(V, ld, j + 1, hcol, -1.0, Vn, N, st);
-      if (cgs_two_pass<R>()) {  // second classical Gram-Schmidt pass (FP64)
+      if (cgs_two_pass<R>(m)) {  // second classical Gram-Schmidt pass
         launch_multidot<R>(V, ld, j + 1, Vn, N, part, nwg, st);
         launch_reduce(part, j + 1, nwg, ws.y.template as<cx<double>>(), 0, st);
         launch_reduce(part, j + 1, nwg, hcol, 1, st);
@@ -591,8 +591,8 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
       A(z, Vn, K);
       cx<double>* hcol = H + (long)j * ldh;
       if (j + 1 <= 32) {
-        // classical Gram-Schmidt (two passes in FP64, one in FP32), norm, scaling
-        // and Givens step
+        // classical Gram-Schmidt (one or two passes, cgs_two_pass), norm,
+        // scaling and Givens step
         // the look-ahead estimate goes straight to its pinned slot (no copy launch)
         launch_cgs_step<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, part + (long)K * pcs, pcs, nwgf, hcol, hcs, H,
                            ldh, m, ws.cs.template as<double>(), ws.sn.template as<cx<double>>(), g, j,
@@ -602,7 +602,7 @@ KrylovResultM fgmres_multi(Ctx& c, KrylovWSm<R>& ws, int K, long N, const OpM<R>
         launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
         launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 0, K, act, st);
         launch_multi_axpy_b<R>(V, (long)K * ld, ld, j + 1, nullptr, hcol, hcs, -1.0, Vn, ld, N, K, act, st);
-        if (cgs_two_pass<R>()) {
+        if (cgs_two_pass<R>(m)) {
           launch_multidot_b<R>(V, (long)K * ld, ld, j + 1, Vn, ld, N, part, pcs, nwg, K, act, st);
           launch_reduce_b(part, pcs, j + 1, nwg, y, ldh, 0, K, act, st);
           launch_reduce_b(part, pcs, j + 1, nwg, hcol, hcs, 1, K, act, st);
