@@ -48,6 +48,7 @@ struct CGeom {
   int nsites;      // sites
   int neven;       // even sites (stored first)
   const int* nbr;  // [nsites][8]: +T +Z +Y +X -T -Z -Y -X
+  const int* lexord = nullptr;  // [nsites]: ordered index of the site at each lexicographic position
 };
 
 // ---------------------------------------------------------------- fine level

@@ -222,7 +222,7 @@ struct CoarseGeo {
   int nsblk = 0, ssz = 0, nsblk_col[2] = {0, 0};
   DevBuf sap_sites;  // [nsblk][ssz], colour-0 blocks first
   DevBuf sap_nbr;    // [nsblk][ssz][8]
-  CGeom cg() const { return CGeom{n, nsites, neven, nbr.as<int>()}; }
+  CGeom cg() const { return CGeom{n, nsites, neven, nbr.as<int>(), d_order.as<int>()}; }
 };
 
 struct MGBase {
