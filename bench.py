@@ -421,6 +421,23 @@ def main():
                "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_s,
                "launches": n_s, "avg_launch_ms": round(ms_s / n_s, 4)}
 
+    # the one-field D(mu) launch (ddamg_apply_dirac's form) on resident
+    # fields, after the timed steps and outside them: the D(mu) GB/s of a
+    # single application
+    ctx.timing(True)
+    ctx.bench_dirac(10, "fp64")
+    n_1, ms_1 = ctx.timing_query(0)
+    bytes_1 = ctx.timing_bytes(0)
+    ctx.timing(False)
+    one_field = None
+    if n_1 and ms_1 > 0:
+        a1 = bytes_1 / (ms_1 * 1e-3) / 1e9
+        t1 = traffic_for(src_hash, 1)
+        one_field = {"kernel": "D(mu) FP64 full-lattice apply, one field per launch (10 launches after the steps)",
+                     "achieved": round(a1, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(a1 / HBM_PEAK_GBS, 4), "traffic": t1,
+                     "algorithmic_bytes_per_launch": bytes_1 / n_1, "avg_launch_ms": round(ms_1 / n_1, 4)}
+
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -513,7 +530,7 @@ def main():
                      "traffic": d_traffic, "algorithmic_bytes_per_launch": bytes_launch,
                      "traffic_gbs": round(d_traffic / (avg_ms * 1e-3) / 1e9, 1) if d_traffic and n_d else None,
                      "fields_per_launch": d_fields, "launches": n_d, "avg_launch_ms": round(avg_ms, 4),
-                     "ms_per_field": round(avg_ms / max(d_fields, 1), 4)},
+                     "ms_per_field": round(avg_ms / max(d_fields, 1), 4), "one_field": one_field},
         "roofline_sap": sap,
         "cpu_baseline": cpu,
         "oracle_check": check,
