@@ -49,6 +49,7 @@ KAPPA, CSW, MU = 0.13729, 1.57551, 0.0009
 # algorithmic bytes per site of one FP64 D(mu) apply: spinor in + out (2 x 192),
 # links (4 x 9 complex), clover (two Hermitian 6x6 = 72 reals)
 DIRAC_FP64_BYTES_PER_SITE = 2 * 192 + 576 + 576
+SAP_POST = 2  # fine post-smoothing sweeps (k of Eq. (1)) of both forms
 
 
 def parse():
@@ -82,7 +83,7 @@ def parse():
     ap.add_argument("--time-budget", type=float, default=540.0,
                     help="seconds since start beyond which the FP64 leg is skipped")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
-                    help="override a solver parameter of the mixed form (ddamg_params field)")
+                    help="override a solver parameter (ddamg_params field) of both forms")
     return ap.parse_args()
 
 
@@ -298,10 +299,12 @@ def main():
             c.net_set_params(wts)
         return c
 
+    # two fine post-smoothing sweeps in both forms: on this synthetic field
+    # one, three and four sweeps all take more outer iterations
     def params(prec, setup_iters, rhs_batch, batch):
         return ddamg.default_params(levels=levels, block=[block, (2, 2, 2, 2)], nvec=nv, setup_iters=setup_iters,
                                     coarse_setup_iters=3, precision=prec, coarse_mu_factor=5.0, batch=batch,
-                                    rhs_batch=rhs_batch)
+                                    rhs_batch=rhs_batch, sap_post=SAP_POST)
 
     ctx = make_ctx(U, net=need_net)
     # the oracle leg takes its slices of the inputs now and runs on the host
@@ -465,6 +468,8 @@ def main():
                 f"fp64: setup level {level} " + ("initial phase done" if stage == 0 else f"iteration {i + 1} done")))
             # FP64 fine fields are twice the size: 4 test vectors per setup batch
             p64 = params("fp64", args.fp64_setup_iters, min(args.fp64_rhs_batch, args.nrhs), min(args.batch, 4))
+            for k, v in overrides.items():  # the same solver parameters in both forms
+                setattr(p64, k, v)
             torch.cuda.synchronize()
             t1 = time.time()
             c64.setup(p64, [V0, V1])
@@ -517,7 +522,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(str(d) for d in reversed(dims))} twisted-mass Wilson-clover, "
                                f"kappa {KAPPA}, c_sw {CSW}, mu {MU}, delta 5, 3 levels (4^4, 2^4 aggregates, "
-                               f"Nv 24/32), {args.nrhs} rhs ({kb} in lock step, outer restart {args.restart}), "
+                               f"Nv 24/32, {SAP_POST} fine post-smoothing SAP sweeps), {args.nrhs} rhs ({kb} in lock step, "
+                               f"outer restart {args.restart}), "
                                f"{'learned' if args.learned else 'random'} initial test vectors + "
                                f"{args.setup_iters} setup iteration(s) on batches of {args.batch} test vectors, "
                                f"preconditioner {args.precision}, outer FGMRES FP64, tol 1e-10"
