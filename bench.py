@@ -250,8 +250,8 @@ def traffic_for(kernel_src_hash, nfields):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of "
-              "this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on one GPU; "
+              "how the path would shard is described in the design notes", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
